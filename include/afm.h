@@ -1,0 +1,271 @@
+/*
+ * afm.h -- C ABI of the MI355X (gfx950) library for the strictly-local
+ * E(3)-equivariant edge potential trained as Allegro-FM (arXiv 2502.06073).
+ *
+ * The library computes, on one GPU, energies and their derivatives for
+ * atoms that interact only within a radial cutoff (the "strictly-local"
+ * architecture of the paper's Abstract; its hyperparameters are given in
+ * Methodology / Model Training and Table 1):
+ *
+ *   edges     every ordered pair (i, j, n) with |r_j - r_i + n.h| < r_list,
+ *             all periodic images n, canonical order (i, j, n0, n1, n2);
+ *   basis     n_b Bessel functions times a polynomial cutoff envelope of the
+ *             edge length; real spherical harmonics (l <= l_max) of its
+ *             direction;
+ *   network   two-body latent MLP -> per-layer linear environment embedding,
+ *             environment sum over the central atom's edges, channelwise
+ *             Clebsch-Gordan tensor products, latent MLP with residual ->
+ *             linear edge-energy MLP;
+ *   energies  E_i = sigma_Z * energy_scale * sum_{row i} eps_e + mu_Z,
+ *             E_s = sum_{i in s} E_i;
+ *   forces    F_i = -dE/dr_i = sum_{e in row i} (g_e - g_rev(e)) with
+ *             g_e = dE/d(delta_e); virial W_s = -sum_{e in s} g_e delta_e^T.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named in afm_system / afm_nlist and every per-atom or
+ *     per-structure output are DEVICE pointers owned by the caller.  The
+ *     library never frees them.  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued asynchronously on it; no entry point
+ *     allocates device memory or synchronises the stream except
+ *     afm_model_create / afm_model_destroy.
+ *   - Units: Angstrom, eV, amu, fs.  Cells are row-major [3][3] with the
+ *     lattice vectors a, b, c as rows; a structure is either periodic in all
+ *     three directions (pbc = 1) or open (pbc = 0).  Positions are used as
+ *     given (never wrapped by the evaluation calls).
+ *   - Return value: AFM_OK (0) or a negative afm_status.  Nothing throws
+ *     across the ABI.  afm_last_error() gives a message for the calling
+ *     thread.  Conditions found on the device (edge capacity overflow,
+ *     non-finite positions, species out of range, MD skin violation) are
+ *     OR-ed into the device word nlist->status; the caller reads it when it
+ *     synchronises.
+ */
+#ifndef AFM_H_
+#define AFM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef enum {
+  AFM_OK = 0,
+  AFM_E_INVALID = -1,     /* null pointer, bad size or hyperparameter       */
+  AFM_E_CAPACITY = -2,    /* a caller buffer is too small                   */
+  AFM_E_NONFINITE = -3,   /* non-finite input found on the host             */
+  AFM_E_UNSUPPORTED = -4, /* precision or shape not built into this library */
+  AFM_E_HIP = -5,         /* HIP runtime error (see afm_last_error)         */
+  AFM_E_WEIGHTS = -6      /* weight vector length does not match layout     */
+} afm_status;
+
+/* bits of the device status word nlist->status */
+#define AFM_FLAG_CAPACITY 1   /* edges exceeded nlist->capacity; n_edges holds the need */
+#define AFM_FLAG_NONFINITE 2  /* a position was not finite                               */
+#define AFM_FLAG_SPECIES 4    /* a species index was outside [0, n_species)              */
+#define AFM_FLAG_SKIN 8       /* an atom moved more than skin/2 since the last rebuild    */
+#define AFM_FLAG_IMAGES 16    /* a periodic image index did not fit in int8               */
+
+typedef enum {
+  AFM_FP64_REF = 0,    /* not built: the FP64 reference is the CPU oracle     */
+  AFM_FP32_PLAIN = 1,  /* every step in FP32 on the vector ALUs               */
+  AFM_BF16_MFMA = 2    /* MLP GEMMs on BF16 MFMA with FP32 accumulation       */
+} afm_precision;
+
+/* ---- hyperparameters (host struct) --------------------------------------
+ * Methodology / Model Training and Table 1: tensor features `channels` with
+ * l <= l_max in full O(3); two-body latent MLP widths twobody[0..n_twobody-1]
+ * (the last equals `latent`); latent MLPs of depth latent_depth and width
+ * `latent`; SiLU nonlinearities; edge-energy MLP latent -> edge_hidden -> 1
+ * without nonlinearity; radial cutoff r_cut.  n_bessel radial functions with
+ * a polynomial envelope of power poly_p; avg_num_neighbors normalises the
+ * environment sum by its inverse square root. */
+typedef struct {
+  int32_t n_species;
+  int32_t l_max;          /* 0, 1 or 2 */
+  int32_t n_layers;       /* >= 1 */
+  int32_t latent;         /* latent width w (multiple of 16) */
+  int32_t channels;       /* tensor channels c (multiple of 8, <= 256) */
+  int32_t n_bessel;       /* <= 16 */
+  int32_t poly_p;         /* envelope power p >= 2 */
+  int32_t n_twobody;      /* 1..4 */
+  int32_t twobody[4];
+  int32_t latent_depth;   /* 1..4 */
+  int32_t edge_hidden;
+  double r_cut;
+  double avg_num_neighbors;
+  double energy_scale;
+} afm_hparams;
+
+/* ---- weight layout ------------------------------------------------------
+ * The weights are one flat float64 vector made of these blocks in order
+ * (matrices row-major, out x in):
+ *   twobody.k           [twobody[k], k ? twobody[k-1] : 2 S + n_bessel]
+ *   layerL.env          [channels * (l_max + 1), latent]   (row n*(l_max+1)+l)
+ *   layerL.latent.k     [latent, k ? latent : latent + n0e_L * channels]
+ *   layerL.alpha        [n_paths_L, channels]      (only for L < n_layers)
+ *   edge.0              [edge_hidden, latent]
+ *   edge.1              [1, edge_hidden]
+ *   species.scale       [S]       species.shift [S]
+ * with n0e_L the number of tensor-product paths of layer L ending in a 0e
+ * scalar.  `init` says how the seeded generator fills a block:
+ *   0 = N(0, 1/fan_in), 1 = N(0, 1), 2 = ones. */
+typedef struct {
+  char name[32];
+  int64_t offset;
+  int64_t rows, cols;     /* cols = 1 for vectors */
+  int64_t fan_in;
+  int32_t init;
+} afm_param_block;
+
+/* Number of blocks and total parameter count for `hp`. */
+int afm_param_layout_size(const afm_hparams* hp /*host*/, int64_t* n_blocks /*host*/,
+                          int64_t* n_params /*host*/);
+/* Block `k` (0-based) of the layout. */
+int afm_param_layout_block(const afm_hparams* hp /*host*/, int64_t k,
+                           afm_param_block* out /*host*/);
+
+/* Real Clebsch-Gordan tensor C^{l1 l2 l3}[m1][m2][m3] as used by the
+ * library (real spherical harmonics without Condon-Shortley phase, order
+ * m = -l..l, l = 1 as (y, z, x); sum C^2 = 2 l3 + 1; first nonzero entry in
+ * row-major order positive).  out: host, (2l1+1)(2l2+1)(2l3+1) doubles. */
+int afm_cg_real(int32_t l1, int32_t l2, int32_t l3, double* out /*host*/);
+
+/* ---- model --------------------------------------------------------------- */
+typedef struct afm_model afm_model;
+
+/* Copy `weights` (host, float64, afm_param_layout_size values) to the
+ * device in the layouts the kernels of `precision` read.  Allocates device
+ * memory owned by the model (freed by afm_model_destroy).  Synchronous. */
+int afm_model_create(const afm_hparams* hp /*host*/, const double* weights /*host*/,
+                     int64_t n_weights, afm_precision precision, afm_model** out /*host*/);
+int afm_model_destroy(afm_model* model);
+
+/* ---- systems, neighbour lists, workspaces --------------------------------- */
+typedef struct {
+  int64_t n_atoms;
+  int64_t n_struct;
+  const double* pos;       /* [n_atoms, 3] */
+  const int32_t* species;  /* [n_atoms] */
+  const double* cell;      /* [n_struct, 3, 3] */
+  const uint8_t* pbc;      /* [n_struct] */
+  const int64_t* seg;      /* [n_struct + 1] atom offsets, seg[0] = 0 */
+} afm_system;
+
+/* CSR edge list in canonical order.  row_ptr[i]..row_ptr[i+1] are the edges
+ * of central atom i; col = neighbour atom j; shift = image n (int8 x 3);
+ * rev = index of (j, i, -n).  n_edges and status are single device words. */
+typedef struct {
+  int64_t capacity;        /* edges the col/shift/rev arrays can hold */
+  int64_t* row_ptr;        /* [n_atoms + 1] */
+  int32_t* col;            /* [capacity] */
+  int8_t* shift;           /* [capacity, 3] */
+  int32_t* rev;            /* [capacity] */
+  int64_t* n_edges;        /* [1] */
+  int32_t* status;         /* [1] AFM_FLAG_* bits, OR-ed, never cleared by the library */
+} afm_nlist;
+
+/* Device scratch memory for one (model, system size, edge capacity).
+ * Filled by afm_workspace_plan; the caller allocates `bytes` bytes of device
+ * memory (256-byte aligned) and stores the pointer in `ptr`.  Edges are
+ * processed in chunks of whole rows of at most chunk_edges + max_row edges;
+ * chunk_edges is chosen so the plan fits in max_bytes (0 = no limit).  A
+ * row longer than max_row sets AFM_FLAG_CAPACITY. */
+typedef struct {
+  void* ptr;
+  int64_t bytes;
+  int64_t n_atoms;
+  int64_t n_struct;
+  int64_t edge_capacity;
+  int64_t chunk_edges;
+  int64_t n_chunks;
+  int64_t max_row;
+  int32_t precision;
+  int32_t with_second_order;  /* plan holds the double-backward state */
+} afm_workspace;
+
+int afm_workspace_plan(const afm_model* model, int64_t n_atoms, int64_t n_struct,
+                       int64_t edge_capacity, int64_t max_bytes, int32_t with_second_order,
+                       afm_workspace* ws /*host, out*/);
+
+/* Abstract ("strictly-local") and Model Training (radial cutoff): build the
+ * canonical edge list of every structure at cutoff r_list (>= the model
+ * cutoff; the surplus is an MD skin).  The inclusion test is evaluated in
+ * float64 exactly as d2 = (dx*dx + dy*dy) + dz*dz < r_list*r_list with
+ * delta = (r_j - r_i) + ((n0*a + n1*b) + n2*c), no fused multiply-add.
+ * Periodic structures enumerate every image with |n_k| <= ceil(r / w_k)
+ * (w_k the perpendicular widths).  Uses the workspace's scratch area.  If
+ * the edges do not fit, *n_edges holds the required count, AFM_FLAG_CAPACITY
+ * is set and col/shift/rev are left unspecified. */
+int afm_build_neighbors(const afm_system* sys, double r_list, afm_nlist* nl,
+                        const afm_workspace* ws, void* stream);
+
+/* Model Training: per-atom energies e_atom[n_atoms] (float64) and
+ * per-structure energies e_struct[n_struct] (float64).  Leaves in `ws` the
+ * state afm_backward_forces needs (the same sys/nl/ws must follow). */
+int afm_forward_energy(const afm_model* model, const afm_system* sys, const afm_nlist* nl,
+                       double* e_atom, double* e_struct, const afm_workspace* ws, void* stream);
+
+/* Forces and virial as derivatives of the energy (they are the force and
+ * stress terms of the training loss, Model Training): given the upstream
+ * weights grad_e_struct[n_struct] (NULL = all ones) computes
+ * forces[n_atoms,3] = -d(sum_s gE_s E_s)/dr and virial[n_struct,3,3]
+ * (either may be NULL).  Accumulation in float64, deterministic (no atomics).
+ * Must follow afm_forward_energy with the same arguments on the same stream. */
+int afm_backward_forces(const afm_model* model, const afm_system* sys, const afm_nlist* nl,
+                        const double* grad_e_struct, double* forces, double* virial,
+                        const afm_workspace* ws, void* stream);
+
+/* Energies, forces and virial in one pass (forward and adjoint per chunk). */
+int afm_energy_forces(const afm_model* model, const afm_system* sys, const afm_nlist* nl,
+                      double* e_atom, double* e_struct, double* forces, double* virial,
+                      const afm_workspace* ws, void* stream);
+
+/* Weight gradients for force matching (Model Training: the loss combines
+ * energy and force errors): given upstream grad_e_struct[n_struct] and
+ * grad_forces[n_atoms,3] (device, float64), writes
+ *   grad_weights[n_params] = d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i]
+ * (device, float32, in the flat weight layout, overwritten).  Needs a
+ * workspace planned with with_second_order = 1.  grad_pos must be NULL. */
+int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
+                                 const afm_nlist* nl, const double* grad_e_struct,
+                                 const double* grad_forces, float* grad_weights,
+                                 double* grad_pos, const afm_workspace* ws, void* stream);
+
+/* ---- molecular dynamics ---------------------------------------------------
+ * Methodology (MD simulations, 0.5 fs time step): velocity Verlet in
+ * float64 with a = F / m * 9.648533212e-3 A fs^-2 per (eV A^-1 amu^-1).  The
+ * neighbour list (cutoff r_cut + skin) is rebuilt, after wrapping periodic
+ * atoms by whole lattice shifts, before the force evaluation of every step
+ * k with k % rebuild_every == 0 (k counts from state->step).  Each step
+ * writes (kinetic, potential) energies to energy_log[2 * t] (device,
+ * float64, n_steps pairs).  Forces of the current positions must be in
+ * state->forces on entry (afm_energy_forces) and are updated. */
+typedef struct {
+  double* pos;                   /* [n_atoms, 3] device, updated */
+  double* vel;                   /* [n_atoms, 3] device, updated */
+  double* forces;                /* [n_atoms, 3] device, updated */
+  const double* mass_by_species; /* [n_species] device */
+  double dt_fs;
+  double skin;
+  int32_t rebuild_every;
+  int64_t step;                  /* host, advanced by n_steps */
+  double* energy_log;            /* [n_steps, 2] device */
+  double* e_atom;                /* [n_atoms] device scratch */
+  double* e_struct;              /* [n_struct] device scratch */
+} afm_md_state;
+
+int afm_md_step(const afm_model* model, const afm_system* sys, afm_nlist* nl,
+                afm_md_state* state, int32_t n_steps, const afm_workspace* ws, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char* afm_strerror(int code);
+const char* afm_last_error(void);
+/* Library version string. */
+const char* afm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFM_H_ */
