@@ -171,7 +171,8 @@ typedef struct {
  * memory (256-byte aligned) and stores the pointer in `ptr`.  Edges are
  * processed in chunks of whole rows of at most chunk_edges + max_row edges;
  * chunk_edges is chosen so the plan fits in max_bytes (0 = no limit).  A
- * row longer than max_row sets AFM_FLAG_CAPACITY. */
+ * row longer than max_row sets AFM_FLAG_CAPACITY.  With model == NULL the plan
+ * holds only the scratch of afm_build_neighbors. */
 typedef struct {
   void* ptr;
   int64_t bytes;

@@ -1,0 +1,302 @@
+"""MI355X (gfx950) library for the strictly-local equivariant edge potential
+of Allegro-FM (arXiv 2502.06073): Python binding of the C ABI.
+
+Every step of the computation runs in the HIP kernels of ``libafm.so``;
+this module only marshals arguments.  PyTorch provides device memory and the
+current HIP stream.  There is no CPU fallback: without the built library or
+a GPU the calls raise.
+
+    import paper_2502_06073_amd as afm
+    model = afm.Model(hparams, weights, precision="bf16")
+    sysd = afm.DeviceSystem.from_arrays(pos, species, cell, pbc, seg)
+    calc = afm.Calculator(model, sysd, r_list=hparams["r_cut"])
+    out = calc.energy_forces()        # e_atom, e_struct, forces, virial
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import AfmError, check, load
+
+__all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
+           "param_layout", "cg_real", "hparams_struct", "energy_and_forces", "AfmError"]
+
+
+def _stream_ptr(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def hparams_struct(hp: Dict) -> _abi.Hparams:
+    tb = list(hp["twobody"])
+    h = _abi.Hparams()
+    h.n_species = int(hp["n_species"])
+    h.l_max = int(hp["l_max"])
+    h.n_layers = int(hp["n_layers"])
+    h.latent = int(hp["latent"])
+    h.channels = int(hp["channels"])
+    h.n_bessel = int(hp["n_bessel"])
+    h.poly_p = int(hp["poly_p"])
+    h.n_twobody = len(tb)
+    for k in range(4):
+        h.twobody[k] = int(tb[k]) if k < len(tb) else 0
+    h.latent_depth = int(hp["latent_depth"])
+    h.edge_hidden = int(hp["edge_hidden"])
+    h.r_cut = float(hp["r_cut"])
+    h.avg_num_neighbors = float(hp.get("avg_num_neighbors", 1.0))
+    h.energy_scale = float(hp.get("energy_scale", 1.0))
+    return h
+
+
+def param_layout(hp: Dict) -> List[Dict]:
+    """The library's flat weight layout (block name, offset, shape, fan-in, init)."""
+    lib = load()
+    h = hparams_struct(hp)
+    nb, npar = C.c_int64(), C.c_int64()
+    check("afm_param_layout_size", lib.afm_param_layout_size(C.byref(h), C.byref(nb), C.byref(npar)))
+    out = []
+    for k in range(nb.value):
+        b = _abi.ParamBlock()
+        check("afm_param_layout_block", lib.afm_param_layout_block(C.byref(h), k, C.byref(b)))
+        init = {0: "fan_in", 1: "normal", 2: "ones"}[b.init]
+        shape = (b.rows,) if b.name.decode().startswith("species.") else (b.rows, b.cols)
+        out.append(dict(name=b.name.decode(), offset=b.offset, shape=shape,
+                        size=b.rows * b.cols, fan_in=b.fan_in, init=init))
+    return out
+
+
+def cg_real(l1: int, l2: int, l3: int) -> np.ndarray:
+    lib = load()
+    out = np.zeros((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1))
+    check("afm_cg_real", lib.afm_cg_real(l1, l2, l3, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out.reshape(2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1)
+
+
+class Model:
+    """Device copy of a weight vector for one precision ("fp32" or "bf16")."""
+
+    def __init__(self, hp: Dict, weights: np.ndarray, precision: str = "bf16", device: int = 0):
+        lib = load()
+        self.hp = dict(hp)
+        self.precision = precision
+        self.device = torch.device("cuda", device)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        h = hparams_struct(hp)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check("afm_model_create",
+                  lib.afm_model_create(C.byref(h), w.ctypes.data_as(C.POINTER(C.c_double)), w.shape[0],
+                                       _abi.PRECISION[precision], C.byref(handle)))
+        self.handle = handle
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            with torch.cuda.device(self.device):
+                load().afm_model_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceSystem:
+    """Device tensors of a batch of structures (see afm_system)."""
+
+    def __init__(self, pos, species, cell, pbc, seg):
+        self.pos, self.species, self.cell, self.pbc, self.seg = pos, species, cell, pbc, seg
+
+    @staticmethod
+    def from_arrays(pos, species, cell, pbc, seg, device="cuda:0") -> "DeviceSystem":
+        dev = torch.device(device)
+        return DeviceSystem(
+            torch.as_tensor(np.ascontiguousarray(pos, np.float64), device=dev),
+            torch.as_tensor(np.ascontiguousarray(species, np.int32), device=dev),
+            torch.as_tensor(np.ascontiguousarray(np.asarray(cell, np.float64).reshape(-1, 3, 3)), device=dev),
+            torch.as_tensor(np.ascontiguousarray(pbc, np.uint8), device=dev),
+            torch.as_tensor(np.ascontiguousarray(seg, np.int64), device=dev))
+
+    @staticmethod
+    def from_synth(s, device="cuda:0") -> "DeviceSystem":
+        return DeviceSystem.from_arrays(s.pos, s.species, s.cell, s.pbc, s.seg, device)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_struct(self) -> int:
+        return int(self.seg.shape[0] - 1)
+
+    def struct(self, pos: Optional[torch.Tensor] = None) -> _abi.System:
+        s = _abi.System()
+        s.n_atoms = self.n_atoms
+        s.n_struct = self.n_struct
+        s.pos = _ptr(self.pos if pos is None else pos)
+        s.species = _ptr(self.species)
+        s.cell = _ptr(self.cell)
+        s.pbc = _ptr(self.pbc)
+        s.seg = _ptr(self.seg)
+        return s
+
+
+class NeighborList:
+    """Device CSR edge list with a fixed edge capacity."""
+
+    def __init__(self, n_atoms: int, capacity: int, device):
+        self.capacity = int(capacity)
+        self.row_ptr = torch.zeros(n_atoms + 1, dtype=torch.int64, device=device)
+        self.col = torch.zeros(max(1, capacity), dtype=torch.int32, device=device)
+        self.shift = torch.zeros(max(1, capacity) * 3, dtype=torch.int8, device=device)
+        self.rev = torch.zeros(max(1, capacity), dtype=torch.int32, device=device)
+        self.n_edges = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def struct(self) -> _abi.Nlist:
+        n = _abi.Nlist()
+        n.capacity = self.capacity
+        n.row_ptr = _ptr(self.row_ptr)
+        n.col = _ptr(self.col)
+        n.shift = _ptr(self.shift)
+        n.rev = _ptr(self.rev)
+        n.n_edges = _ptr(self.n_edges)
+        n.status = _ptr(self.status)
+        return n
+
+
+class Workspace:
+    """Planned and allocated device scratch (afm_workspace_plan)."""
+
+    def __init__(self, model: Optional[Model], n_atoms: int, n_struct: int, capacity: int,
+                 max_bytes: int = 0, second_order: bool = False, device=None):
+        lib = load()
+        w = _abi.Workspace()
+        check("afm_workspace_plan",
+              lib.afm_workspace_plan(model.handle if model else None, n_atoms, n_struct, capacity,
+                                     max_bytes, int(second_order), C.byref(w)))
+        dev = model.device if model else device
+        self.buf = torch.empty(int(w.bytes) + 256, dtype=torch.uint8, device=dev)
+        base = self.buf.data_ptr()
+        w.ptr = (base + 255) & ~255
+        self.ws = w
+
+    @property
+    def n_chunks(self) -> int:
+        return int(self.ws.n_chunks)
+
+
+class Calculator:
+    """Binds a model, a device system, a neighbour list and a workspace."""
+
+    def __init__(self, model: Model, sysd: DeviceSystem, r_list: Optional[float] = None,
+                 capacity: Optional[int] = None, max_bytes: int = 0, second_order: bool = False):
+        self.model = model
+        self.sysd = sysd
+        self.r_list = float(model.hp["r_cut"] if r_list is None else r_list)
+        dev = model.device
+        N, B = sysd.n_atoms, sysd.n_struct
+        if capacity is None:
+            capacity = self._estimate_capacity()
+        self.nl = NeighborList(N, capacity, dev)
+        self.ws = Workspace(model, N, B, capacity, max_bytes, second_order)
+        self.lib = load()
+
+    def _estimate_capacity(self) -> int:
+        # one build with a probe list to learn the edge count (host sync)
+        N, B = self.sysd.n_atoms, self.sysd.n_struct
+        probe = NeighborList(N, 0, self.model.device)
+        ws = Workspace(None, N, B, 0, device=self.model.device)
+        with torch.cuda.device(self.model.device):
+            check("afm_build_neighbors",
+                  load().afm_build_neighbors(C.byref(self.sysd.struct()), self.r_list,
+                                             C.byref(probe.struct()), C.byref(ws.ws),
+                                             _stream_ptr(self.model.device)))
+            n = int(probe.n_edges.item())
+        return max(16, int(n * 1.1) + 64)
+
+    def build_neighbors(self, pos: Optional[torch.Tensor] = None):
+        with torch.cuda.device(self.model.device):
+            check("afm_build_neighbors",
+                  self.lib.afm_build_neighbors(C.byref(self.sysd.struct(pos)), self.r_list,
+                                               C.byref(self.nl.struct()), C.byref(self.ws.ws),
+                                               _stream_ptr(self.model.device)))
+
+    def status(self) -> int:
+        return int(self.nl.status.item())
+
+    def _outs(self, forces: bool):
+        dev = self.model.device
+        N, B = self.sysd.n_atoms, self.sysd.n_struct
+        e_atom = torch.empty(N, dtype=torch.float64, device=dev)
+        e_struct = torch.empty(B, dtype=torch.float64, device=dev)
+        F = torch.empty(N, 3, dtype=torch.float64, device=dev) if forces else None
+        W = torch.empty(B, 3, 3, dtype=torch.float64, device=dev) if forces else None
+        return e_atom, e_struct, F, W
+
+    def energy_forces(self, pos: Optional[torch.Tensor] = None, virial: bool = True) -> Dict:
+        e_atom, e_struct, F, W = self._outs(True)
+        with torch.cuda.device(self.model.device):
+            check("afm_energy_forces",
+                  self.lib.afm_energy_forces(self.model.handle, C.byref(self.sysd.struct(pos)),
+                                             C.byref(self.nl.struct()), _ptr(e_atom), _ptr(e_struct),
+                                             _ptr(F), _ptr(W) if virial else None, C.byref(self.ws.ws),
+                                             _stream_ptr(self.model.device)))
+        return dict(e_atom=e_atom, e_struct=e_struct, forces=F, virial=W if virial else None)
+
+    def forward_energy(self, pos: Optional[torch.Tensor] = None):
+        e_atom, e_struct, _, _ = self._outs(False)
+        with torch.cuda.device(self.model.device):
+            check("afm_forward_energy",
+                  self.lib.afm_forward_energy(self.model.handle, C.byref(self.sysd.struct(pos)),
+                                              C.byref(self.nl.struct()), _ptr(e_atom), _ptr(e_struct),
+                                              C.byref(self.ws.ws), _stream_ptr(self.model.device)))
+        return e_atom, e_struct
+
+    def backward_forces(self, grad_e_struct: Optional[torch.Tensor] = None,
+                        pos: Optional[torch.Tensor] = None, virial: bool = False):
+        _, _, F, W = self._outs(True)
+        g = None if grad_e_struct is None else grad_e_struct.to(torch.float64).contiguous()
+        with torch.cuda.device(self.model.device):
+            check("afm_backward_forces",
+                  self.lib.afm_backward_forces(self.model.handle, C.byref(self.sysd.struct(pos)),
+                                               C.byref(self.nl.struct()), _ptr(g), _ptr(F),
+                                               _ptr(W) if virial else None, C.byref(self.ws.ws),
+                                               _stream_ptr(self.model.device)))
+        return F, (W if virial else None)
+
+
+class _EnergyFn(torch.autograd.Function):
+    """E_s(pos); its backward returns -forces weighted by the upstream grad."""
+
+    @staticmethod
+    def forward(ctx, pos, calc):
+        e_atom, e_struct = calc.forward_energy(pos.detach())
+        ctx.calc = calc
+        ctx.save_for_backward(pos)
+        return e_struct
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        (pos,) = ctx.saved_tensors
+        F, _ = ctx.calc.backward_forces(grad_e.contiguous(), pos=pos.detach())
+        return -F, None
+
+
+def energy_and_forces(calc: Calculator, pos: torch.Tensor) -> torch.Tensor:
+    """Differentiable E_s(pos) (forces = -dE/dpos through autograd)."""
+    return _EnergyFn.apply(pos, calc)

@@ -1,0 +1,44 @@
+// Layout of the per-chunk edge buffers shared by the edge and atom kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace afm {
+
+// geo[t][16]: delta (3, float32 from the float64 difference), |delta|,
+// envelope u, the 9 spherical-harmonic components (l <= 2), 2 unused.
+constexpr int GEO_D = 3, GEO_U = 4, GEO_Y = 5, GEO_STRIDE = 16;
+
+// Row (central atom) and edge range of one chunk, read on the device.
+struct RowRange {
+  const int64_t* chunk_rows;
+  const int64_t* row_ptr;
+  int chunk;
+  __device__ __forceinline__ void get(int64_t& e0, int64_t& e1) const {
+    e0 = row_ptr[chunk_rows[chunk]];
+    e1 = row_ptr[chunk_rows[chunk + 1]];
+  }
+};
+
+// Operands of the environment-sum / tensor-product kernels of one layer.
+struct TPArgs {
+  RowRange rr;
+  const float* geo;
+  const float* omega;    // omega^L  [t][lmax+1][C]
+  const float* omega1;   // omega^1  (features V^0 = omega^1 (x) Y when L == 1)
+  const float* vin;      // V^{L-1}  [t][n_in_comps][C]   (L > 1)
+  float* vout;           // V^L      [t][n_out_comps][C]  (L < NL)
+  float* s;              // s^L      [t][n0e][C]
+  float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
+  const float* alpha;    // [n_paths][C]
+  float inv_sqrt_nbar;
+  const float* gs;       // dE/ds^L
+  const float* gvout;    // dE/dV^L (L < NL)
+  float* gvin;           // dE/dV^{L-1} (L > 1)
+  float* gomega;         // dE/domega^L [t][lmax+1][C]
+  float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
+};
+
+int launch_tp(int lmax, int NL, int L, int C, bool bwd, const TPArgs& a, int64_t n_atoms_max, hipStream_t st);
+
+}  // namespace afm

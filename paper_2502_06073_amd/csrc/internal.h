@@ -1,0 +1,166 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/afm.h"
+#include "plan.h"
+
+namespace afm {
+
+void set_error(const std::string& msg);
+
+#define AFM_HIP_CHECK(expr)                                                   \
+  do {                                                                        \
+    hipError_t _e = (expr);                                                   \
+    if (_e != hipSuccess) {                                                   \
+      ::afm::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));    \
+      return AFM_E_HIP;                                                       \
+    }                                                                         \
+  } while (0)
+
+#define AFM_LAUNCH_CHECK()                                                    \
+  do {                                                                        \
+    hipError_t _e = hipGetLastError();                                        \
+    if (_e != hipSuccess) {                                                   \
+      ::afm::set_error(std::string("kernel launch: ") + hipGetErrorString(_e)); \
+      return AFM_E_HIP;                                                       \
+    }                                                                         \
+  } while (0)
+
+constexpr int kMaxTwobody = 4;
+constexpr int kMaxDepth = 4;
+constexpr int kMaxSpecies = 128;
+
+// Device-side weights.  FP32 copies in the layouts the kernels read; the
+// environment embedding rows are reordered l-major (row l*c + n holds the
+// paper-order row n*(l_max+1) + l) so that omega is stored [l][c] per edge.
+struct DevWeights {
+  const float* tb[kMaxTwobody] = {};           // [out][in]
+  const float* env[kMaxLayers] = {};           // [(lmax+1)*c][w], l-major rows
+  const float* lat[kMaxLayers][kMaxDepth] = {};// [out][in]
+  const float* alpha[kMaxLayers] = {};         // [n_paths][c]
+  const float* w_eff = nullptr;                // [w] = W_E1^T W_E2^T
+  const float* e0 = nullptr;                   // [h][w]
+  const float* e1 = nullptr;                   // [h]
+  const double* sp_scale = nullptr;            // [S]
+  const double* sp_shift = nullptr;            // [S]
+  // BF16 MFMA fragment-packed copies (see mfma_chain.hip); null for FP32
+  const void* frag = nullptr;
+  int64_t frag_off_fwd[kMaxLayers + 1][kMaxDepth + 1] = {};
+  int64_t frag_off_bwd[kMaxLayers + 1][kMaxDepth + 1] = {};
+};
+
+struct ModelDims {
+  int S, lmax, NL, w, c, nb, p, ntb, depth, h;
+  int tb[kMaxTwobody];
+  int n_lm;             // (lmax+1)^2 spherical-harmonic components
+  double r_cut, nbar, escale;
+};
+
+}  // namespace afm
+
+struct afm_model {
+  afm_hparams hp;
+  afm_precision prec;
+  afm::ModelDims dims;
+  afm::Plan plan;
+  int device;
+  int64_t n_params;
+  std::vector<afm_param_block> blocks;
+  void* dev_mem = nullptr;
+  afm::DevWeights W;
+};
+
+namespace afm {
+
+// Byte layout of a workspace, derived deterministically from the model and
+// the afm_workspace fields.  Offsets are relative to ws->ptr.
+struct WsLayout {
+  int64_t total = 0;
+  // neighbour-list scratch
+  int64_t nb_struct = 0, nb_atom = 0, nb_bin_count = 0, nb_bin_start = 0,
+          nb_bin_atoms = 0, nb_counts = 0, nb_scan = 0;
+  int64_t n_bins_max = 0;
+  // chunking
+  int64_t chunk_rows = 0;      // int64 [n_chunks + 1]
+  // global per-edge / per-atom buffers
+  int64_t g = 0;               // float [capacity][3]
+  int64_t gamma[kMaxLayers] = {};  // float [N][n_lm][c]
+  int64_t eps = 0;             // float [capacity] edge energies
+  int64_t atom_virial = 0;     // double [N][9]
+  // per-chunk edge buffers (CEX edges)
+  int64_t cex = 0;
+  int64_t eidx = 0;            // int32 [CEX] central atom of each local edge
+  int64_t geo = 0;             // float [CEX][16]
+  int64_t tb_pre[kMaxTwobody] = {};          // float [CEX][tb_k]
+  int64_t x[kMaxLayers + 1] = {};            // float [CEX][w]  x^0..x^{NL-1}
+  int64_t omega[kMaxLayers] = {};            // float [CEX][(lmax+1)c]
+  int64_t s[kMaxLayers] = {};                // float [CEX][n0e c]
+  int64_t v[kMaxLayers] = {};                // float [CEX][ncomp c] (V^1..V^{NL-1})
+  int64_t lat_pre[kMaxLayers][kMaxDepth] = {};  // float [CEX][w] (BF16 path: bf16)
+  int64_t gx = 0, gt0 = 0, gt1 = 0;          // float [CEX][max(w, w+n0e c)]
+  int64_t gs = 0;                            // float [CEX][n0e c]
+  int64_t gv0 = 0, gv1 = 0;                  // float [CEX][kMaxComps c]
+  int64_t gy = 0;                            // float [CEX][16] (GY[9], Gu at [9])
+  int64_t gomega = 0;                        // float [CEX][(lmax+1)c]
+  int64_t grho = 0;                          // float [CEX][16]
+};
+
+WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws);
+
+template <class T>
+inline T* ws_ptr(const afm_workspace* ws, int64_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws->ptr) + off);
+}
+
+int pack_weights(afm_model* m, const double* w);   // weights.cpp
+
+// ---- kernel launchers (defined in the .hip files) ----
+int upload_cg_table(const float* host_table);   // tp_kernels.hip
+
+struct SysDev {
+  int64_t N, B;
+  const double* pos;
+  const int32_t* species;
+  const double* cell;
+  const uint8_t* pbc;
+  const int64_t* seg;
+};
+
+struct NlDev {
+  int64_t capacity;
+  int64_t* row_ptr;
+  int32_t* col;
+  int8_t* shift;
+  int32_t* rev;
+  int64_t* n_edges;
+  int32_t* status;
+};
+
+int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl,
+                           const afm_workspace* ws, const WsLayout& L, int n_species,
+                           hipStream_t st);
+
+// chunk boundaries (rows) from row_ptr
+int launch_chunk_rows(const SysDev& s, const NlDev& nl, const afm_workspace* ws,
+                      const WsLayout& L, hipStream_t st);
+
+// forward/backward orchestration for one chunk (forward.hip)
+int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl,
+                      const afm_workspace* ws, const WsLayout& L, int chunk,
+                      hipStream_t st);
+int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl,
+                       const afm_workspace* ws, const WsLayout& L, int chunk,
+                       const double* grad_e_struct, hipStream_t st);
+int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl,
+                    const afm_workspace* ws, const WsLayout& L, double* e_atom,
+                    double* e_struct, hipStream_t st);
+int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl,
+                      const afm_workspace* ws, const WsLayout& L, double* forces,
+                      double* virial, hipStream_t st);
+
+}  // namespace afm

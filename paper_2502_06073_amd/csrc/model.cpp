@@ -1,0 +1,406 @@
+// Host side of the library: hyperparameter checks, the flat weight layout,
+// the real Clebsch-Gordan tables, model creation and workspace planning.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace afm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ----------------------------------------------------------------------------
+// hyperparameters
+
+static int dims_of(const afm_hparams* hp, ModelDims* d) {
+  if (!hp) { set_error("null hparams"); return AFM_E_INVALID; }
+  if (hp->n_species < 1 || hp->n_species > kMaxSpecies) { set_error("n_species out of range"); return AFM_E_INVALID; }
+  if (hp->l_max < 0 || hp->l_max > kMaxLmax) { set_error("l_max must be 0..2"); return AFM_E_UNSUPPORTED; }
+  if (hp->n_layers < 1 || hp->n_layers > 3) { set_error("n_layers must be 1..3"); return AFM_E_UNSUPPORTED; }
+  if (hp->n_twobody < 1 || hp->n_twobody > kMaxTwobody) { set_error("n_twobody must be 1..4"); return AFM_E_INVALID; }
+  if (hp->latent_depth < 1 || hp->latent_depth > kMaxDepth) { set_error("latent_depth must be 1..4"); return AFM_E_INVALID; }
+  if (hp->latent < 8 || hp->latent % 8) { set_error("latent width must be a positive multiple of 8"); return AFM_E_INVALID; }
+  if (hp->twobody[hp->n_twobody - 1] != hp->latent) { set_error("last two-body width must equal latent"); return AFM_E_INVALID; }
+  for (int k = 0; k < hp->n_twobody; ++k)
+    if (hp->twobody[k] < 1) { set_error("bad two-body width"); return AFM_E_INVALID; }
+  if (hp->channels != 8 && hp->channels != 16 && hp->channels != 32 && hp->channels != 64) {
+    set_error("channels must be 8, 16, 32 or 64"); return AFM_E_UNSUPPORTED;
+  }
+  if (hp->n_bessel < 1 || hp->n_bessel > 16) { set_error("n_bessel must be 1..16"); return AFM_E_INVALID; }
+  if (hp->poly_p < 2) { set_error("poly_p must be >= 2"); return AFM_E_INVALID; }
+  if (hp->edge_hidden < 1) { set_error("edge_hidden must be >= 1"); return AFM_E_INVALID; }
+  if (!(hp->r_cut > 0) || !(hp->avg_num_neighbors > 0) || !isfinite(hp->energy_scale)) {
+    set_error("r_cut, avg_num_neighbors must be positive, energy_scale finite"); return AFM_E_INVALID;
+  }
+  d->S = hp->n_species; d->lmax = hp->l_max; d->NL = hp->n_layers; d->w = hp->latent;
+  d->c = hp->channels; d->nb = hp->n_bessel; d->p = hp->poly_p; d->ntb = hp->n_twobody;
+  d->depth = hp->latent_depth; d->h = hp->edge_hidden;
+  for (int k = 0; k < kMaxTwobody; ++k) d->tb[k] = k < hp->n_twobody ? hp->twobody[k] : 0;
+  d->n_lm = (hp->l_max + 1) * (hp->l_max + 1);
+  d->r_cut = hp->r_cut; d->nbar = hp->avg_num_neighbors; d->escale = hp->energy_scale;
+  return AFM_OK;
+}
+
+static void push_block(std::vector<afm_param_block>& v, const char* name, int64_t rows,
+                       int64_t cols, int64_t fan_in, int init, int64_t& off) {
+  afm_param_block b{};
+  strncpy(b.name, name, sizeof(b.name) - 1);
+  b.offset = off; b.rows = rows; b.cols = cols; b.fan_in = fan_in; b.init = init;
+  off += rows * cols;
+  v.push_back(b);
+}
+
+static int build_layout(const afm_hparams* hp, std::vector<afm_param_block>& out, int64_t* total) {
+  ModelDims d{};
+  int rc = dims_of(hp, &d);
+  if (rc) return rc;
+  Plan P = make_plan(d.lmax, d.NL);
+  if (!P.ok) { set_error("unsupported (l_max, n_layers)"); return AFM_E_UNSUPPORTED; }
+  out.clear();
+  int64_t off = 0;
+  char nm[32];
+  int64_t in = 2 * d.S + d.nb;
+  for (int k = 0; k < d.ntb; ++k) {
+    snprintf(nm, sizeof nm, "twobody.%d", k);
+    push_block(out, nm, d.tb[k], in, in, 0, off);
+    in = d.tb[k];
+  }
+  for (int L = 1; L <= d.NL; ++L) {
+    const LayerPlan& lp = P.layer[L - 1];
+    snprintf(nm, sizeof nm, "layer%d.env", L);
+    push_block(out, nm, (int64_t)d.c * (d.lmax + 1), d.w, d.w, 0, off);
+    int64_t lin = d.w + (int64_t)lp.n0e * d.c;
+    for (int k = 0; k < d.depth; ++k) {
+      snprintf(nm, sizeof nm, "layer%d.latent.%d", L, k);
+      push_block(out, nm, d.w, k ? d.w : lin, k ? d.w : lin, 0, off);
+    }
+    if (L < d.NL) {
+      snprintf(nm, sizeof nm, "layer%d.alpha", L);
+      push_block(out, nm, lp.n_paths, d.c, 1, 2, off);
+    }
+  }
+  push_block(out, "edge.0", d.h, d.w, d.w, 0, off);
+  push_block(out, "edge.1", 1, d.h, d.h, 0, off);
+  push_block(out, "species.scale", d.S, 1, 1, 2, off);
+  push_block(out, "species.shift", d.S, 1, 1, 1, off);
+  *total = off;
+  return AFM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Real Clebsch-Gordan tensors.  Complex coefficients from Racah's closed
+// formula, moved to the real basis Y_real = U Y_complex of spherical
+// harmonics without the Condon-Shortley phase (l = 1 ordered (y, z, x)),
+// normalised to sum C^2 = 2 l3 + 1, sign fixed by the first nonzero entry.
+
+static double fact(int n) {
+  double r = 1;
+  for (int k = 2; k <= n; ++k) r *= k;
+  return r;
+}
+
+static double cg_complex(int j1, int m1, int j2, int m2, int J, int M) {
+  if (m1 + m2 != M || abs(m1) > j1 || abs(m2) > j2 || abs(M) > J) return 0.0;
+  if (J < abs(j1 - j2) || J > j1 + j2) return 0.0;
+  double pre = sqrt((2 * J + 1) * fact(J + j1 - j2) * fact(J - j1 + j2) * fact(j1 + j2 - J) /
+                    fact(j1 + j2 + J + 1));
+  pre *= sqrt(fact(J + M) * fact(J - M) * fact(j1 - m1) * fact(j1 + m1) * fact(j2 - m2) *
+              fact(j2 + m2));
+  double s = 0;
+  for (int k = 0; k <= j1 + j2 + J; ++k) {
+    int a = j1 + j2 - J - k, b = j1 - m1 - k, c = j2 + m2 - k, d = J - j2 + m1 + k,
+        e = J - j1 - m2 + k;
+    if (a < 0 || b < 0 || c < 0 || d < 0 || e < 0) continue;
+    s += ((k & 1) ? -1.0 : 1.0) / (fact(k) * fact(a) * fact(b) * fact(c) * fact(d) * fact(e));
+  }
+  return pre * s;
+}
+
+typedef std::complex<double> cd;
+
+static void real_basis(int l, std::vector<cd>& U) {
+  int d = 2 * l + 1;
+  U.assign(d * d, cd(0, 0));
+  const double r2 = 1.0 / sqrt(2.0);
+  for (int m = -l; m <= l; ++m) {
+    int r = m + l;
+    if (m == 0) {
+      U[r * d + l] = 1.0;
+    } else if (m > 0) {
+      U[r * d + l + m] = ((m & 1) ? -1.0 : 1.0) * r2;
+      U[r * d + l - m] = r2;
+    } else {
+      int am = -m;
+      U[r * d + l + am] = cd(0, -((am & 1) ? -1.0 : 1.0) * r2);
+      U[r * d + l - am] = cd(0, r2);
+    }
+  }
+}
+
+int real_cg(int l1, int l2, int l3, double* out) {
+  if (l1 < 0 || l2 < 0 || l3 < 0 || l3 < abs(l1 - l2) || l3 > l1 + l2 || l1 > 6 || l2 > 6)
+    return AFM_E_INVALID;
+  int d1 = 2 * l1 + 1, d2 = 2 * l2 + 1, d3 = 2 * l3 + 1;
+  std::vector<cd> U1, U2, U3;
+  real_basis(l1, U1); real_basis(l2, U2); real_basis(l3, U3);
+  std::vector<cd> Cr(d1 * d2 * d3, cd(0, 0));
+  for (int i = 0; i < d1; ++i)
+    for (int j = 0; j < d2; ++j)
+      for (int k = 0; k < d3; ++k) {
+        cd acc(0, 0);
+        for (int a = 0; a < d1; ++a) {
+          if (U1[i * d1 + a] == cd(0, 0)) continue;
+          for (int b = 0; b < d2; ++b) {
+            if (U2[j * d2 + b] == cd(0, 0)) continue;
+            int c = (a - l1) + (b - l2) + l3;
+            if (c < 0 || c >= d3) continue;
+            double cc = cg_complex(l1, a - l1, l2, b - l2, l3, c - l3);
+            if (cc == 0) continue;
+            acc += std::conj(U1[i * d1 + a]) * std::conj(U2[j * d2 + b]) * U3[k * d3 + c] * cc;
+          }
+        }
+        Cr[(i * d2 + j) * d3 + k] = acc;
+      }
+  double mr = 0, mi = 0;
+  for (auto& z : Cr) { mr = fmax(mr, fabs(z.real())); mi = fmax(mi, fabs(z.imag())); }
+  bool use_imag = mi > mr;
+  double ss = 0;
+  for (int q = 0; q < d1 * d2 * d3; ++q) {
+    double v = use_imag ? Cr[q].imag() : Cr[q].real();
+    if (fabs(v) < 1e-14) v = 0.0;
+    out[q] = v;
+    ss += v * v;
+  }
+  double sc = sqrt(d3 / ss);
+  double first = 0;
+  for (int q = 0; q < d1 * d2 * d3; ++q) {
+    out[q] *= sc;
+    if (first == 0 && fabs(out[q]) > 1e-9) first = out[q];
+  }
+  if (first < 0)
+    for (int q = 0; q < d1 * d2 * d3; ++q) out[q] = -out[q] + 0.0;
+  return AFM_OK;
+}
+
+static std::vector<float> cg_table_f32() {
+  std::vector<float> t(cg_table_size(), 0.f);
+  double buf[125];
+  for (int a = 0; a <= kMaxLmax; ++a)
+    for (int b = 0; b <= kMaxLmax; ++b)
+      for (int c = abs(a - b); c <= a + b && c <= kMaxLmax + kMaxLmax; ++c) {
+        int off = cg_offset(a, b, c);
+        if (off < 0) continue;
+        real_cg(a, b, c, buf);
+        int n = (2 * a + 1) * (2 * b + 1) * (2 * c + 1);
+        for (int q = 0; q < n; ++q) t[off + q] = (float)buf[q];
+      }
+  return t;
+}
+
+// ----------------------------------------------------------------------------
+// workspace layout
+
+static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
+  WsLayout L{};
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off += align256(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  const int64_t N = ws->n_atoms, B = ws->n_struct, cap = ws->edge_capacity;
+  L.n_bins_max = N + 27 * B + 1;
+  L.nb_struct = take(B * 128);
+  L.nb_atom = take(N * 16);
+  L.nb_bin_count = take((L.n_bins_max + 1) * 4);
+  L.nb_bin_start = take((L.n_bins_max + 1) * 4);
+  L.nb_bin_atoms = take(N * 4);
+  L.nb_counts = take((N + 1) * 8);
+  L.nb_scan = take(((N + 27 * B + 2) / 1024 + 4) * 8 + 4096);
+  L.chunk_rows = take((ws->n_chunks + 1) * 8);
+  if (!m) { L.total = off; return L; }   // neighbour-list part only
+  const ModelDims& d = m->dims;
+  const Plan& P = m->plan;
+  L.g = take(cap * 12);
+  for (int l = 0; l < d.NL; ++l) L.gamma[l] = take(N * d.n_lm * d.c * 4);
+  L.eps = take(cap * 4);
+  L.atom_virial = take(N * 72);
+  const int64_t E = ws->n_chunks > 1 ? ws->chunk_edges + ws->max_row : cap;
+  L.cex = E;
+  int maxcomp = 1, maxn0 = 1;
+  for (int l = 0; l < d.NL; ++l) {
+    maxcomp = maxcomp > P.layer[l].n_in_comps ? maxcomp : P.layer[l].n_in_comps;
+    maxcomp = maxcomp > P.layer[l].n_out_comps ? maxcomp : P.layer[l].n_out_comps;
+    maxn0 = maxn0 > P.layer[l].n0e ? maxn0 : P.layer[l].n0e;
+  }
+  const int64_t wide = d.w + (int64_t)maxn0 * d.c;
+  const int64_t gwide = wide > d.tb[0] ? wide : d.tb[0];
+  const int pre_bytes = (m->prec == AFM_BF16_MFMA) ? 2 : 4;
+  L.eidx = take(E * 4);
+  L.geo = take(E * 64);
+  for (int k = 0; k < d.ntb; ++k) L.tb_pre[k] = take(E * d.tb[k] * pre_bytes);
+  for (int l = 0; l < d.NL; ++l) L.x[l] = take(E * d.w * 4);
+  for (int l = 0; l < d.NL; ++l) L.omega[l] = take(E * (d.lmax + 1) * d.c * 4);
+  for (int l = 0; l < d.NL; ++l) L.s[l] = take(E * (int64_t)P.layer[l].n0e * d.c * 4);
+  for (int l = 0; l + 1 < d.NL; ++l) L.v[l] = take(E * (int64_t)P.layer[l].n_out_comps * d.c * 4);
+  for (int l = 0; l < d.NL; ++l)
+    for (int k = 0; k < d.depth; ++k) L.lat_pre[l][k] = take(E * d.w * pre_bytes);
+  L.gx = take(E * gwide * 4);
+  L.gt0 = take(E * gwide * 4);
+  L.gt1 = take(E * gwide * 4);
+  L.gs = take(E * (int64_t)maxn0 * d.c * 4);
+  L.gv0 = take(E * (int64_t)maxcomp * d.c * 4);
+  L.gv1 = take(E * (int64_t)maxcomp * d.c * 4);
+  L.gy = take(E * 64);
+  L.gomega = take(E * (d.lmax + 1) * d.c * 4);
+  L.grho = take(E * 64);
+  L.total = off;
+  return L;
+}
+
+}  // namespace afm
+
+using namespace afm;
+
+// ============================================================================
+// C ABI
+
+extern "C" {
+
+const char* afm_strerror(int code) {
+  switch (code) {
+    case AFM_OK: return "ok";
+    case AFM_E_INVALID: return "invalid argument";
+    case AFM_E_CAPACITY: return "buffer capacity exceeded";
+    case AFM_E_NONFINITE: return "non-finite input";
+    case AFM_E_UNSUPPORTED: return "unsupported precision or shape";
+    case AFM_E_HIP: return "HIP runtime error";
+    case AFM_E_WEIGHTS: return "weight vector does not match the layout";
+    default: return "unknown error";
+  }
+}
+
+const char* afm_last_error(void) { return g_last_error.c_str(); }
+const char* afm_version(void) { return "afm-mi355x 0.1 (gfx950)"; }
+
+int afm_param_layout_size(const afm_hparams* hp, int64_t* n_blocks, int64_t* n_params) {
+  if (!n_blocks || !n_params) { set_error("null output"); return AFM_E_INVALID; }
+  std::vector<afm_param_block> v;
+  int64_t tot = 0;
+  int rc = build_layout(hp, v, &tot);
+  if (rc) return rc;
+  *n_blocks = (int64_t)v.size();
+  *n_params = tot;
+  return AFM_OK;
+}
+
+int afm_param_layout_block(const afm_hparams* hp, int64_t k, afm_param_block* out) {
+  if (!out) { set_error("null output"); return AFM_E_INVALID; }
+  std::vector<afm_param_block> v;
+  int64_t tot = 0;
+  int rc = build_layout(hp, v, &tot);
+  if (rc) return rc;
+  if (k < 0 || k >= (int64_t)v.size()) { set_error("block index out of range"); return AFM_E_INVALID; }
+  *out = v[k];
+  return AFM_OK;
+}
+
+int afm_cg_real(int32_t l1, int32_t l2, int32_t l3, double* out) {
+  if (!out) { set_error("null output"); return AFM_E_INVALID; }
+  int rc = real_cg(l1, l2, l3, out);
+  if (rc) set_error("triangle rule violated or l > 6");
+  return rc;
+}
+
+int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_weights,
+                     afm_precision precision, afm_model** out) {
+  if (!out || !weights) { set_error("null argument"); return AFM_E_INVALID; }
+  *out = nullptr;
+  if (precision != AFM_FP32_PLAIN && precision != AFM_BF16_MFMA) {
+    set_error("precision not built (the FP64 reference is the CPU oracle)");
+    return AFM_E_UNSUPPORTED;
+  }
+  afm_model* m = new afm_model();
+  int rc = dims_of(hp, &m->dims);
+  if (!rc) rc = build_layout(hp, m->blocks, &m->n_params);
+  if (rc) { delete m; return rc; }
+  if (n_weights != m->n_params) {
+    set_error("expected " + std::to_string(m->n_params) + " weights, got " + std::to_string(n_weights));
+    delete m;
+    return AFM_E_WEIGHTS;
+  }
+  for (int64_t q = 0; q < n_weights; ++q)
+    if (!isfinite(weights[q])) { set_error("non-finite weight"); delete m; return AFM_E_NONFINITE; }
+  m->hp = *hp;
+  m->prec = precision;
+  m->plan = make_plan(m->dims.lmax, m->dims.NL);
+  hipError_t e = hipGetDevice(&m->device);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); delete m; return AFM_E_HIP; }
+  rc = pack_weights(m, weights);
+  if (rc) { if (m->dev_mem) (void)hipFree(m->dev_mem); delete m; return rc; }
+  std::vector<float> cg = cg_table_f32();
+  rc = upload_cg_table(cg.data());
+  if (rc) { (void)hipFree(m->dev_mem); delete m; return rc; }
+  *out = m;
+  return AFM_OK;
+}
+
+int afm_model_destroy(afm_model* m) {
+  if (!m) return AFM_OK;
+  if (m->dev_mem) {
+    hipError_t e = hipFree(m->dev_mem);
+    m->dev_mem = nullptr;
+    delete m;
+    if (e != hipSuccess) { set_error(hipGetErrorString(e)); return AFM_E_HIP; }
+    return AFM_OK;
+  }
+  delete m;
+  return AFM_OK;
+}
+
+int afm_workspace_plan(const afm_model* m, int64_t n_atoms, int64_t n_struct, int64_t edge_capacity,
+                       int64_t max_bytes, int32_t with_second_order, afm_workspace* ws) {
+  if (!ws) { set_error("null argument"); return AFM_E_INVALID; }
+  if (n_atoms < 0 || n_struct < 1 || edge_capacity < 0) { set_error("bad sizes"); return AFM_E_INVALID; }
+  if (edge_capacity >= (int64_t(1) << 31)) { set_error("edge capacity must be < 2^31"); return AFM_E_INVALID; }
+  if (with_second_order) { set_error("second-order workspace not built yet"); return AFM_E_UNSUPPORTED; }
+  afm_workspace w{};
+  w.n_atoms = n_atoms; w.n_struct = n_struct; w.edge_capacity = edge_capacity;
+  w.max_row = 1024;
+  w.precision = m ? m->prec : -1;
+  w.with_second_order = with_second_order;
+  w.chunk_edges = edge_capacity > 0 ? edge_capacity : 1;
+  w.n_chunks = 1;
+  WsLayout L = workspace_layout(m, &w);
+  if (m && max_bytes > 0 && L.total > max_bytes) {
+    // bytes that do not scale with the chunk
+    afm_workspace w1 = w;
+    w1.n_chunks = 2; w1.chunk_edges = 1;
+    WsLayout L1 = workspace_layout(m, &w1);
+    w1.chunk_edges = 1 + 65536;
+    WsLayout L2 = workspace_layout(m, &w1);
+    double per_edge = double(L2.total - L1.total) / 65536.0;
+    double fixed = double(L1.total) - per_edge * (1 + w1.max_row);
+    int64_t ce = (int64_t)((double(max_bytes) - fixed) / per_edge) - w1.max_row - 1024;
+    if (ce < 4096) { set_error("max_bytes too small for a chunk of 4096 edges"); return AFM_E_CAPACITY; }
+    w.chunk_edges = ce;
+    w.n_chunks = (edge_capacity + ce - 1) / ce;
+    if (w.n_chunks < 1) w.n_chunks = 1;
+    if (w.n_chunks == 1) w.chunk_edges = edge_capacity;
+    L = workspace_layout(m, &w);
+  }
+  w.bytes = L.total;
+  w.ptr = nullptr;
+  *ws = w;
+  return AFM_OK;
+}
+
+}  // extern "C"

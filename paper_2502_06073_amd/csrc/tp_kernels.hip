@@ -1,0 +1,333 @@
+// Environment sums and channelwise Clebsch-Gordan tensor products (the
+// "tensor features ... l = 2 in full O(3)" of Methodology / Model Training).
+//
+// One workgroup per central atom i (all edges of row i): 256 threads =
+// (256 / C) edge slots x C channels, channel fastest so every load is
+// coalesced over channels.
+//   forward:  Gamma_i[lm][n] = nbar^-1/2 sum_{e in row i} omega_e[l][n] Y_e[lm]
+//             M^pi_i[m1][m3][n] = sum_m2 C^{l1 l2 l3}[m1][m2][m3] Gamma_i[l2 m2][n]
+//             T^pi_e[m3][n] = sum_m1 V_e[l1 p1, m1][n] M^pi_i[m1][m3][n]
+//             s_e (0e paths), V'_e = sum_pi alpha[pi][n] T^pi_e   (next layer)
+//   backward: the adjoints of the three lines above; the adjoint of M is
+//             accumulated per thread in registers over the row's edges,
+//             reduced over slots in LDS, then contracted back to Gamma.
+// The per-atom precontraction M turns the per-edge product into small dense
+// (2l1+1) x (2l3+1) products with compile-time shapes.
+#include <hip/hip_runtime.h>
+
+#include "device_util.h"
+#include "gemm_f32.h"
+#include "internal.h"
+
+namespace afm {
+
+__constant__ float c_cg[cg_table_size()];
+
+int upload_cg_table(const float* host_table) {
+  AFM_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_cg), host_table, sizeof(float) * cg_table_size(), 0,
+                                  hipMemcpyHostToDevice));
+  return AFM_OK;
+}
+
+
+template <int LMAX, int NL, int L>
+struct LayerCT {
+  static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
+};
+
+// M^pi for every path of the layer into LDS (paths split over slots)
+template <int LMAX, int NL, int L, int C>
+__device__ __forceinline__ void build_M(float* Ms, const float* gam, int n, int slot) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
+  constexpr int NS = 256 / C;
+  static_for<0, LP.n_paths>([&](auto K) {
+    constexpr PathT pt = LP.p[decltype(K)::value];
+    constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
+    constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
+    if (decltype(K)::value % NS == slot) {
+      float g[d2];
+#pragma unroll
+      for (int m2 = 0; m2 < d2; ++m2) g[m2] = gam[(pt.l2 * pt.l2 + m2) * C + n];
+#pragma unroll
+      for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int m2 = 0; m2 < d2; ++m2) acc += c_cg[off + (m1 * d2 + m2) * d3 + m3] * g[m2];
+          Ms[(pt.m_off + m1 * d3 + m3) * C + n] = acc;
+        }
+    }
+  });
+}
+
+template <int LMAX, int NL, int L, int C>
+__device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const float* Y,
+                                       float* V) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
+  if constexpr (L == 1) {
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) V[l * l + m] = w * Y[l * l + m];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < LP.n_in_comps; ++q) V[q] = a.vin[(t * LP.n_in_comps + q) * C + n];
+  }
+}
+
+template <int LMAX, int NL, int L, int C>
+__global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NS = 256 / C;
+  constexpr int NCI = LP.n_in_comps, NCO = LP.n_out_comps > 0 ? LP.n_out_comps : 1;
+  __shared__ float Ms[LP.m_size * C];
+  __shared__ float red[NS * NLM * C];
+  __shared__ float gam[NLM * C];
+  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    float acc[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) acc[q] = 0.0f;
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) acc[l * l + m] += w * Y[l * l + m];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) red[(slot * NLM + q) * C + n] = acc[q];
+    __syncthreads();
+    for (int q = slot; q < NLM; q += NS) {
+      float g = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) g += red[(s * NLM + q) * C + n];
+      g *= a.inv_sqrt_nbar;
+      gam[q * C + n] = g;
+      a.gamma[(i * NLM + q) * C + n] = g;
+    }
+    __syncthreads();
+    build_M<LMAX, NL, L, C>(Ms, gam, n, slot);
+    __syncthreads();
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      float V[NCI];
+      load_V<LMAX, NL, L, C>(a, t, n, Y, V);
+      float out[NCO];
+#pragma unroll
+      for (int q = 0; q < NCO; ++q) out[q] = 0.0f;
+      static_for<0, LP.n_paths>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr PathT pt = LP.p[k];
+        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        float T[d3];
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) {
+          float v = 0.0f;
+#pragma unroll
+          for (int m1 = 0; m1 < d1; ++m1) v += V[pt.in_off + m1] * Ms[(pt.m_off + m1 * d3 + m3) * C + n];
+          T[m3] = v;
+        }
+        if constexpr (pt.s_idx >= 0) a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
+        if constexpr (pt.out_off >= 0) {
+          const float al = a.alpha[k * C + n];
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3) out[pt.out_off + m3] += al * T[m3];
+        }
+      });
+      if constexpr (LP.n_out_comps > 0) {
+#pragma unroll
+        for (int q = 0; q < LP.n_out_comps; ++q) a.vout[(t * LP.n_out_comps + q) * C + n] = out[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int LMAX, int NL, int L, int C>
+__global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NS = 256 / C;
+  constexpr int NCI = LP.n_in_comps;
+  constexpr int MS = LP.m_size;
+  constexpr int MAXB = 25;   // largest (2l1+1)(2l3+1) block
+  __shared__ float Ms[MS * C];
+  __shared__ float Gm[MS * C];
+  __shared__ float red[NS * MAXB * C];
+  __shared__ float gam[NLM * C];
+  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    for (int q = slot; q < NLM; q += NS) gam[q * C + n] = a.gamma[(i * NLM + q) * C + n];
+    __syncthreads();
+    build_M<LMAX, NL, L, C>(Ms, gam, n, slot);
+    __syncthreads();
+    float GM[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) GM[q] = 0.0f;
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      float V[NCI];
+      load_V<LMAX, NL, L, C>(a, t, n, Y, V);
+      float GV[NCI];
+#pragma unroll
+      for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
+      static_for<0, LP.n_paths>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr PathT pt = LP.p[k];
+        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        float GT[d3];
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) GT[m3] = 0.0f;
+        if constexpr (pt.s_idx >= 0) GT[0] = a.gs[(t * LP.n0e + pt.s_idx) * C + n];
+        if constexpr (pt.out_off >= 0) {
+          const float al = a.alpha[k * C + n];
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3)
+            GT[m3] += al * a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
+        }
+#pragma unroll
+        for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3) {
+            GV[pt.in_off + m1] += Ms[(pt.m_off + m1 * d3 + m3) * C + n] * GT[m3];
+            GM[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GT[m3];
+          }
+      });
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int q = 0; q < NCI; ++q) a.gvin[(t * NCI + q) * C + n] = GV[q];
+      } else {
+        // V^0 = omega^1 (x) Y
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) {
+          const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+          float go = 0.0f;
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) {
+            go += GV[l * l + m] * Y[l * l + m];
+            const float gyv = group_sum<C>(GV[l * l + m] * w);
+            if (n == 0) a.gy[t * GEO_STRIDE + l * l + m] += gyv;
+          }
+          a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
+        }
+      }
+    }
+    // reduce GM over slots, path by path
+    static_for<0, LP.n_paths>([&](auto K) {
+      constexpr PathT pt = LP.p[decltype(K)::value];
+      constexpr int blk = (2 * pt.l1 + 1) * (2 * pt.l3 + 1);
+#pragma unroll
+      for (int q = 0; q < blk; ++q) red[(slot * MAXB + q) * C + n] = GM[pt.m_off + q];
+      __syncthreads();
+      for (int q = slot; q < blk; q += NS) {
+        float v = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v += red[(s * MAXB + q) * C + n];
+        Gm[(pt.m_off + q) * C + n] = v;
+      }
+      __syncthreads();
+    });
+    // dE/dGamma, scaled by nbar^-1/2, into gam
+    for (int q = slot; q < NLM; q += NS) {
+      float g = 0.0f;
+      static_for<0, LP.n_paths>([&](auto K) {
+        constexpr PathT pt = LP.p[decltype(K)::value];
+        constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
+        constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
+        const int m2 = q - pt.l2 * pt.l2;
+        if (m2 >= 0 && m2 < d2) {
+#pragma unroll
+          for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+            for (int m3 = 0; m3 < d3; ++m3)
+              g += c_cg[off + (m1 * d2 + m2) * d3 + m3] * Gm[(pt.m_off + m1 * d3 + m3) * C + n];
+        }
+      });
+      red[q * C + n] = g * a.inv_sqrt_nbar;
+    }
+    __syncthreads();
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+        float go = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const float gg = red[(l * l + m) * C + n];
+          go += gg * Y[l * l + m];
+          const float gyv = group_sum<C>(gg * w);
+          if (n == 0) a.gy[t * GEO_STRIDE + l * l + m] += gyv;
+        }
+        float* dst = a.gomega + (t * (LMAX + 1) + l) * C + n;
+        if constexpr (L == 1) *dst += go; else *dst = go;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+typedef void (*tp_kernel_t)(TPArgs);
+
+template <int LMAX, int NL, int C>
+static tp_kernel_t pick(int L, bool bwd) {
+  if (L == 1) return bwd ? k_tp_bwd<LMAX, NL, 1, C> : k_tp_fwd<LMAX, NL, 1, C>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp_bwd<LMAX, NL, 2, C> : k_tp_fwd<LMAX, NL, 2, C>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp_bwd<LMAX, NL, 3, C> : k_tp_fwd<LMAX, NL, 3, C>;
+  return nullptr;
+}
+
+template <int LMAX, int C>
+static tp_kernel_t pick_nl(int NL, int L, bool bwd) {
+  switch (NL) {
+    case 1: return pick<LMAX, 1, C>(L, bwd);
+    case 2: return pick<LMAX, 2, C>(L, bwd);
+    case 3: return pick<LMAX, 3, C>(L, bwd);
+  }
+  return nullptr;
+}
+
+template <int LMAX>
+static tp_kernel_t pick_c(int C, int NL, int L, bool bwd) {
+  switch (C) {
+    case 8: return pick_nl<LMAX, 8>(NL, L, bwd);
+    case 16: return pick_nl<LMAX, 16>(NL, L, bwd);
+    case 32: return pick_nl<LMAX, 32>(NL, L, bwd);
+    case 64: return pick_nl<LMAX, 64>(NL, L, bwd);
+  }
+  return nullptr;
+}
+
+int launch_tp(int lmax, int NL, int L, int C, bool bwd, const TPArgs& a, int64_t n_atoms_max,
+              hipStream_t st) {
+  tp_kernel_t k = nullptr;
+  switch (lmax) {
+    case 0: k = pick_c<0>(C, NL, L, bwd); break;
+    case 1: k = pick_c<1>(C, NL, L, bwd); break;
+    case 2: k = pick_c<2>(C, NL, L, bwd); break;
+  }
+  if (!k) { set_error("tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
+  const unsigned grid = grid_for(n_atoms_max, 1, 65536);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, a);
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
+}  // namespace afm

@@ -1,0 +1,109 @@
+// Packs the flat float64 weight vector into the device layouts the kernels
+// read (one device allocation per model).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace afm {
+int64_t bf16_frag_bytes(const afm_model* m);                       // mfma_chain.hip
+void pack_bf16_frags(const afm_model* m, const std::vector<const double*>& blk,
+                     std::vector<char>& out, DevWeights* W_offsets); // mfma_chain.hip
+}
+
+namespace afm {
+
+static const afm_param_block* find_block(const afm_model* m, const char* name) {
+  for (auto& b : m->blocks)
+    if (strcmp(b.name, name) == 0) return &b;
+  return nullptr;
+}
+
+int pack_weights(afm_model* m, const double* w) {
+  const ModelDims& d = m->dims;
+  std::vector<char> host;
+  auto reserve = [&](int64_t bytes) {
+    int64_t o = (int64_t)host.size();
+    int64_t pad = (bytes + 255) & ~int64_t(255);
+    host.resize(o + pad, 0);
+    return o;
+  };
+  struct Fix { const void** dst; int64_t off; };
+  std::vector<Fix> fix;
+  auto put_f32 = [&](const void** dst, const double* src, int64_t n) {
+    int64_t o = reserve(n * 4);
+    float* p = reinterpret_cast<float*>(host.data() + o);
+    for (int64_t q = 0; q < n; ++q) p[q] = (float)src[q];
+    fix.push_back({dst, o});
+  };
+  char nm[32];
+  std::vector<const double*> blk;   // block pointers in layout order
+  for (auto& b : m->blocks) blk.push_back(w + b.offset);
+
+  for (int k = 0; k < d.ntb; ++k) {
+    snprintf(nm, sizeof nm, "twobody.%d", k);
+    const afm_param_block* b = find_block(m, nm);
+    put_f32((const void**)&m->W.tb[k], w + b->offset, b->rows * b->cols);
+  }
+  for (int L = 1; L <= d.NL; ++L) {
+    snprintf(nm, sizeof nm, "layer%d.env", L);
+    const afm_param_block* b = find_block(m, nm);
+    std::vector<double> perm((size_t)b->rows * b->cols);
+    for (int l = 0; l <= d.lmax; ++l)
+      for (int n = 0; n < d.c; ++n)
+        memcpy(&perm[((size_t)l * d.c + n) * d.w], w + b->offset + ((size_t)n * (d.lmax + 1) + l) * d.w,
+               sizeof(double) * d.w);
+    put_f32((const void**)&m->W.env[L - 1], perm.data(), (int64_t)perm.size());
+    for (int k = 0; k < d.depth; ++k) {
+      snprintf(nm, sizeof nm, "layer%d.latent.%d", L, k);
+      b = find_block(m, nm);
+      put_f32((const void**)&m->W.lat[L - 1][k], w + b->offset, b->rows * b->cols);
+    }
+    if (L < d.NL) {
+      snprintf(nm, sizeof nm, "layer%d.alpha", L);
+      b = find_block(m, nm);
+      put_f32((const void**)&m->W.alpha[L - 1], w + b->offset, b->rows * b->cols);
+    }
+  }
+  const afm_param_block* e0 = find_block(m, "edge.0");
+  const afm_param_block* e1 = find_block(m, "edge.1");
+  put_f32((const void**)&m->W.e0, w + e0->offset, e0->rows * e0->cols);
+  put_f32((const void**)&m->W.e1, w + e1->offset, e1->rows * e1->cols);
+  std::vector<double> weff(d.w, 0.0);
+  for (int hh = 0; hh < d.h; ++hh) {
+    double a = w[e1->offset + hh];
+    for (int f = 0; f < d.w; ++f) weff[f] += w[e0->offset + (int64_t)hh * d.w + f] * a;
+  }
+  put_f32((const void**)&m->W.w_eff, weff.data(), d.w);
+  {
+    const afm_param_block* sc = find_block(m, "species.scale");
+    const afm_param_block* sh = find_block(m, "species.shift");
+    int64_t o = reserve(d.S * 8);
+    memcpy(host.data() + o, w + sc->offset, d.S * 8);
+    fix.push_back({(const void**)&m->W.sp_scale, o});
+    o = reserve(d.S * 8);
+    memcpy(host.data() + o, w + sh->offset, d.S * 8);
+    fix.push_back({(const void**)&m->W.sp_shift, o});
+  }
+  int64_t frag_off = -1;
+  if (m->prec == AFM_BF16_MFMA) {
+    std::vector<char> frags;
+    pack_bf16_frags(m, blk, frags, &m->W);
+    frag_off = reserve((int64_t)frags.size());
+    memcpy(host.data() + frag_off, frags.data(), frags.size());
+  }
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, host.size());
+  if (e != hipSuccess) { set_error(std::string("hipMalloc weights: ") + hipGetErrorString(e)); return AFM_E_HIP; }
+  m->dev_mem = dev;
+  e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { set_error(std::string("hipMemcpy weights: ") + hipGetErrorString(e)); return AFM_E_HIP; }
+  for (auto& f : fix) *f.dst = static_cast<char*>(dev) + f.off;
+  if (frag_off >= 0) m->W.frag = static_cast<char*>(dev) + frag_off;
+  return AFM_OK;
+}
+
+}  // namespace afm

@@ -1,0 +1,96 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+the header declares, its host-side tables (weight layout, real CG tensors)
+agree with the oracle's independent derivations, and argument errors come
+back as status codes (no GPU call is made by these paths)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import model as M
+from oracle import so3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+afm = pytest.importorskip("paper_2502_06073_amd")
+from paper_2502_06073_amd import _abi  # noqa: E402
+
+
+def _lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libafm.so not built (python -m paper_2502_06073_amd.build)")
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "afm.h")).read()
+    names = set(re.findall(r"\b(afm_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(_abi.EXPORTS) == names
+
+
+@pytest.mark.parametrize("name", list("ABCDE"))
+def test_param_layout_matches_oracle(name):
+    _lib()
+    hp = synth.load_hparams(name)
+    ours = afm.param_layout(hp)
+    ref = M.param_layout(M.HParams.from_dict(hp))
+    assert [b["name"] for b in ours] == [b["name"] for b in ref]
+    for a, b in zip(ours, ref):
+        assert tuple(a["shape"]) == tuple(b["shape"]), a["name"]
+        assert a["fan_in"] == b["fan_in"] and a["init"] == b["init"], a["name"]
+    assert sum(b["size"] for b in ours) == M.n_params(M.HParams.from_dict(hp))
+
+
+def test_table1_counts_through_library():
+    _lib()
+    want = {64: 46914, 256: 676466, 512: 2614194}
+    for w, c, h in [(64, 16, 64), (256, 64, 128)]:
+        hp = dict(n_species=89, l_max=2, n_layers=2, latent=w, channels=c, n_bessel=8, poly_p=6,
+                  twobody=[w // 4, w // 2, w], latent_depth=3, edge_hidden=h, r_cut=5.2)
+        assert sum(b["size"] for b in afm.param_layout(hp)) == want[w]
+
+
+@pytest.mark.parametrize("t", [(l1, l2, l3) for l1 in range(3) for l2 in range(3)
+                               for l3 in range(abs(l1 - l2), min(l1 + l2, 3) + 1)])
+def test_cg_tables_match_oracle(t):
+    _lib()
+    np.testing.assert_allclose(afm.cg_real(*t), so3.cg(*t), atol=1e-13)
+
+
+def test_host_error_paths():
+    lib = _lib()
+    hp = synth.load_hparams("A")
+    h = afm.hparams_struct(hp)
+    out = C.c_void_p()
+    w = np.zeros(10)
+    rc = lib.afm_model_create(C.byref(h), w.ctypes.data_as(C.POINTER(C.c_double)), 10, 1, C.byref(out))
+    assert rc == -6 and out.value is None           # AFM_E_WEIGHTS
+    assert b"expected 4836" in lib.afm_last_error()
+    rc = lib.afm_model_create(C.byref(h), w.ctypes.data_as(C.POINTER(C.c_double)), 10, 0, C.byref(out))
+    assert rc == -4                                 # FP64 on the device is not built
+    rc = lib.afm_model_create(None, None, 0, 1, C.byref(out))
+    assert rc == -1
+    bad = afm.hparams_struct(dict(hp, l_max=3))
+    nb, npar = C.c_int64(), C.c_int64()
+    assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == -4
+    bad = afm.hparams_struct(dict(hp, twobody=[16, 48]))
+    assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == -1
+    ws = _abi.Workspace()
+    assert lib.afm_workspace_plan(None, 10, 1, 100, 0, 0, None) == -1
+    assert lib.afm_workspace_plan(None, 10, 0, 100, 0, 0, C.byref(ws)) == -1
+    assert lib.afm_workspace_plan(None, 10, 1, 100, 0, 0, C.byref(ws)) == 0 and ws.bytes > 0
+    assert lib.afm_build_neighbors(None, 4.0, None, None, None) == -1
+    assert lib.afm_strerror(-2) == b"buffer capacity exceeded"
+    assert lib.afm_version().startswith(b"afm")
+    nanw = synth.draw_weights(M.param_layout(M.HParams.from_dict(hp)), 1)
+    nanw[3] = np.nan
+    rc = lib.afm_model_create(C.byref(h), nanw.ctypes.data_as(C.POINTER(C.c_double)), nanw.shape[0], 1,
+                              C.byref(out))
+    assert rc == -3                                 # AFM_E_NONFINITE
