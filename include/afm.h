@@ -239,10 +239,16 @@ int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
  * float64 with a = F / m * 9.648533212e-3 A fs^-2 per (eV A^-1 amu^-1).  The
  * neighbour list (cutoff r_cut + skin) is rebuilt, after wrapping periodic
  * atoms by whole lattice shifts, before the force evaluation of every step
- * k with k % rebuild_every == 0 (k counts from state->step).  Each step
- * writes (kinetic, potential) energies to energy_log[2 * t] (device,
- * float64, n_steps pairs).  Forces of the current positions must be in
- * state->forces on entry (afm_energy_forces) and are updated. */
+ * k with k % rebuild_every == 0 (k counts from state->step + 1).  Each step
+ * writes (kinetic, potential) energies to energy_log[2 t], [2 t + 1]
+ * (device, float64, n_steps pairs).  On entry state->forces must hold the
+ * forces of the current positions (afm_energy_forces) and the list must be
+ * current; state->step == 0 marks a fresh start (the positions become the
+ * rebuild reference for the skin check).  An atom displaced by more than
+ * skin/2 since the last rebuild sets AFM_FLAG_SKIN.  With use_graph != 0 and
+ * a non-null stream, the n-step sequence is captured into a hipGraph on the
+ * first call for a given phase (step % rebuild_every) and replayed after
+ * that (the first call instantiates the graph: host-side setup). */
 typedef struct {
   double* pos;                   /* [n_atoms, 3] device, updated */
   double* vel;                   /* [n_atoms, 3] device, updated */
@@ -251,6 +257,7 @@ typedef struct {
   double dt_fs;
   double skin;
   int32_t rebuild_every;
+  int32_t use_graph;
   int64_t step;                  /* host, advanced by n_steps */
   double* energy_log;            /* [n_steps, 2] device */
   double* e_atom;                /* [n_atoms] device scratch */
@@ -259,6 +266,21 @@ typedef struct {
 
 int afm_md_step(const afm_model* model, const afm_system* sys, afm_nlist* nl,
                 afm_md_state* state, int32_t n_steps, const afm_workspace* ws, void* stream);
+
+/* ---- tracing -------------------------------------------------------------
+ * Per-stage HIP-event timers for profiling (host bookkeeping; do not enable
+ * while capturing a graph).  afm_trace_enable(1) clears old records and
+ * starts recording a start/stop event pair around every kernel stage of the
+ * library on its stream; afm_trace_read waits for the recorded events and
+ * returns, per stage name (e.g. "latent_fwd2"), the launch count and the
+ * summed GPU time.  out: host, `max` entries; *n receives the stage count. */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  double total_ms;
+} afm_trace_stat;
+int afm_trace_enable(int32_t enable);
+int afm_trace_read(afm_trace_stat* out /*host*/, int32_t max, int32_t* n /*host*/);
 
 /* ---- diagnostics ------------------------------------------------------- */
 const char* afm_strerror(int code);

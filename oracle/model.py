@@ -402,6 +402,37 @@ def forces_subset(hp, weights: np.ndarray, sys, atoms: np.ndarray,
                 n_edges=int(g.shape[0]))
 
 
+def rows_energy_grad(hp, weights: np.ndarray, sys, rows: np.ndarray,
+                     r_list: Optional[float] = None, chunk: int = 256) -> Dict[str, np.ndarray]:
+    """E_i of the given central atoms and g_e = dE/d delta_e of their edges:
+    the per-row share of one energy+force evaluation (rows are independent
+    by locality).  Used to time the oracle on a bounded sample."""
+    hp = _as_hp(hp)
+    rows = np.sort(np.asarray(rows, np.int64))
+    nl = nbr.build(sys, hp.r_cut if r_list is None else r_list, rows=rows)
+    P = unpack(hp, torch.tensor(weights, dtype=DT))
+    species = torch.tensor(sys.species.astype(np.int64))
+    delta_all = nbr.edge_vectors(sys, nl)
+    g = np.zeros_like(delta_all)
+    E = np.zeros(rows.shape[0])
+    rs = np.searchsorted(nl["i"], rows, side="left")
+    re = np.searchsorted(nl["i"], rows, side="right")
+    for c0 in range(0, rows.shape[0], chunk):
+        c1 = min(rows.shape[0], c0 + chunk)
+        e0, e1 = int(rs[c0]), int(re[c1 - 1])
+        delta = torch.tensor(delta_all[e0:e1], dtype=DT, requires_grad=True)
+        I = torch.tensor(nl["i"][e0:e1])
+        J = torch.tensor(nl["j"][e0:e1])
+        loc = torch.tensor(np.searchsorted(rows[c0:c1], nl["i"][e0:e1]))
+        Ei = rows_energy(hp, P, delta, species[I], species[J], loc,
+                         species[torch.tensor(rows[c0:c1])])
+        E[c0:c1] = Ei.detach().numpy()
+        if e1 > e0:
+            (gc,) = torch.autograd.grad(Ei.sum(), delta)
+            g[e0:e1] = gc.numpy()
+    return dict(e_atom=E, g=g, n_edges=int(g.shape[0]))
+
+
 def vjp_weights(hp, weights: np.ndarray, sys, grad_e_struct: np.ndarray,
                 grad_forces: np.ndarray, nl: Optional[Dict] = None,
                 r_list: Optional[float] = None,

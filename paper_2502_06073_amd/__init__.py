@@ -25,7 +25,24 @@ from . import _abi
 from ._abi import AfmError, check, load
 
 __all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
-           "param_layout", "cg_real", "hparams_struct", "energy_and_forces", "AfmError"]
+           "param_layout", "cg_real", "hparams_struct", "energy_and_forces", "AfmError",
+           "trace_enable", "trace_read"]
+
+
+def trace_enable(on: bool = True) -> None:
+    """Start (clearing old records) or stop per-stage HIP-event timing."""
+    check("afm_trace_enable", load().afm_trace_enable(1 if on else 0))
+
+
+def trace_read() -> Dict[str, Dict[str, float]]:
+    """Per-stage launch counts and summed GPU milliseconds since trace_enable."""
+    lib = load()
+    n = C.c_int32()
+    check("afm_trace_read", lib.afm_trace_read(None, 0, C.byref(n)))
+    arr = (_abi.TraceStat * max(1, n.value))()
+    check("afm_trace_read", lib.afm_trace_read(arr, n.value, C.byref(n)))
+    return {arr[k].name.decode(): dict(launches=arr[k].launches, total_ms=arr[k].total_ms)
+            for k in range(n.value)}
 
 
 def _stream_ptr(device) -> C.c_void_p:
@@ -300,3 +317,60 @@ class _EnergyFn(torch.autograd.Function):
 def energy_and_forces(calc: Calculator, pos: torch.Tensor) -> torch.Tensor:
     """Differentiable E_s(pos) (forces = -dE/dpos through autograd)."""
     return _EnergyFn.apply(pos, calc)
+
+
+class MD:
+    """NVE velocity-Verlet driver over afm_md_step.  Positions are updated in
+    place in calc.sysd.pos; calc must have been built with r_list = r_cut +
+    skin.  With use_graph the steps run on a private stream and are replayed
+    from a captured hipGraph after the first call of each phase."""
+
+    def __init__(self, calc: Calculator, masses_by_species, v0, dt_fs: float = 0.5, skin: float = 0.5,
+                 rebuild_every: int = 10, use_graph: bool = False):
+        dev = calc.model.device
+        self.calc = calc
+        self.stream = torch.cuda.Stream(dev) if use_graph else None
+        N, B = calc.sysd.n_atoms, calc.sysd.n_struct
+        self.mass = torch.as_tensor(np.asarray(masses_by_species, np.float64), device=dev)
+        self.vel = torch.as_tensor(np.ascontiguousarray(v0, np.float64), device=dev).reshape(N, 3).contiguous()
+        self.e_atom = torch.zeros(N, dtype=torch.float64, device=dev)
+        self.e_struct = torch.zeros(B, dtype=torch.float64, device=dev)
+        calc.build_neighbors()
+        out = calc.energy_forces(virial=False)
+        self.forces = out["forces"]
+        st = _abi.MdState()
+        st.pos = _ptr(calc.sysd.pos)
+        st.vel = _ptr(self.vel)
+        st.forces = _ptr(self.forces)
+        st.mass_by_species = _ptr(self.mass)
+        st.dt_fs = float(dt_fs)
+        st.skin = float(skin)
+        st.rebuild_every = int(rebuild_every)
+        st.use_graph = int(use_graph)
+        st.step = 0
+        st.e_atom = _ptr(self.e_atom)
+        st.e_struct = _ptr(self.e_struct)
+        self.state = st
+        self._logs = {}
+
+    def run(self, n_steps: int) -> torch.Tensor:
+        """Advance n_steps; returns the [n_steps, 2] (kinetic, potential) log."""
+        dev = self.calc.model.device
+        log = self._logs.get(n_steps)
+        if log is None:
+            log = torch.zeros(n_steps, 2, dtype=torch.float64, device=dev)
+            self._logs[n_steps] = log
+        self.state.energy_log = _ptr(log)
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(dev))
+            with torch.cuda.stream(self.stream):
+                check("afm_md_step", load().afm_md_step(
+                    self.calc.model.handle, C.byref(self.calc.sysd.struct()), C.byref(self.calc.nl.struct()),
+                    C.byref(self.state), n_steps, C.byref(self.calc.ws.ws), C.c_void_p(self.stream.cuda_stream)))
+            torch.cuda.current_stream(dev).wait_stream(self.stream)
+        else:
+            with torch.cuda.device(dev):
+                check("afm_md_step", load().afm_md_step(
+                    self.calc.model.handle, C.byref(self.calc.sysd.struct()), C.byref(self.calc.nl.struct()),
+                    C.byref(self.state), n_steps, C.byref(self.calc.ws.ws), _stream_ptr(dev)))
+        return log.clone()

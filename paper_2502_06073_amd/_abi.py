@@ -47,10 +47,15 @@ class Workspace(C.Structure):
                 ("with_second_order", C.c_int32)]
 
 
+class TraceStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("total_ms", C.c_double)]
+
+
 class MdState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("forces", C.c_void_p),
                 ("mass_by_species", C.c_void_p), ("dt_fs", C.c_double), ("skin", C.c_double),
-                ("rebuild_every", C.c_int32), ("step", C.c_int64), ("energy_log", C.c_void_p),
+                ("rebuild_every", C.c_int32), ("use_graph", C.c_int32), ("step", C.c_int64),
+                ("energy_log", C.c_void_p),
                 ("e_atom", C.c_void_p), ("e_struct", C.c_void_p)]
 
 
@@ -76,6 +81,8 @@ EXPORTS = {
                                      C.c_void_p],
     "afm_md_step": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(MdState), C.c_int32,
                     C.POINTER(Workspace), C.c_void_p],
+    "afm_trace_enable": [C.c_int32],
+    "afm_trace_read": [C.POINTER(TraceStat), C.c_int32, C.POINTER(C.c_int32)],
     "afm_strerror": [C.c_int],
     "afm_last_error": [],
     "afm_version": [],

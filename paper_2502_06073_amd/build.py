@@ -23,7 +23,7 @@ OUT = os.path.join(HERE, "libafm.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["model.cpp", "weights.cpp", "api.cpp", "neighbors.hip", "forward.hip",
+SOURCES = ["model.cpp", "weights.cpp", "api.cpp", "trace.cpp", "neighbors.hip", "forward.hip",
            "tp_kernels.hip", "mfma_chain.hip", "md.hip", "second_order.hip"]
 
 FLAGS = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}",

@@ -7,9 +7,6 @@
 
 namespace afm {
 
-int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
-                 hipStream_t st);   // chunks.hip
-
 static int check_sys(const afm_system* sys, const afm_workspace* ws, SysDev* out) {
   if (!sys || !ws) { set_error("null system or workspace"); return AFM_E_INVALID; }
   if (!sys->pos || !sys->species || !sys->cell || !sys->pbc || !sys->seg) {
@@ -39,6 +36,21 @@ static int check_model(const afm_model* m, const afm_workspace* ws, WsLayout* L)
   *L = workspace_layout(m, ws);
   if (ws->bytes < L->total) { set_error("workspace smaller than its plan"); return AFM_E_CAPACITY; }
   return AFM_OK;
+}
+
+// energies, forces and virial for already-checked arguments (also used by md.hip)
+int api_energy_forces_dev(const afm_model* m, const SysDev& s, const NlDev& n, double* e_atom, double* e_struct,
+                          double* forces, double* virial, const afm_workspace* ws, const WsLayout& L,
+                          hipStream_t st) {
+  int rc = launch_chunk_rows(s, n, ws, L, st);
+  if (!rc) rc = check_chunks(s, n, ws, L, st);
+  for (int c = 0; !rc && c < ws->n_chunks; ++c) {
+    rc = run_forward_chunk(m, s, n, ws, L, c, st);
+    if (!rc) rc = run_backward_chunk(m, s, n, ws, L, c, nullptr, st);
+  }
+  if (!rc) rc = run_atom_energy(m, s, n, ws, L, e_atom, e_struct, st);
+  if (!rc && (forces || virial)) rc = run_force_scatter(m, s, n, ws, L, forces, virial, st);
+  return rc;
 }
 
 }  // namespace afm
@@ -108,16 +120,7 @@ int afm_energy_forces(const afm_model* m, const afm_system* sys, const afm_nlist
   if (!rc) rc = check_model(m, ws, &L);
   if (rc) return rc;
   if (!e_atom) { set_error("e_atom is required"); return AFM_E_INVALID; }
-  hipStream_t st = (hipStream_t)stream;
-  rc = launch_chunk_rows(s, n, ws, L, st);
-  if (!rc) rc = check_chunks(s, n, ws, L, st);
-  for (int c = 0; !rc && c < ws->n_chunks; ++c) {
-    rc = run_forward_chunk(m, s, n, ws, L, c, st);
-    if (!rc) rc = run_backward_chunk(m, s, n, ws, L, c, nullptr, st);
-  }
-  if (!rc) rc = run_atom_energy(m, s, n, ws, L, e_atom, e_struct, st);
-  if (!rc && (forces || virial)) rc = run_force_scatter(m, s, n, ws, L, forces, virial, st);
-  return rc;
+  return api_energy_forces_dev(m, s, n, e_atom, e_struct, forces, virial, ws, L, (hipStream_t)stream);
 }
 
 int afm_backward_forces_backward(const afm_model* m, const afm_system* sys, const afm_nlist* nl,
@@ -131,9 +134,24 @@ int afm_backward_forces_backward(const afm_model* m, const afm_system* sys, cons
 
 int afm_md_step(const afm_model* m, const afm_system* sys, afm_nlist* nl, afm_md_state* state, int32_t n_steps,
                 const afm_workspace* ws, void* stream) {
-  (void)m; (void)sys; (void)nl; (void)state; (void)n_steps; (void)ws; (void)stream;
-  set_error("md_step not built yet");
-  return AFM_E_UNSUPPORTED;
+  SysDev s{};
+  NlDev n{};
+  WsLayout L{};
+  int rc = check_sys(sys, ws, &s);
+  if (!rc) rc = check_nl(nl, ws, &n);
+  if (!rc) rc = check_model(m, ws, &L);
+  if (rc) return rc;
+  if (!state || !state->pos || !state->vel || !state->forces || !state->mass_by_species || !state->energy_log ||
+      !state->e_atom || !state->e_struct) {
+    set_error("null MD state array");
+    return AFM_E_INVALID;
+  }
+  if (n_steps < 0 || !(state->dt_fs > 0) || !(state->skin >= 0) || state->rebuild_every < 0 || state->step < 0) {
+    set_error("bad MD parameters");
+    return AFM_E_INVALID;
+  }
+  s.pos = state->pos;
+  return md_step(m, s, n, state, n_steps, ws, L, (hipStream_t)stream);
 }
 
 }  // extern "C"

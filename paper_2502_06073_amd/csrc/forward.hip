@@ -15,12 +15,13 @@
 #include "device_util.h"
 #include "gemm_f32.h"
 #include "internal.h"
+#include "trace.h"
 
 namespace afm {
 
 // BF16 MFMA chains (mfma_chain.hip)
 int mfma_twobody_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
-                     const int32_t* species, hipStream_t st);
+                     const int32_t* species, const int32_t* col, hipStream_t st);
 int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer,
                     hipStream_t st);
 int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer,
@@ -444,14 +445,20 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
   const int64_t E = L.cex;
   float* geo = ws_ptr<float>(ws, L.geo);
   int32_t* eidx = ws_ptr<int32_t>(ws, L.eidx);
-  hipLaunchKernelGGL(k_geometry, dim3(grid_for(E, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
-                     s.seg, s.B, (const int32_t*)nl.col, (const int8_t*)nl.shift, (float)d.r_cut, d.p, eidx, geo);
-  AFM_LAUNCH_CHECK();
   const int cw = (d.lmax + 1) * d.c;
+  {
+    TraceScope tr(st, "geometry");
+    hipLaunchKernelGGL(k_geometry, dim3(grid_for(E, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
+                       s.seg, s.B, (const int32_t*)nl.col, (const int8_t*)nl.shift, (float)d.r_cut, d.p, eidx,
+                       geo);
+    AFM_LAUNCH_CHECK();
+  }
   if (m->prec == AFM_BF16_MFMA) {
-    int rc = mfma_twobody_fwd(m, ws, L, rr, s.species, st);
+    TraceScope tr(st, "twobody_fwd");
+    int rc = mfma_twobody_fwd(m, ws, L, rr, s.species, nl.col, st);
     if (rc) return rc;
   } else {
+    TraceScope tr(st, "twobody_fwd");
     float* pre0 = ws_ptr<float>(ws, L.tb_pre[0]);
     hipLaunchKernelGGL(k_twobody_first, dim3(grid_for(E, 64)), dim3(256), 0, st, rr, (const int32_t*)eidx,
                        (const int32_t*)nl.col, s.species, (const float*)geo, m->W.tb[0], d.S, d.nb, d.tb[0],
@@ -472,11 +479,15 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
     AFM_LAUNCH_CHECK();
   }
   for (int layer = 1; layer <= d.NL; ++layer) {
-    TPArgs ta = tp_args(m, ws, L, rr, layer);
-    int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, ta, s.N, st);
-    if (rc) return rc;
+    {
+      TraceScope tr(st, "tp_fwd", layer);
+      TPArgs ta = tp_args(m, ws, L, rr, layer);
+      int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, ta, s.N, st);
+      if (rc) return rc;
+    }
+    TraceScope tr(st, "latent_fwd", layer);
     if (m->prec == AFM_BF16_MFMA) {
-      rc = mfma_latent_fwd(m, ws, L, rr, layer, st);
+      int rc = mfma_latent_fwd(m, ws, L, rr, layer, st);
       if (rc) return rc;
       continue;
     }
@@ -532,37 +543,41 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
   for (int layer = d.NL; layer >= 1; --layer) {
     const LayerPlan& lp = P.layer[layer - 1];
     const int ls = lp.n0e * d.c;
-    if (m->prec == AFM_BF16_MFMA) {
-      rc = mfma_latent_bwd(m, ws, L, rr, layer, s.species, s.seg, s.B, grad_e_struct, st);
-      if (rc) return rc;
-    } else {
-      if (layer == d.NL) {
-        hipLaunchKernelGGL(k_gx_init, dim3(grid_for(E * d.w, 256, 65536)), dim3(256), 0, st, rr,
-                           (const int32_t*)eidx, s.species, s.seg, s.B, grad_e_struct, m->W.sp_scale, d.S,
-                           d.escale, m->W.w_eff, d.w, gx);
+    {
+      TraceScope tr(st, "latent_bwd", layer);
+      if (m->prec == AFM_BF16_MFMA) {
+        rc = mfma_latent_bwd(m, ws, L, rr, layer, s.species, s.seg, s.B, grad_e_struct, st);
+        if (rc) return rc;
       } else {
-        // dE/dx^L += dE/domega^{L+1} W_env^{L+1}
-        sgemm<false>(st, rr, E, cw, d.w, m->W.env[layer], d.w, LoadPlain{ws_ptr<float>(ws, L.gomega), cw},
-                     EpAdd{gx, d.w});
+        if (layer == d.NL) {
+          hipLaunchKernelGGL(k_gx_init, dim3(grid_for(E * d.w, 256, 65536)), dim3(256), 0, st, rr,
+                             (const int32_t*)eidx, s.species, s.seg, s.B, grad_e_struct, m->W.sp_scale, d.S,
+                             d.escale, m->W.w_eff, d.w, gx);
+        } else {
+          // dE/dx^L += dE/domega^{L+1} W_env^{L+1}
+          sgemm<false>(st, rr, E, cw, d.w, m->W.env[layer], d.w, LoadPlain{ws_ptr<float>(ws, L.gomega), cw},
+                       EpAdd{gx, d.w});
+        }
+        AFM_LAUNCH_CHECK();
+        // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2
+        const float r2 = 0.70710678118654752f;
+        float* ga = gt0;
+        hipLaunchKernelGGL(k_mlp_head_bwd, dim3(grid_for(E, 4, 16384)), dim3(256), 0, st, rr, d.w,
+                           (const float*)ws_ptr<float>(ws, L.lat_pre[layer - 1][d.depth - 1]), (const float*)geo,
+                           r2, r2, gx, ga, gy);
+        AFM_LAUNCH_CHECK();
+        for (int k = d.depth - 1; k >= 1; --k) {
+          float* gnext = (ga == gt0) ? gt1 : gt0;
+          sgemm<false>(st, rr, E, d.w, d.w, m->W.lat[layer - 1][k], d.w, LoadPlain{ga, d.w},
+                       EpDsilu{ws_ptr<float>(ws, L.lat_pre[layer - 1][k - 1]), gnext, d.w});
+          ga = gnext;
+        }
+        sgemm<false>(st, rr, E, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LoadPlain{ga, d.w},
+                     EpSplit{gx, d.w, ws_ptr<float>(ws, L.gs), ls});
+        AFM_LAUNCH_CHECK();
       }
-      AFM_LAUNCH_CHECK();
-      // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2
-      const float r2 = 0.70710678118654752f;
-      float* ga = gt0;
-      hipLaunchKernelGGL(k_mlp_head_bwd, dim3(grid_for(E, 4, 16384)), dim3(256), 0, st, rr, d.w,
-                         (const float*)ws_ptr<float>(ws, L.lat_pre[layer - 1][d.depth - 1]), (const float*)geo, r2,
-                         r2, gx, ga, gy);
-      AFM_LAUNCH_CHECK();
-      for (int k = d.depth - 1; k >= 1; --k) {
-        float* gnext = (ga == gt0) ? gt1 : gt0;
-        sgemm<false>(st, rr, E, d.w, d.w, m->W.lat[layer - 1][k], d.w, LoadPlain{ga, d.w},
-                     EpDsilu{ws_ptr<float>(ws, L.lat_pre[layer - 1][k - 1]), gnext, d.w});
-        ga = gnext;
-      }
-      sgemm<false>(st, rr, E, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LoadPlain{ga, d.w},
-                   EpSplit{gx, d.w, ws_ptr<float>(ws, L.gs), ls});
-      AFM_LAUNCH_CHECK();
     }
+    TraceScope tr(st, "tp_bwd", layer);
     TPArgs ta = tp_args(m, ws, L, rr, layer);
     ta.gs = ws_ptr<float>(ws, L.gs);
     float* gva = ws_ptr<float>(ws, L.gv0);
@@ -574,27 +589,32 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
     if (rc) return rc;
   }
   // two-body: dE/dx^0 += dE/domega^1 W_env^1, then the MLP adjoint
-  if (m->prec == AFM_BF16_MFMA) {
-    rc = mfma_twobody_bwd(m, ws, L, rr, s.species, st);
-    if (rc) return rc;
-  } else {
-    sgemm<false>(st, rr, E, cw, d.w, m->W.env[0], d.w, LoadPlain{ws_ptr<float>(ws, L.gomega), cw}, EpAdd{gx, d.w});
-    const int F = d.tb[d.ntb - 1];
-    float* ga = gt0;
-    hipLaunchKernelGGL(k_mlp_head_bwd, dim3(grid_for(E, 4, 16384)), dim3(256), 0, st, rr, F,
-                       (const float*)ws_ptr<float>(ws, L.tb_pre[d.ntb - 1]), (const float*)geo, 1.0f, 0.0f, gx, ga,
-                       gy);
-    for (int k = d.ntb - 1; k >= 1; --k) {
-      float* gnext = (ga == gt0) ? gt1 : gt0;
-      sgemm<false>(st, rr, E, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LoadPlain{ga, d.tb[k]},
-                   EpDsilu{ws_ptr<float>(ws, L.tb_pre[k - 1]), gnext, d.tb[k - 1]});
-      ga = gnext;
+  {
+    TraceScope tr(st, "twobody_bwd");
+    if (m->prec == AFM_BF16_MFMA) {
+      rc = mfma_twobody_bwd(m, ws, L, rr, s.species, st);
+      if (rc) return rc;
+    } else {
+      sgemm<false>(st, rr, E, cw, d.w, m->W.env[0], d.w, LoadPlain{ws_ptr<float>(ws, L.gomega), cw},
+                   EpAdd{gx, d.w});
+      const int F = d.tb[d.ntb - 1];
+      float* ga = gt0;
+      hipLaunchKernelGGL(k_mlp_head_bwd, dim3(grid_for(E, 4, 16384)), dim3(256), 0, st, rr, F,
+                         (const float*)ws_ptr<float>(ws, L.tb_pre[d.ntb - 1]), (const float*)geo, 1.0f, 0.0f, gx,
+                         ga, gy);
+      for (int k = d.ntb - 1; k >= 1; --k) {
+        float* gnext = (ga == gt0) ? gt1 : gt0;
+        sgemm<false>(st, rr, E, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LoadPlain{ga, d.tb[k]},
+                     EpDsilu{ws_ptr<float>(ws, L.tb_pre[k - 1]), gnext, d.tb[k - 1]});
+        ga = gnext;
+      }
+      // dE/drho_n = sum_f ga[f] W_0[f][2S + n]
+      sgemm<false>(st, rr, E, d.tb[0], d.nb, m->W.tb[0] + 2 * d.S, 2 * d.S + d.nb, LoadPlain{ga, d.tb[0]},
+                   EpStore{ws_ptr<float>(ws, L.grho), 16});
+      AFM_LAUNCH_CHECK();
     }
-    // dE/drho_n = sum_f ga[f] W_0[f][2S + n]
-    sgemm<false>(st, rr, E, d.tb[0], d.nb, m->W.tb[0] + 2 * d.S, 2 * d.S + d.nb, LoadPlain{ga, d.tb[0]},
-                 EpStore{ws_ptr<float>(ws, L.grho), 16});
-    AFM_LAUNCH_CHECK();
   }
+  TraceScope tr(st, "geometry_bwd");
   hipLaunchKernelGGL(k_geometry_bwd, dim3(grid_for(E, 256, 65536)), dim3(256), 0, st, rr, (const float*)geo,
                      (const float*)ws_ptr<float>(ws, L.grho), (const float*)gy, d.nb, (float)d.r_cut, d.p,
                      ws_ptr<float>(ws, L.g));
@@ -604,6 +624,7 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
 
 int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                     const WsLayout& L, double* e_atom, double* e_struct, hipStream_t st) {
+  TraceScope tr(st, "energy");
   hipLaunchKernelGGL(k_atom_energy, dim3(grid_for(s.N, 256)), dim3(256), 0, st, (const int64_t*)nl.row_ptr, s.N,
                      nl.capacity, (const float*)ws_ptr<float>(ws, L.eps), s.species, m->dims.S, m->W.sp_scale,
                      m->W.sp_shift, m->dims.escale, e_atom, nl.status);
@@ -616,6 +637,7 @@ int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl, const 
 
 int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                       const WsLayout& L, double* forces, double* virial, hipStream_t st) {
+  TraceScope tr(st, "force_scatter");
   double* wat = virial ? ws_ptr<double>(ws, L.atom_virial) : nullptr;
   hipLaunchKernelGGL(k_force_scatter, dim3(grid_for(s.N, 128)), dim3(128), 0, st, s.pos, s.cell, s.pbc, s.seg,
                      s.B, (const int64_t*)nl.row_ptr, s.N, (const int32_t*)nl.col, (const int8_t*)nl.shift,

@@ -50,8 +50,7 @@ struct DevWeights {
   const double* sp_shift = nullptr;            // [S]
   // BF16 MFMA fragment-packed copies (see mfma_chain.hip); null for FP32
   const void* frag = nullptr;
-  int64_t frag_off_fwd[kMaxLayers + 1][kMaxDepth + 1] = {};
-  int64_t frag_off_bwd[kMaxLayers + 1][kMaxDepth + 1] = {};
+  int64_t frag_off[64] = {};   // byte offsets of the packed matrices in `frag`
 };
 
 struct ModelDims {
@@ -92,6 +91,8 @@ struct WsLayout {
   int64_t gamma[kMaxLayers] = {};  // float [N][n_lm][c]
   int64_t eps = 0;             // float [capacity] edge energies
   int64_t atom_virial = 0;     // double [N][9]
+  int64_t md_ref = 0;          // double [N][3] positions at the last rebuild
+  int64_t md_ke = 0;           // double [ceil(N/256)] kinetic-energy partials
   // per-chunk edge buffers (CEX edges)
   int64_t cex = 0;
   int64_t eidx = 0;            // int32 [CEX] central atom of each local edge
@@ -159,6 +160,11 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl,
 int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl,
                     const afm_workspace* ws, const WsLayout& L, double* e_atom,
                     double* e_struct, hipStream_t st);
+int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* state, int32_t n_steps,
+            const afm_workspace* ws, const WsLayout& L, hipStream_t st);   // md.hip
+int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
+                 hipStream_t st);                                          // neighbors.hip
+
 int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl,
                       const afm_workspace* ws, const WsLayout& L, double* forces,
                       double* virial, hipStream_t st);

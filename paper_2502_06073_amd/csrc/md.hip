@@ -1,0 +1,224 @@
+// NVE molecular dynamics step (Methodology: MD with a 0.5 fs time step).
+// Velocity Verlet in float64:
+//   v += dt/2 F/m k_acc;  r += dt v;
+//   [k % rebuild_every == 0: wrap periodic atoms by whole lattice shifts,
+//    rebuild the edge list at r_cut + skin];
+//   F = F(r);  v += dt/2 F/m k_acc;  log (KE, PE)
+// with k_acc = 9.648533212e-3 A fs^-2 per (eV A^-1 amu^-1).  An atom that
+// moved more than skin/2 since the last rebuild sets AFM_FLAG_SKIN.  The
+// kinetic energy is reduced in a fixed order (per-block partials, then one
+// block), so trajectories are bitwise reproducible.  Optionally the n-step
+// sequence is captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "device_util.h"
+#include "internal.h"
+#include "trace.h"
+
+namespace afm {
+
+constexpr double kAcc = 9.648533212e-3;
+constexpr int kMdBlock = 256;
+
+__global__ void k_md_kick_drift(double* __restrict__ pos, double* __restrict__ vel,
+                                const double* __restrict__ F, const int32_t* __restrict__ species,
+                                const double* __restrict__ mass, int S, int64_t N, double dt,
+                                const double* __restrict__ ref, double half_skin2, int32_t* status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double inv_m = kAcc / mass[min(max(species[i], 0), S - 1)];
+  double d2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double v = vel[3 * i + q] + 0.5 * dt * F[3 * i + q] * inv_m;
+    vel[3 * i + q] = v;
+    const double r = pos[3 * i + q] + dt * v;
+    pos[3 * i + q] = r;
+    const double dd = r - ref[3 * i + q];
+    d2 += dd * dd;
+  }
+  if (d2 > half_skin2) atomicOr(status, AFM_FLAG_SKIN);
+}
+
+__global__ void __launch_bounds__(kMdBlock) k_md_kick(double* __restrict__ vel, const double* __restrict__ F,
+                                                       const int32_t* __restrict__ species,
+                                                       const double* __restrict__ mass, int S, int64_t N, double dt,
+                                                       double* __restrict__ ke_part) {
+  __shared__ double part[kMdBlock];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double ke = 0.0;
+  if (i < N) {
+    const double m = mass[min(max(species[i], 0), S - 1)];
+    const double inv_m = kAcc / m;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double v = vel[3 * i + q] + 0.5 * dt * F[3 * i + q] * inv_m;
+      vel[3 * i + q] = v;
+      ke += 0.5 * m * v * v / kAcc;
+    }
+  }
+  part[threadIdx.x] = ke;
+  __syncthreads();
+  for (int off = kMdBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ke_part[blockIdx.x] = part[0];
+}
+
+__global__ void __launch_bounds__(256) k_md_log(const double* __restrict__ ke_part, int64_t nb,
+                                                 const double* __restrict__ e_struct, int64_t B,
+                                                 double* __restrict__ log2) {
+  __shared__ double pa[256], pb[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t k = threadIdx.x; k < nb; k += 256) a += ke_part[k];
+  for (int64_t k = threadIdx.x; k < B; k += 256) b += e_struct[k];
+  pa[threadIdx.x] = a;
+  pb[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      pa[threadIdx.x] += pa[threadIdx.x + off];
+      pb[threadIdx.x] += pb[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    log2[0] = pa[0];
+    log2[1] = pb[0];
+  }
+}
+
+// r' = r - ((n0 a + n1 b) + n2 c), n = floor(frac(r)), only where n != 0
+__global__ void k_md_wrap(double* __restrict__ pos, const double* __restrict__ cell,
+                          const uint8_t* __restrict__ pbc, const int64_t* __restrict__ seg, int64_t B, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int64_t lo = 0, hi = B;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (seg[mid] <= i) lo = mid; else hi = mid;
+  }
+  if (!pbc[lo]) return;
+  const double* h = cell + 9 * lo;
+  const double a[3] = {h[0], h[1], h[2]}, b[3] = {h[3], h[4], h[5]}, c[3] = {h[6], h[7], h[8]};
+  const double bxc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+  const double cxa[3] = {c[1] * a[2] - c[2] * a[1], c[2] * a[0] - c[0] * a[2], c[0] * a[1] - c[1] * a[0]};
+  const double axb[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  const double det = a[0] * bxc[0] + a[1] * bxc[1] + a[2] * bxc[2];
+  if (!(fabs(det) > 1e-12)) return;
+  const double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  double n[3];
+  n[0] = floor((r[0] * bxc[0] + r[1] * bxc[1] + r[2] * bxc[2]) / det);
+  n[1] = floor((r[0] * cxa[0] + r[1] * cxa[1] + r[2] * cxa[2]) / det);
+  n[2] = floor((r[0] * axb[0] + r[1] * axb[1] + r[2] * axb[2]) / det);
+  if (n[0] == 0.0 && n[1] == 0.0 && n[2] == 0.0) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double s = __dadd_rn(__dadd_rn(__dmul_rn(n[0], h[q]), __dmul_rn(n[1], h[3 + q])), __dmul_rn(n[2], h[6 + q]));
+    pos[3 * i + q] = __dsub_rn(r[q], s);
+  }
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    b[q] = a[q];
+}
+
+int api_energy_forces_dev(const afm_model* m, const SysDev& s, const NlDev& n, double* e_atom, double* e_struct,
+                          double* forces, double* virial, const afm_workspace* ws, const WsLayout& L,
+                          hipStream_t st);
+
+static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, const afm_md_state* state,
+                       int32_t n_steps, const afm_workspace* ws, const WsLayout& L, hipStream_t st) {
+  const int64_t N = s.N;
+  const unsigned gb = grid_for(N, kMdBlock);
+  double* ref = ws_ptr<double>(ws, L.md_ref);
+  double* ke_part = ws_ptr<double>(ws, L.md_ke);
+  const double r_list = m->dims.r_cut + state->skin;
+  const double hs2 = 0.25 * state->skin * state->skin;
+  if (state->step == 0) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(3 * N, 256, 4096)), dim3(256), 0, st, (const double*)state->pos,
+                       ref, 3 * N);
+  }
+  for (int32_t t = 0; t < n_steps; ++t) {
+    const int64_t k = state->step + t + 1;
+    hipLaunchKernelGGL(k_md_kick_drift, dim3(gb), dim3(kMdBlock), 0, st, state->pos, state->vel,
+                       (const double*)state->forces, s.species, state->mass_by_species, m->dims.S, N, state->dt_fs,
+                       (const double*)ref, hs2, n.status);
+    AFM_LAUNCH_CHECK();
+    if (state->rebuild_every > 0 && k % state->rebuild_every == 0) {
+      hipLaunchKernelGGL(k_md_wrap, dim3(gb), dim3(256), 0, st, state->pos, s.cell, s.pbc, s.seg, s.B, N);
+      int rc = launch_build_neighbors(s, r_list, n, ws, L, kMaxSpecies * 1024, st);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(3 * N, 256, 4096)), dim3(256), 0, st,
+                         (const double*)state->pos, ref, 3 * N);
+    }
+    int rc = api_energy_forces_dev(m, s, n, state->e_atom, state->e_struct, state->forces, nullptr, ws, L, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_md_kick, dim3(gb), dim3(kMdBlock), 0, st, state->vel, (const double*)state->forces,
+                       s.species, state->mass_by_species, m->dims.S, N, state->dt_fs, ke_part);
+    hipLaunchKernelGGL(k_md_log, dim3(1), dim3(256), 0, st, (const double*)ke_part, (int64_t)gb,
+                       (const double*)state->e_struct, s.B, state->energy_log + 2 * (int64_t)t);
+    AFM_LAUNCH_CHECK();
+  }
+  return AFM_OK;
+}
+
+// cached graphs keyed by every pointer and size the captured sequence uses
+typedef std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*,
+                   int64_t, int32_t, int64_t, hipStream_t>
+    GraphKey;
+static std::mutex g_graph_mu;
+static std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* state, int32_t n_steps,
+            const afm_workspace* ws, const WsLayout& L, hipStream_t st) {
+  TraceScope tr(st, "md_step");
+  if (!state->use_graph || trace_on()) {
+    int rc = md_sequence(m, s, n, state, n_steps, ws, L, st);
+    if (!rc) state->step += n_steps;
+    return rc;
+  }
+  if (state->step == 0 || !st) {
+    // the reference capture at step 0 and the null stream are not captured
+    int rc = md_sequence(m, s, n, state, n_steps, ws, L, st);
+    if (!rc) state->step += n_steps;
+    return rc;
+  }
+  const int64_t phase = state->rebuild_every > 0 ? state->step % state->rebuild_every : 0;
+  GraphKey key{m, ws->ptr, state->pos, state->vel, state->forces, state->energy_log, n.row_ptr, phase, n_steps,
+               (int64_t)s.N, st};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    AFM_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = md_sequence(m, s, n, state, n_steps, ws, L, st);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) { set_error(std::string("capture: ") + hipGetErrorString(e)); return AFM_E_HIP; }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { set_error(std::string("graph instantiate: ") + hipGetErrorString(e)); return AFM_E_HIP; }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graphs[key] = exec;
+  }
+  AFM_HIP_CHECK(hipGraphLaunch(exec, st));
+  state->step += n_steps;
+  return AFM_OK;
+}
+
+}  // namespace afm

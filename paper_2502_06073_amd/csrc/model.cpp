@@ -233,7 +233,10 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   for (int l = 0; l < d.NL; ++l) L.gamma[l] = take(N * d.n_lm * d.c * 4);
   L.eps = take(cap * 4);
   L.atom_virial = take(N * 72);
-  const int64_t E = ws->n_chunks > 1 ? ws->chunk_edges + ws->max_row : cap;
+  L.md_ref = take(N * 24);
+  L.md_ke = take(((N + 255) / 256 + 1) * 8);
+  // per-chunk edge buffers hold whole 256-edge tiles
+  const int64_t E = ((ws->n_chunks > 1 ? ws->chunk_edges + ws->max_row : cap) + 255) / 256 * 256;
   L.cex = E;
   int maxcomp = 1, maxn0 = 1;
   for (int l = 0; l < d.NL; ++l) {

@@ -20,6 +20,8 @@
 #include <math.h>
 
 #include "internal.h"
+#include "trace.h"
+#include "device_util.h"
 
 namespace afm {
 
@@ -447,7 +449,9 @@ int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, cons
   int64_t* counts = ws_ptr<int64_t>(ws, L.nb_counts);
   int64_t* sums = ws_ptr<int64_t>(ws, L.nb_scan);
   const double r2 = r_list * r_list;
-  AFM_HIP_CHECK(hipMemsetAsync(bcount, 0, (L.n_bins_max + 1) * 4, st));
+  TraceScope tr(st, "neighbors");
+  int rc0 = zero_async(bcount, (L.n_bins_max + 1) * 4, st);
+  if (rc0) return rc0;
   hipLaunchKernelGGL(k_struct_prep, dim3(nblk(B, 64)), dim3(64), 0, st, s.cell, s.pbc, s.seg, B, r_list,
                      meta, nl.status);
   hipLaunchKernelGGL(k_bin_offsets, dim3(1), dim3(1), 0, st, meta, B);
@@ -458,7 +462,8 @@ int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, cons
   int rc = exclusive_scan<int32_t>(bcount, bstart, L.n_bins_max + 1, reinterpret_cast<int32_t*>(sums), st);
   if (rc) return rc;
   // bcount becomes the fill cursor
-  AFM_HIP_CHECK(hipMemsetAsync(bcount, 0, (L.n_bins_max + 1) * 4, st));
+  rc = zero_async(bcount, (L.n_bins_max + 1) * 4, st);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_bin_fill, dim3(nblk(N, 256)), dim3(256), 0, st, (const AtomMeta*)am, N,
                      (const int32_t*)bstart, bcount, batoms);
   AFM_LAUNCH_CHECK();

@@ -9,9 +9,8 @@
 #include "internal.h"
 
 namespace afm {
-int64_t bf16_frag_bytes(const afm_model* m);                       // mfma_chain.hip
-void pack_bf16_frags(const afm_model* m, const std::vector<const double*>& blk,
-                     std::vector<char>& out, DevWeights* W_offsets); // mfma_chain.hip
+void pack_bf16_frags(const afm_model* m, const double* w, std::vector<char>& out, DevWeights* Wd);  // mfma_chain.hip
+int mfma_check_shape(const afm_model* m);                                                         // mfma_chain.hip
 }
 
 namespace afm {
@@ -40,8 +39,10 @@ int pack_weights(afm_model* m, const double* w) {
     fix.push_back({dst, o});
   };
   char nm[32];
-  std::vector<const double*> blk;   // block pointers in layout order
-  for (auto& b : m->blocks) blk.push_back(w + b.offset);
+  if (m->prec == AFM_BF16_MFMA) {
+    int rc = mfma_check_shape(m);
+    if (rc) return rc;
+  }
 
   for (int k = 0; k < d.ntb; ++k) {
     snprintf(nm, sizeof nm, "twobody.%d", k);
@@ -91,7 +92,7 @@ int pack_weights(afm_model* m, const double* w) {
   int64_t frag_off = -1;
   if (m->prec == AFM_BF16_MFMA) {
     std::vector<char> frags;
-    pack_bf16_frags(m, blk, frags, &m->W);
+    pack_bf16_frags(m, w, frags, &m->W);
     frag_off = reserve((int64_t)frags.size());
     memcpy(host.data() + frag_off, frags.data(), frags.size());
   }
