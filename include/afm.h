@@ -227,8 +227,11 @@ int afm_energy_forces(const afm_model* model, const afm_system* sys, const afm_n
  * energy and force errors): given upstream grad_e_struct[n_struct] and
  * grad_forces[n_atoms,3] (device, float64), writes
  *   grad_weights[n_params] = d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i]
- * (device, float32, in the flat weight layout, overwritten).  Needs a
- * workspace planned with with_second_order = 1.  grad_pos must be NULL. */
+ * (device, float32, in the flat weight layout, overwritten).  A NULL
+ * grad_e_struct or grad_forces stands for zeros.  Needs a workspace planned
+ * with with_second_order = 1; runs in FP32 on the vector ALUs with FP64
+ * accumulation of the weight gradients (deterministic).  grad_pos must be
+ * NULL (position gradients are not built). */
 int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
                                  const afm_nlist* nl, const double* grad_e_struct,
                                  const double* grad_forces, float* grad_weights,

@@ -26,7 +26,7 @@ from ._abi import AfmError, check, load
 
 __all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
            "param_layout", "cg_real", "hparams_struct", "energy_and_forces", "AfmError",
-           "trace_enable", "trace_read"]
+           "trace_enable", "trace_read", "energy_forces_for_training", "MD"]
 
 
 def trace_enable(on: bool = True) -> None:
@@ -256,6 +256,13 @@ class Calculator:
     def status(self) -> int:
         return int(self.nl.status.item())
 
+    def model_n_params(self) -> int:
+        return int(sum(b["size"] for b in param_layout(self.model.hp)))
+
+    def forces_backward(self, grad_e_struct=None, grad_forces=None) -> torch.Tensor:
+        """Weight gradient of sum gE E + sum gF . F (needs second_order=True)."""
+        return _forces_backward(self, grad_e_struct, grad_forces)
+
     def _outs(self, forces: bool):
         dev = self.model.device
         N, B = self.sysd.n_atoms, self.sysd.n_struct
@@ -295,6 +302,44 @@ class Calculator:
                                                _ptr(W) if virial else None, C.byref(self.ws.ws),
                                                _stream_ptr(self.model.device)))
         return F, (W if virial else None)
+
+
+def _forces_backward(calc: "Calculator", grad_e_struct: Optional[torch.Tensor],
+                     grad_forces: Optional[torch.Tensor], pos: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """d/dtheta [sum gE E + sum gF . F] (float32, flat weight layout)."""
+    dev = calc.model.device
+    g = torch.empty(calc.model_n_params(), dtype=torch.float32, device=dev)
+    gE = None if grad_e_struct is None else grad_e_struct.to(torch.float64).contiguous()
+    gF = None if grad_forces is None else grad_forces.to(torch.float64).contiguous()
+    with torch.cuda.device(dev):
+        check("afm_backward_forces_backward",
+              calc.lib.afm_backward_forces_backward(calc.model.handle, C.byref(calc.sysd.struct(pos)),
+                                                    C.byref(calc.nl.struct()), _ptr(gE), _ptr(gF), _ptr(g), None,
+                                                    C.byref(calc.ws.ws), _stream_ptr(dev)))
+    return g
+
+
+class _ForceMatchFn(torch.autograd.Function):
+    """(E_s, F) as functions of a proxy weight tensor: the backward returns
+    the weight gradient of sum gE E + sum gF . F from the library's
+    second-order entry point (the weights themselves live in the model)."""
+
+    @staticmethod
+    def forward(ctx, theta, calc):
+        out = calc.energy_forces(virial=False)
+        ctx.calc = calc
+        return out["e_struct"], out["forces"]
+
+    @staticmethod
+    def backward(ctx, gE, gF):
+        g = _forces_backward(ctx.calc, gE, gF)
+        return g.to(torch.float64), None
+
+
+def energy_forces_for_training(calc: "Calculator", theta: torch.Tensor):
+    """E_s and F whose gradients flow to `theta` (a float64 tensor standing
+    for the model's weights; requires a calculator with second_order=True)."""
+    return _ForceMatchFn.apply(theta, calc)
 
 
 class _EnergyFn(torch.autograd.Function):

@@ -437,6 +437,15 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   return a;
 }
 
+int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
+                    RowRange rr, hipStream_t st) {
+  hipLaunchKernelGGL(k_geometry, dim3(grid_for(L.cex, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
+                     s.seg, s.B, (const int32_t*)nl.col, (const int8_t*)nl.shift, (float)m->dims.r_cut, m->dims.p,
+                     ws_ptr<int32_t>(ws, L.eidx), ws_ptr<float>(ws, L.geo));
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
 int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                       const WsLayout& L, int chunk, hipStream_t st) {
   const ModelDims& d = m->dims;

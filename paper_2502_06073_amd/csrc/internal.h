@@ -109,6 +109,25 @@ struct WsLayout {
   int64_t gy = 0;                            // float [CEX][16] (GY[9], Gu at [9])
   int64_t gomega = 0;                        // float [CEX][(lmax+1)c]
   int64_t grho = 0;                          // float [CEX][16]
+  // second order (stacked rows: primal [0, CEX), tangent [CEX, 2 CEX))
+  int64_t so_geo2 = 0;                                   // float [CEX][16]
+  int64_t so_tb_pre[kMaxTwobody] = {};                   // float [2CEX][tb_k]
+  int64_t so_x[kMaxLayers + 1] = {};                     // float [2CEX][w]
+  int64_t so_omega[kMaxLayers] = {};                     // float [2CEX][(lmax+1)c]
+  int64_t so_s[kMaxLayers] = {};                         // float [2CEX][n0e c]
+  int64_t so_v[kMaxLayers] = {};                         // float [2CEX][ncomp c]
+  int64_t so_lat_pre[kMaxLayers][kMaxDepth] = {};        // float [2CEX][w]
+  int64_t so_gammad[kMaxLayers] = {};                    // float [N][n_lm][c]
+  int64_t so_gx = 0, so_ga = 0, so_gh = 0;               // float [2CEX][wide]
+  int64_t so_gs = 0;                                     // float [2CEX][n0e c]
+  int64_t so_gv0 = 0, so_gv1 = 0;                        // float [2CEX][maxcomp c]
+  int64_t so_gomega = 0;                                 // float [2CEX][(lmax+1)c]
+  int64_t so_eps = 0, so_coef = 0;                       // float [2CEX]
+  int64_t so_partial = 0;                                // float [32][max |W|]
+  int64_t so_gacc = 0;                                   // double [n_params]
+  int64_t so_q = 0;                                      // double [w]
+  int64_t so_galpha[kMaxLayers] = {};                    // float [N][n_paths][c]
+  int64_t so_asig = 0, so_amu = 0;                       // double [N]
 };
 
 WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws);
@@ -121,7 +140,8 @@ inline T* ws_ptr(const afm_workspace* ws, int64_t off) {
 int pack_weights(afm_model* m, const double* w);   // weights.cpp
 
 // ---- kernel launchers (defined in the .hip files) ----
-int upload_cg_table(const float* host_table);   // tp_kernels.hip
+int upload_cg_table(const float* host_table);                // tp_kernels.hip
+int upload_cg_table_second_order(const float* host_table);   // second_order.hip
 
 struct SysDev {
   int64_t N, B;
@@ -164,6 +184,10 @@ int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* s
             const afm_workspace* ws, const WsLayout& L, hipStream_t st);   // md.hip
 int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
                  hipStream_t st);                                          // neighbors.hip
+
+int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
+                     const WsLayout& L, const double* gE, const double* gF, float* grad_out,
+                     hipStream_t st);                                      // second_order.hip
 
 int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl,
                       const afm_workspace* ws, const WsLayout& L, double* forces,

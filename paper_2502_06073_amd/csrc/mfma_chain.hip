@@ -175,7 +175,7 @@ template <int RB, int KB, int R0 = 0>
 __device__ __forceinline__ void gemm_reg(const uint4* __restrict__ W, const bf16x8 (&in)[KB][JW],
                                          f32x4 (&acc)[RB][JW], int lane) {
   zero(acc);
-#pragma unroll 2
+#pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {

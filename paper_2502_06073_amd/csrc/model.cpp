@@ -265,6 +265,40 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   L.gy = take(E * 64);
   L.gomega = take(E * (d.lmax + 1) * d.c * 4);
   L.grho = take(E * 64);
+  if (ws->with_second_order) {
+    const int64_t E2 = 2 * E;
+    const int envw = (d.lmax + 1) * d.c;
+    L.so_geo2 = take(E * 64);
+    for (int k = 0; k < d.ntb; ++k) L.so_tb_pre[k] = take(E2 * d.tb[k] * 4);
+    for (int l = 0; l <= d.NL; ++l) L.so_x[l] = take(E2 * d.w * 4);
+    for (int l = 0; l < d.NL; ++l) L.so_omega[l] = take(E2 * envw * 4);
+    for (int l = 0; l < d.NL; ++l) L.so_s[l] = take(E2 * (int64_t)P.layer[l].n0e * d.c * 4);
+    for (int l = 0; l + 1 < d.NL; ++l) L.so_v[l] = take(E2 * (int64_t)P.layer[l].n_out_comps * d.c * 4);
+    for (int l = 0; l < d.NL; ++l)
+      for (int k = 0; k < d.depth; ++k) L.so_lat_pre[l][k] = take(E2 * d.w * 4);
+    for (int l = 0; l < d.NL; ++l) L.so_gammad[l] = take(N * d.n_lm * d.c * 4);
+    L.so_gx = take(E2 * gwide * 4);
+    L.so_ga = take(E2 * gwide * 4);
+    L.so_gh = take(E2 * gwide * 4);
+    L.so_gs = take(E2 * (int64_t)maxn0 * d.c * 4);
+    L.so_gv0 = take(E2 * (int64_t)maxcomp * d.c * 4);
+    L.so_gv1 = take(E2 * (int64_t)maxcomp * d.c * 4);
+    L.so_gomega = take(E2 * envw * 4);
+    L.so_eps = take(E2 * 4);
+    L.so_coef = take(E2 * 4);
+    int64_t maxw = (int64_t)d.w * (d.w + maxn0 * d.c);
+    maxw = maxw > (int64_t)envw * d.w ? maxw : (int64_t)envw * d.w;
+    for (int k = 0; k < d.ntb; ++k) {
+      const int64_t in = k ? d.tb[k - 1] : 2 * d.S + d.nb;
+      maxw = maxw > in * d.tb[k] ? maxw : in * d.tb[k];
+    }
+    L.so_partial = take(32 * maxw * 4);
+    L.so_gacc = take(m->n_params * 8);
+    L.so_q = take((int64_t)d.w * 8);
+    for (int l = 0; l + 1 < d.NL; ++l) L.so_galpha[l] = take(N * (int64_t)P.layer[l].n_paths * d.c * 4);
+    L.so_asig = take(N * 8);
+    L.so_amu = take(N * 8);
+  }
   L.total = off;
   return L;
 }
@@ -351,6 +385,7 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
   if (rc) { if (m->dev_mem) (void)hipFree(m->dev_mem); delete m; return rc; }
   std::vector<float> cg = cg_table_f32();
   rc = upload_cg_table(cg.data());
+  if (!rc) rc = upload_cg_table_second_order(cg.data());
   if (rc) { (void)hipFree(m->dev_mem); delete m; return rc; }
   *out = m;
   return AFM_OK;
@@ -374,7 +409,7 @@ int afm_workspace_plan(const afm_model* m, int64_t n_atoms, int64_t n_struct, in
   if (!ws) { set_error("null argument"); return AFM_E_INVALID; }
   if (n_atoms < 0 || n_struct < 1 || edge_capacity < 0) { set_error("bad sizes"); return AFM_E_INVALID; }
   if (edge_capacity >= (int64_t(1) << 31)) { set_error("edge capacity must be < 2^31"); return AFM_E_INVALID; }
-  if (with_second_order) { set_error("second-order workspace not built yet"); return AFM_E_UNSUPPORTED; }
+  if (with_second_order && !m) { set_error("a second-order plan needs a model"); return AFM_E_INVALID; }
   afm_workspace w{};
   w.n_atoms = n_atoms; w.n_struct = n_struct; w.edge_capacity = edge_capacity;
   w.max_row = 1024;
@@ -386,12 +421,12 @@ int afm_workspace_plan(const afm_model* m, int64_t n_atoms, int64_t n_struct, in
   if (m && max_bytes > 0 && L.total > max_bytes) {
     // bytes that do not scale with the chunk
     afm_workspace w1 = w;
-    w1.n_chunks = 2; w1.chunk_edges = 1;
+    w1.n_chunks = 2; w1.chunk_edges = 1024;
     WsLayout L1 = workspace_layout(m, &w1);
-    w1.chunk_edges = 1 + 65536;
+    w1.chunk_edges = 1024 + 65536;
     WsLayout L2 = workspace_layout(m, &w1);
     double per_edge = double(L2.total - L1.total) / 65536.0;
-    double fixed = double(L1.total) - per_edge * (1 + w1.max_row);
+    double fixed = double(L1.total) - per_edge * (1024 + w1.max_row);
     int64_t ce = (int64_t)((double(max_bytes) - fixed) / per_edge) - w1.max_row - 1024;
     if (ce < 4096) { set_error("max_bytes too small for a chunk of 4096 edges"); return AFM_E_CAPACITY; }
     w.chunk_edges = ce;

@@ -1,0 +1,1024 @@
+// Backward of the force adjoint: weight gradients for force matching
+// (Methodology / Model Training: the loss combines energy and force errors,
+// so training needs d/dtheta of the forces).
+//
+// Objective J(theta) = sum_s gE_s E_s + sum_i gF_i . F_i.  With
+// F_i = -dE/dr_i this is J = sum_s gE_s E_s - Edot, where Edot is the
+// derivative of E along positions moving with velocity gF, i.e. along edge
+// tangents delta_dot_e = gF_j - gF_i.  The schedule is forward-over-reverse:
+// every network quantity z gets a tangent z_dot (stacked as extra rows under
+// the primal rows, so each GEMM serves both), then J is reversed with
+// respect to the weights through primal and tangent together.  Basis and
+// spherical harmonics (and their tangents) do not depend on the weights, so
+// no second derivatives of the geometry are needed.  Everything runs in FP32
+// on the vector ALUs; weight gradients are reduced in fixed-order slices and
+// accumulated in FP64 (deterministic).  Chunks of rows are exact (E_i and
+// Edot_i depend only on row i).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "device_util.h"
+#include "edge_layout.h"
+#include "gemm_f32.h"
+#include "internal.h"
+#include "trace.h"
+
+namespace afm {
+
+constexpr int kSlices = 32;
+
+__device__ __forceinline__ float sig_f(float a) { return 1.0f / (1.0f + expf(-a)); }
+__device__ __forceinline__ float d1silu(float a) {
+  const float s = sig_f(a);
+  return s * (1.0f + a * (1.0f - s));
+}
+// silu''(a) = s (1 - s) (2 + a (1 - 2 s))
+__device__ __forceinline__ float d2silu(float a) {
+  const float s = sig_f(a);
+  return s * (1.0f - s) * (2.0f + a * (1.0f - 2.0f * s));
+}
+
+__device__ __forceinline__ float env_f(float x, int p) {
+  if (x >= 1.0f) return 0.0f;
+  float xp = 1.0f;
+  for (int q = 0; q < p; ++q) xp *= x;
+  return 1.0f - 0.5f * (p + 1) * (p + 2) * xp + (float)(p * (p + 2)) * xp * x - 0.5f * p * (p + 1) * xp * x * x;
+}
+__device__ __forceinline__ float env_dx_f(float x, int p) {
+  if (x >= 1.0f) return 0.0f;
+  float xp = 1.0f;
+  for (int q = 0; q < p - 1; ++q) xp *= x;
+  return -0.5f * p * (p + 1) * (p + 2) * xp * (1.0f - x) * (1.0f - x);
+}
+
+// forward derivative of the 9 harmonics at unit u along w
+__device__ __forceinline__ void sh9_jvp(float x, float y, float z, const float* w, float* Yd) {
+  const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+  Yd[0] = 0.0f;
+  Yd[1] = s3 * w[1]; Yd[2] = s3 * w[2]; Yd[3] = s3 * w[0];
+  Yd[4] = s15 * (x * w[1] + y * w[0]);
+  Yd[5] = s15 * (y * w[2] + z * w[1]);
+  Yd[6] = s5h * 6.0f * z * w[2];
+  Yd[7] = s15 * (x * w[2] + z * w[0]);
+  Yd[8] = s15 * (x * w[0] - y * w[1]);
+}
+
+// tangent geometry: geo2[t] = (delta_dot[3], d_dot, u_dot, Y_dot[9], -, -)
+__global__ void k_geom2(RowRange rr, const float* __restrict__ geo, const int32_t* __restrict__ eidx,
+                        const int32_t* __restrict__ col, const double* __restrict__ gF, float r_cut, int p,
+                        float* __restrict__ geo2) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < e1 - e0; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = eidx[t], j = col[e0 + t];
+    float dd[3];
+    for (int q = 0; q < 3; ++q) dd[q] = gF ? (float)(gF[3 * j + q] - gF[3 * i + q]) : 0.0f;
+    const float* G = geo + t * GEO_STRIDE;
+    const float r = G[GEO_D];
+    float* o = geo2 + t * GEO_STRIDE;
+    if (r > 0.0f) {
+      const float inv = 1.0f / r;
+      const float u[3] = {G[0] * inv, G[1] * inv, G[2] * inv};
+      const float rd = u[0] * dd[0] + u[1] * dd[1] + u[2] * dd[2];
+      const float w[3] = {(dd[0] - u[0] * rd) * inv, (dd[1] - u[1] * rd) * inv, (dd[2] - u[2] * rd) * inv};
+      float Yd[9];
+      sh9_jvp(u[0], u[1], u[2], w, Yd);
+      o[0] = dd[0]; o[1] = dd[1]; o[2] = dd[2];
+      o[GEO_D] = rd;
+      o[GEO_U] = env_dx_f(r / r_cut, p) / r_cut * rd;
+      for (int q = 0; q < 9; ++q) o[GEO_Y + q] = Yd[q];
+    } else {
+      for (int q = 0; q < 14; ++q) o[q] = 0.0f;
+    }
+    o[14] = 0.0f; o[15] = 0.0f;
+  }
+}
+
+// rho_n and its tangent for edge t
+__device__ __forceinline__ void rho_pair(const float* G, const float* G2, float r_cut, int p, int n, float& rho,
+                                         float& rhod) {
+  const float r = G[GEO_D], u = G[GEO_U];
+  const float c = sqrtf(2.0f / r_cut);
+  const float k = (n + 1) * 3.14159265358979323846f / r_cut;
+  const float sn = sinf(k * r), cs = cosf(k * r);
+  const float B = c * sn / r;
+  const float dB = c * (k * cs / r - sn / (r * r));
+  const float du = env_dx_f(r / r_cut, p) / r_cut;
+  rho = B * u;
+  rhod = (dB * u + B * du) * G2[GEO_D];
+}
+
+// first two-body layer, primal rows t and tangent rows stack + t
+__global__ void k_tb2_first(RowRange rr, int stack, const float* __restrict__ geo, const float* __restrict__ geo2,
+                            const int32_t* __restrict__ eidx, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ species, const float* __restrict__ W, int S, int nb, int F,
+                            float r_cut, int p, float* __restrict__ pre) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const int K = 2 * S + nb;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+    const int zi = min(max(species[eidx[t]], 0), S - 1), zj = min(max(species[col[e0 + t]], 0), S - 1);
+    const float* w = W + (int64_t)f * K;
+    float a = w[zi] + w[S + zj], ad = 0.0f;
+    for (int n = 0; n < nb; ++n) {
+      float rho, rhod;
+      rho_pair(geo + t * GEO_STRIDE, geo2 + t * GEO_STRIDE, r_cut, p, n, rho, rhod);
+      a += w[2 * S + n] * rho;
+      ad += w[2 * S + n] * rhod;
+    }
+    pre[t * F + f] = a;
+    pre[(stack + t) * F + f] = ad;
+  }
+}
+
+// x0 = u silu(a), x0_dot = u_dot silu(a) + u silu'(a) a_dot
+__global__ void k_tb2_out(RowRange rr, int stack, int F, const float* __restrict__ pre,
+                          const float* __restrict__ geo, const float* __restrict__ geo2, float* __restrict__ x) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+    const float a = pre[t * F + f], ad = pre[(stack + t) * F + f];
+    const float u = geo[t * GEO_STRIDE + GEO_U], ud = geo2[t * GEO_STRIDE + GEO_U];
+    x[t * F + f] = u * a * sig_f(a);
+    x[(stack + t) * F + f] = ud * a * sig_f(a) + u * d1silu(a) * ad;
+  }
+}
+
+// x^L = (x^{L-1} + u silu(a)) / sqrt 2 and its tangent
+__global__ void k_lat2_out(RowRange rr, int stack, int F, const float* __restrict__ pre,
+                           const float* __restrict__ xprev, const float* __restrict__ geo,
+                           const float* __restrict__ geo2, float* __restrict__ x) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const float r2 = 0.70710678118654752f;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+    const float a = pre[t * F + f], ad = pre[(stack + t) * F + f];
+    const float u = geo[t * GEO_STRIDE + GEO_U], ud = geo2[t * GEO_STRIDE + GEO_U];
+    const float h = a * sig_f(a), hd = d1silu(a) * ad;
+    x[t * F + f] = (xprev[t * F + f] + u * h) * r2;
+    x[(stack + t) * F + f] = (xprev[(stack + t) * F + f] + ud * h + u * hd) * r2;
+  }
+}
+
+__device__ __forceinline__ int64_t struct_of(const int64_t* seg, int64_t B, int64_t i) {
+  int64_t lo = 0, hi = B;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (seg[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// eps, eps_dot, the initial adjoints of x^{N_L} and the coefficients used
+// for the edge-energy weight gradient
+__global__ void __launch_bounds__(256) k_energy2(RowRange rr, int stack, int w, const float* __restrict__ x,
+                                                 const float* __restrict__ w_eff, const int32_t* __restrict__ eidx,
+                                                 const int32_t* __restrict__ species, const double* __restrict__ sc,
+                                                 int S, double escale, const int64_t* __restrict__ seg, int64_t B,
+                                                 const double* __restrict__ gE, float* __restrict__ eps2,
+                                                 float* __restrict__ coef, float* __restrict__ gx) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const int lane = threadIdx.x & 63;
+  for (int64_t t = blockIdx.x * 4 + (threadIdx.x >> 6); t < M; t += (int64_t)gridDim.x * 4) {
+    const int64_t i = eidx[t];
+    const float cs = (float)(sc[min(max(species[i], 0), S - 1)] * escale);
+    const float ge = gE ? (float)gE[struct_of(seg, B, i)] : 0.0f;
+    float a = 0.0f, ad = 0.0f;
+    for (int f = lane; f < w; f += 64) {
+      a += w_eff[f] * x[t * w + f];
+      ad += w_eff[f] * x[(stack + t) * w + f];
+      gx[t * w + f] = ge * cs * w_eff[f];
+      gx[(stack + t) * w + f] = -cs * w_eff[f];
+    }
+    a = group_sum<64>(a);
+    ad = group_sum<64>(ad);
+    if (lane == 0) {
+      eps2[t] = a;
+      eps2[stack + t] = ad;
+      coef[t] = ge * cs;
+      coef[stack + t] = -cs;
+    }
+  }
+}
+
+// per-atom shares of the species-scale and species-shift gradients
+__global__ void k_atom2(RowRange rr, int stack, const float* __restrict__ eps2, const int32_t* __restrict__ species,
+                        int S, double escale, const int64_t* __restrict__ seg, int64_t B,
+                        const double* __restrict__ gE, double* __restrict__ a_sig, double* __restrict__ a_mu) {
+  const int64_t a0 = rr.chunk_rows[rr.chunk], a1 = rr.chunk_rows[rr.chunk + 1];
+  const int64_t e0 = rr.row_ptr[a0];
+  for (int64_t i = a0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a1; i += (int64_t)gridDim.x * blockDim.x) {
+    double se = 0.0, sd = 0.0;
+    for (int64_t e = rr.row_ptr[i]; e < rr.row_ptr[i + 1]; ++e) {
+      se += (double)eps2[e - e0];
+      sd += (double)eps2[stack + e - e0];
+    }
+    const double ge = gE ? gE[struct_of(seg, B, i)] : 0.0;
+    a_sig[i] = escale * (ge * se - sd);
+    a_mu[i] = ge;
+  }
+}
+
+// adjoint through an activation: given dJ/dh (rows t) and dJ/dh_dot
+// (rows stack + t) with h = silu(a), h_dot = silu'(a) a_dot:
+//   a_bar = h_bar silu'(a) + hd_bar silu''(a) a_dot;  ad_bar = hd_bar silu'(a)
+// head = 1: the input is the adjoint of y = s (x_prev + u h) with s = r2
+// (latent) or y = u h with no residual (two-body, res = 0); it then also
+// scales the residual share in place.
+__global__ void k_act2_bwd(RowRange rr, int stack, int F, const float* __restrict__ pre, float* __restrict__ gin,
+                           float* __restrict__ gout, const float* __restrict__ geo, const float* __restrict__ geo2,
+                           int head, float scale, float res) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+    const float a = pre[t * F + f], ad = pre[(stack + t) * F + f];
+    float hb = gin[t * F + f], hdb = gin[(stack + t) * F + f];
+    if (head) {
+      const float u = geo[t * GEO_STRIDE + GEO_U], ud = geo2[t * GEO_STRIDE + GEO_U];
+      const float xb = hb * scale, xdb = hdb * scale;
+      gin[t * F + f] = hb * res;
+      gin[(stack + t) * F + f] = hdb * res;
+      hb = u * xb + ud * xdb;
+      hdb = u * xdb;
+    }
+    gout[t * F + f] = hb * d1silu(a) + hdb * d2silu(a) * ad;
+    gout[(stack + t) * F + f] = hdb * d1silu(a);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// tensor products with tangents
+
+struct TP2Args {
+  RowRange rr;
+  int stack;
+  const float* geo;
+  const float* geo2;
+  const float* omega;    // stacked omega^L
+  const float* omega1;   // stacked omega^1
+  const float* vin;      // stacked V^{L-1}
+  float* vout;           // stacked V^L
+  float* s;              // stacked s^L
+  float* gamma;          // Gamma^L   [N][NLM][C]
+  float* gammad;         // Gamma_dot [N][NLM][C]
+  const float* alpha;
+  float inv_sqrt_nbar;
+  const float* gs;       // stacked dJ/ds
+  const float* gvout;    // stacked dJ/dV^L
+  float* gvin;           // stacked dJ/dV^{L-1}
+  float* gomega;         // stacked dJ/domega^L
+  float* galpha;         // [N][n_paths][C] per-atom alpha-gradient shares
+};
+
+// this translation unit's copy of the CG table (device symbols are per unit)
+__constant__ float c_cg[cg_table_size()];
+
+int upload_cg_table_second_order(const float* host_table) {
+  AFM_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_cg), host_table, sizeof(float) * cg_table_size(), 0,
+                                  hipMemcpyHostToDevice));
+  return AFM_OK;
+}
+
+template <int LMAX, int NL, int L>
+struct LayerCT2 {
+  static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
+};
+
+template <int LMAX, int NL, int L, int C>
+__device__ __forceinline__ void build_M2(float* Ms, const float* gam, int n, int slot) {
+  constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
+  constexpr int NS = 256 / C;
+  static_for<0, LP.n_paths>([&](auto K) {
+    constexpr PathT pt = LP.p[decltype(K)::value];
+    constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
+    constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
+    if (decltype(K)::value % NS == slot) {
+#pragma unroll
+      for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int m2 = 0; m2 < d2; ++m2) acc += c_cg[off + (m1 * d2 + m2) * d3 + m3] * gam[(pt.l2 * pt.l2 + m2) * C + n];
+          Ms[(pt.m_off + m1 * d3 + m3) * C + n] = acc;
+        }
+    }
+  });
+}
+
+template <int LMAX, int NL, int L, int C>
+__device__ __forceinline__ void load_V2(const TP2Args& a, int64_t t, int n, const float* Y, const float* Yd, float* V,
+                                        float* Vd) {
+  constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
+  const int64_t ts = a.stack + t;
+  if constexpr (L == 1) {
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+      const float wd = a.omega1[(ts * (LMAX + 1) + l) * C + n];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        V[l * l + m] = w * Y[l * l + m];
+        Vd[l * l + m] = wd * Y[l * l + m] + w * Yd[l * l + m];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < LP.n_in_comps; ++q) {
+      V[q] = a.vin[(t * LP.n_in_comps + q) * C + n];
+      Vd[q] = a.vin[(ts * LP.n_in_comps + q) * C + n];
+    }
+  }
+}
+
+template <int LMAX, int NL, int L, int C>
+__global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
+  constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NS = 256 / C;
+  constexpr int NCI = LP.n_in_comps, NCO = LP.n_out_comps > 0 ? LP.n_out_comps : 1;
+  __shared__ float Ms[LP.m_size * C];
+  __shared__ float Mds[LP.m_size * C];
+  __shared__ float red[2 * NS * NLM * C];
+  __shared__ float gam[NLM * C];
+  __shared__ float gamd[NLM * C];
+  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    float acc[NLM], accd[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) { acc[q] = 0.0f; accd[q] = 0.0f; }
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0, ts = a.stack + t;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+        const float wd = a.omega[(ts * (LMAX + 1) + l) * C + n];
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          acc[l * l + m] += w * Y[l * l + m];
+          accd[l * l + m] += wd * Y[l * l + m] + w * Yd[l * l + m];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      red[(slot * NLM + q) * C + n] = acc[q];
+      red[((NS + slot) * NLM + q) * C + n] = accd[q];
+    }
+    __syncthreads();
+    for (int q = slot; q < NLM; q += NS) {
+      float g = 0.0f, gd = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        g += red[(s * NLM + q) * C + n];
+        gd += red[((NS + s) * NLM + q) * C + n];
+      }
+      g *= a.inv_sqrt_nbar;
+      gd *= a.inv_sqrt_nbar;
+      gam[q * C + n] = g;
+      gamd[q * C + n] = gd;
+      a.gamma[(i * NLM + q) * C + n] = g;
+      a.gammad[(i * NLM + q) * C + n] = gd;
+    }
+    __syncthreads();
+    build_M2<LMAX, NL, L, C>(Ms, gam, n, slot);
+    build_M2<LMAX, NL, L, C>(Mds, gamd, n, slot);
+    __syncthreads();
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0, ts = a.stack + t;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
+      float V[NCI], Vd[NCI];
+      load_V2<LMAX, NL, L, C>(a, t, n, Y, Yd, V, Vd);
+      float out[NCO], outd[NCO];
+#pragma unroll
+      for (int q = 0; q < NCO; ++q) { out[q] = 0.0f; outd[q] = 0.0f; }
+      static_for<0, LP.n_paths>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr PathT pt = LP.p[k];
+        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        float T[d3], Td[d3];
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) {
+          float v = 0.0f, vd = 0.0f;
+#pragma unroll
+          for (int m1 = 0; m1 < d1; ++m1) {
+            const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
+            const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
+            v += V[pt.in_off + m1] * mm;
+            vd += Vd[pt.in_off + m1] * mm + V[pt.in_off + m1] * mmd;
+          }
+          T[m3] = v;
+          Td[m3] = vd;
+        }
+        if constexpr (pt.s_idx >= 0) {
+          a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
+          a.s[(ts * LP.n0e + pt.s_idx) * C + n] = Td[0];
+        }
+        if constexpr (pt.out_off >= 0) {
+          const float al = a.alpha[k * C + n];
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3) {
+            out[pt.out_off + m3] += al * T[m3];
+            outd[pt.out_off + m3] += al * Td[m3];
+          }
+        }
+      });
+      if constexpr (LP.n_out_comps > 0) {
+#pragma unroll
+        for (int q = 0; q < LP.n_out_comps; ++q) {
+          a.vout[(t * LP.n_out_comps + q) * C + n] = out[q];
+          a.vout[(ts * LP.n_out_comps + q) * C + n] = outd[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int LMAX, int NL, int L, int C>
+__global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
+  constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NS = 256 / C;
+  constexpr int NCI = LP.n_in_comps;
+  constexpr int MS = LP.m_size;
+  constexpr int NP = LP.n_paths;
+  constexpr int MAXB = 25;
+  __shared__ float Ms[MS * C];
+  __shared__ float Mds[MS * C];
+  __shared__ float red[NS * MAXB * C];
+  __shared__ float gg[2 * NLM * C];   // Gamma, then dJ/dGamma and dJ/dGamma_dot
+  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    for (int q = slot; q < NLM; q += NS) {
+      gg[q * C + n] = a.gamma[(i * NLM + q) * C + n];
+      gg[(NLM + q) * C + n] = a.gammad[(i * NLM + q) * C + n];
+    }
+    __syncthreads();
+    build_M2<LMAX, NL, L, C>(Ms, gg, n, slot);
+    build_M2<LMAX, NL, L, C>(Mds, gg + NLM * C, n, slot);
+    __syncthreads();
+    float GM[MS], GMd[MS], ga[NP];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) { GM[q] = 0.0f; GMd[q] = 0.0f; }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) ga[q] = 0.0f;
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0, ts = a.stack + t;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
+      float V[NCI], Vd[NCI], GV[NCI], GVd[NCI];
+      load_V2<LMAX, NL, L, C>(a, t, n, Y, Yd, V, Vd);
+#pragma unroll
+      for (int q = 0; q < NCI; ++q) { GV[q] = 0.0f; GVd[q] = 0.0f; }
+      static_for<0, NP>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr PathT pt = LP.p[k];
+        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        float GT[d3], GTd[d3];
+#pragma unroll
+        for (int m3 = 0; m3 < d3; ++m3) { GT[m3] = 0.0f; GTd[m3] = 0.0f; }
+        if constexpr (pt.s_idx >= 0) {
+          GT[0] = a.gs[(t * LP.n0e + pt.s_idx) * C + n];
+          GTd[0] = a.gs[(ts * LP.n0e + pt.s_idx) * C + n];
+        }
+        if constexpr (pt.out_off >= 0) {
+          const float al = a.alpha[k * C + n];
+          float gal = 0.0f;
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3) {
+            const float gvo = a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
+            const float gvod = a.gvout[(ts * LP.n_out_comps + pt.out_off + m3) * C + n];
+            float T = 0.0f, Td = 0.0f;
+#pragma unroll
+            for (int m1 = 0; m1 < d1; ++m1) {
+              const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
+              const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
+              T += V[pt.in_off + m1] * mm;
+              Td += Vd[pt.in_off + m1] * mm + V[pt.in_off + m1] * mmd;
+            }
+            gal += gvo * T + gvod * Td;
+            GT[m3] += al * gvo;
+            GTd[m3] += al * gvod;
+          }
+          ga[k] += gal;
+        }
+#pragma unroll
+        for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+          for (int m3 = 0; m3 < d3; ++m3) {
+            const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
+            const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
+            GV[pt.in_off + m1] += mm * GT[m3] + mmd * GTd[m3];
+            GVd[pt.in_off + m1] += mm * GTd[m3];
+            GM[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GT[m3] + Vd[pt.in_off + m1] * GTd[m3];
+            GMd[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GTd[m3];
+          }
+      });
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int q = 0; q < NCI; ++q) {
+          a.gvin[(t * NCI + q) * C + n] = GV[q];
+          a.gvin[(ts * NCI + q) * C + n] = GVd[q];
+        }
+      } else {
+        // V^0 = omega (x) Y, V^0_dot = omega_dot (x) Y + omega (x) Y_dot
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) {
+          float go = 0.0f, god = 0.0f;
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) {
+            go += GV[l * l + m] * Y[l * l + m] + GVd[l * l + m] * Yd[l * l + m];
+            god += GVd[l * l + m] * Y[l * l + m];
+          }
+          a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
+          a.gomega[(ts * (LMAX + 1) + l) * C + n] = god;
+        }
+      }
+    }
+    // reduce dJ/dM and dJ/dM_dot over slots, path by path, into Ms / Mds
+    __syncthreads();
+    static_for<0, NP>([&](auto K) {
+      constexpr PathT pt = LP.p[decltype(K)::value];
+      constexpr int blk = (2 * pt.l1 + 1) * (2 * pt.l3 + 1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < blk; ++q) red[(slot * MAXB + q) * C + n] = h ? GMd[pt.m_off + q] : GM[pt.m_off + q];
+        __syncthreads();
+        for (int q = slot; q < blk; q += NS) {
+          float v = 0.0f;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) v += red[(s * MAXB + q) * C + n];
+          (h ? Mds : Ms)[(pt.m_off + q) * C + n] = v;
+        }
+        __syncthreads();
+      }
+    });
+    // alpha-gradient shares of this atom
+    if constexpr (L < NL) {
+      static_for<0, NP>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        red[slot * C + n] = ga[k];
+        __syncthreads();
+        if (slot == 0) {
+          float v = 0.0f;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) v += red[s * C + n];
+          a.galpha[(i * NP + k) * C + n] = v;
+        }
+        __syncthreads();
+      });
+    }
+    // dJ/dGamma = C^T dJ/dM, dJ/dGamma_dot = C^T dJ/dM_dot (scaled)
+    for (int q = slot; q < NLM; q += NS) {
+      float g = 0.0f, gd = 0.0f;
+      static_for<0, NP>([&](auto K) {
+        constexpr PathT pt = LP.p[decltype(K)::value];
+        constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
+        constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
+        const int m2 = q - pt.l2 * pt.l2;
+        if (m2 >= 0 && m2 < d2) {
+#pragma unroll
+          for (int m1 = 0; m1 < d1; ++m1)
+#pragma unroll
+            for (int m3 = 0; m3 < d3; ++m3) {
+              const float cgv = c_cg[off + (m1 * d2 + m2) * d3 + m3];
+              g += cgv * Ms[(pt.m_off + m1 * d3 + m3) * C + n];
+              gd += cgv * Mds[(pt.m_off + m1 * d3 + m3) * C + n];
+            }
+        }
+      });
+      gg[q * C + n] = g * a.inv_sqrt_nbar;
+      gg[(NLM + q) * C + n] = gd * a.inv_sqrt_nbar;
+    }
+    __syncthreads();
+    // Gamma = sum omega (x) Y;  Gamma_dot = sum omega_dot (x) Y + omega (x) Y_dot
+    for (int64_t e = eb + slot; e < ee; e += NS) {
+      const int64_t t = e - e0, ts = a.stack + t;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        float go = 0.0f, god = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const float G = gg[(l * l + m) * C + n], Gd = gg[(NLM + l * l + m) * C + n];
+          go += G * Y[l * l + m] + Gd * Yd[l * l + m];
+          god += Gd * Y[l * l + m];
+        }
+        float* p0 = a.gomega + (t * (LMAX + 1) + l) * C + n;
+        float* p1 = a.gomega + (ts * (LMAX + 1) + l) * C + n;
+        if constexpr (L == 1) { *p0 += go; *p1 += god; } else { *p0 = go; *p1 = god; }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+typedef void (*tp2_kernel_t)(TP2Args);
+
+template <int LMAX, int NL, int C>
+static tp2_kernel_t pick2(int L, bool bwd) {
+  if (L == 1) return bwd ? k_tp2_bwd<LMAX, NL, 1, C> : k_tp2_fwd<LMAX, NL, 1, C>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp2_bwd<LMAX, NL, 2, C> : k_tp2_fwd<LMAX, NL, 2, C>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp2_bwd<LMAX, NL, 3, C> : k_tp2_fwd<LMAX, NL, 3, C>;
+  return nullptr;
+}
+
+static tp2_kernel_t pick_tp2(int lmax, int NL, int L, int C, bool bwd) {
+#define AFM_TP2(LM, NLV, CV) \
+  if (lmax == LM && NL == NLV && C == CV) return pick2<LM, NLV, CV>(L, bwd);
+  AFM_TP2(1, 1, 8)
+  AFM_TP2(2, 1, 8)
+  AFM_TP2(2, 2, 8)
+  AFM_TP2(2, 2, 16)
+  AFM_TP2(2, 2, 32)
+  AFM_TP2(2, 2, 64)
+  AFM_TP2(2, 3, 64)
+#undef AFM_TP2
+  return nullptr;
+}
+
+// ----------------------------------------------------------------------------
+// loaders / epilogues
+
+struct LdAct {   // primal rows: silu(a); tangent rows: silu'(a) a_dot
+  const float* pre; int ld; int stack;
+  __device__ float operator()(int m, int k) const {
+    if (m < stack) return silu_f(pre[(int64_t)m * ld + k]);
+    const float a = pre[(int64_t)(m - stack) * ld + k];
+    return d1silu(a) * pre[(int64_t)m * ld + k];
+  }
+};
+struct LdPlain {
+  const float* x; int ld;
+  __device__ float operator()(int m, int k) const { return x[(int64_t)m * ld + k]; }
+};
+struct LdCat {
+  const float* x; int w; const float* s; int ls;
+  __device__ float operator()(int m, int k) const {
+    return k < w ? x[(int64_t)m * w + k] : s[(int64_t)m * ls + (k - w)];
+  }
+};
+struct LdCoef {
+  const float* c;
+  __device__ float operator()(int m, int) const { return c[m]; }
+};
+// first two-body layer inputs: [onehot Zi | onehot Zj | rho] (primal rows)
+// and [0 | 0 | rho_dot] (tangent rows)
+struct LdZ {
+  const float* geo; const float* geo2; const int32_t* eidx; const int32_t* col; const int32_t* species;
+  int64_t e0_unused; RowRange rr; int stack, S, nb, p; float r_cut;
+  __device__ float operator()(int m, int k) const {
+    const int t = m < stack ? m : m - stack;
+    const bool tan = m >= stack;
+    if (k < 2 * S) {
+      if (tan) return 0.0f;
+      int64_t e0, e1;
+      rr.get(e0, e1);
+      const int z = k < S ? species[eidx[t]] : species[col[e0 + t]];
+      return (min(max(z, 0), S - 1) == (k < S ? k : k - S)) ? 1.0f : 0.0f;
+    }
+    float rho, rhod;
+    rho_pair(geo + (int64_t)t * GEO_STRIDE, geo2 + (int64_t)t * GEO_STRIDE, r_cut, p, k - 2 * S, rho, rhod);
+    return tan ? rhod : rho;
+  }
+};
+struct EpSt {
+  float* y; int ld;
+  __device__ void operator()(int m, int n, float v) const { y[(int64_t)m * ld + n] = v; }
+};
+struct EpAd {
+  float* y; int ld;
+  __device__ void operator()(int m, int n, float v) const { y[(int64_t)m * ld + n] += v; }
+};
+struct EpSplit2 {
+  float* gx; int w; float* gs; int ls;
+  __device__ void operator()(int m, int n, float v) const {
+    if (n < w) gx[(int64_t)m * w + n] += v; else gs[(int64_t)m * ls + (n - w)] = v;
+  }
+};
+
+// gacc[off + map(n, k)] += sum over slices (fixed order); env matrices map
+// their l-major rows back to the layout's channel-major rows
+__global__ void k_reduce_slices(const float* __restrict__ P, int slices, int N, int K, double* __restrict__ gacc,
+                                int64_t off, int env_c, int env_l1) {
+  const int64_t tot = (int64_t)N * K;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < slices; ++s) v += (double)P[(int64_t)s * tot + q];
+    int64_t n = q / K, k = q % K;
+    if (env_c > 0) n = (n % env_c) * env_l1 + n / env_c;
+    gacc[off + n * K + k] += v;
+  }
+}
+
+// per-atom shares -> gacc (fixed order over atoms)
+__global__ void k_reduce_atoms(const float* __restrict__ part, int64_t N, int64_t width, double* __restrict__ gacc,
+                               int64_t off) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < width; q += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int64_t i = 0; i < N; ++i) v += (double)part[i * width + q];
+    gacc[off + q] += v;
+  }
+}
+
+__global__ void k_species_grad(const double* __restrict__ a_sig, const double* __restrict__ a_mu,
+                               const int32_t* __restrict__ species, int64_t N, int S, double* __restrict__ gacc,
+                               int64_t off_sig, int64_t off_mu) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= S) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < N; ++i)
+    if (species[i] == z) { s1 += a_sig[i]; s2 += a_mu[i]; }
+  gacc[off_sig + z] += s1;
+  gacc[off_mu + z] += s2;
+}
+
+// dJ/dW_E1[h][f] = W_E2[h] q[f];  dJ/dW_E2[h] = sum_f W_E1[h][f] q[f]
+__global__ void k_edge_grad(const double* __restrict__ q, const float* __restrict__ e0, const float* __restrict__ e1,
+                            int H, int W, double* __restrict__ gacc, int64_t off0, int64_t off1) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)H * W + H;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < (int64_t)H * W) {
+      const int64_t h = idx / W, f = idx % W;
+      gacc[off0 + idx] += (double)e1[h] * q[f];
+    } else {
+      const int64_t h = idx - (int64_t)H * W;
+      double v = 0.0;
+      for (int f = 0; f < W; ++f) v += (double)e0[h * W + f] * q[f];
+      gacc[off1 + h] += v;
+    }
+  }
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    b[q] = (float)a[q];
+}
+
+// ----------------------------------------------------------------------------
+// schedule
+
+static int64_t block_offset(const afm_model* m, const char* name) {
+  for (auto& b : m->blocks)
+    if (strcmp(b.name, name) == 0) return b.offset;
+  return -1;
+}
+
+template <class ALA, class ALB>
+static int wgrad(hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, ALB Bl, float* partial,
+                 double* gacc, int64_t off, int env_c = 0, int env_l1 = 0) {
+  const int rows = 2 * stack;
+  const int rps = ((rows + kSlices - 1) / kSlices + 15) / 16 * 16;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)kSlices);
+  hipLaunchKernelGGL((k_wgrad<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
+  hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for((int64_t)N * K, 256, 4096)), dim3(256), 0, st,
+                     (const float*)partial, kSlices, N, K, gacc, off, env_c, env_l1);
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
+int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
+                    RowRange rr, hipStream_t st);   // forward.hip
+
+int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
+                     const WsLayout& L, const double* gE, const double* gF, float* grad_out, hipStream_t st) {
+  TraceScope tr(st, "second_order");
+  const ModelDims& d = m->dims;
+  const Plan& P = m->plan;
+  const int stack = (int)L.cex;
+  const int64_t E2 = 2 * (int64_t)stack;
+  const int env = (d.lmax + 1) * d.c;
+  double* gacc = ws_ptr<double>(ws, L.so_gacc);
+  float* partial = ws_ptr<float>(ws, L.so_partial);
+  float* geo = ws_ptr<float>(ws, L.geo);
+  int32_t* eidx = ws_ptr<int32_t>(ws, L.eidx);
+  float* geo2 = ws_ptr<float>(ws, L.so_geo2);
+  float* gx = ws_ptr<float>(ws, L.so_gx);
+  float* ga = ws_ptr<float>(ws, L.so_ga);
+  float* gh = ws_ptr<float>(ws, L.so_gh);
+  float* gs2 = ws_ptr<float>(ws, L.so_gs);
+  float* gom = ws_ptr<float>(ws, L.so_gomega);
+  float* eps2 = ws_ptr<float>(ws, L.so_eps);
+  float* coef = ws_ptr<float>(ws, L.so_coef);
+  int rc = zero_async(gacc, m->n_params * 8, st);
+  if (!rc) rc = zero_async(ws_ptr<double>(ws, L.so_q), (int64_t)d.w * 8, st);
+  if (rc) return rc;
+  rc = launch_chunk_rows(s, nl, ws, L, st);
+  if (!rc) rc = check_chunks(s, nl, ws, L, st);
+  if (rc) return rc;
+  RowRange rr{ws_ptr<int64_t>(ws, L.chunk_rows), nl.row_ptr, 0};
+  const float inb = (float)(1.0 / sqrt(d.nbar));
+  for (int chunk = 0; chunk < ws->n_chunks; ++chunk) {
+    rr.chunk = chunk;
+    // ---- forward with tangents ----
+    rc = launch_geometry(m, s, nl, ws, L, rr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_geom2, dim3(grid_for(stack, 256, 65536)), dim3(256), 0, st, rr, (const float*)geo,
+                       (const int32_t*)eidx, (const int32_t*)nl.col, gF, (float)d.r_cut, d.p, geo2);
+    float* tbp0 = ws_ptr<float>(ws, L.so_tb_pre[0]);
+    hipLaunchKernelGGL(k_tb2_first, dim3(grid_for((int64_t)stack * d.tb[0], 256, 65536)), dim3(256), 0, st, rr, stack,
+                       (const float*)geo, (const float*)geo2, (const int32_t*)eidx, (const int32_t*)nl.col, s.species,
+                       m->W.tb[0], d.S, d.nb, d.tb[0], (float)d.r_cut, d.p, tbp0);
+    AFM_LAUNCH_CHECK();
+    for (int k = 1; k < d.ntb; ++k)
+      sgemm<true>(st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
+                  LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack},
+                  EpSt{ws_ptr<float>(ws, L.so_tb_pre[k]), d.tb[k]}, stack);
+    float* x0 = ws_ptr<float>(ws, L.so_x[0]);
+    hipLaunchKernelGGL(k_tb2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack, d.w,
+                       (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), (const float*)geo,
+                       (const float*)geo2, x0);
+    sgemm<true>(st, rr, E2, d.w, env, m->W.env[0], d.w, LdPlain{x0, d.w}, EpSt{ws_ptr<float>(ws, L.so_omega[0]), env},
+                stack);
+    AFM_LAUNCH_CHECK();
+    for (int layer = 1; layer <= d.NL; ++layer) {
+      const LayerPlan& lp = P.layer[layer - 1];
+      const int ls = lp.n0e * d.c;
+      TP2Args ta{};
+      ta.rr = rr; ta.stack = stack; ta.geo = geo; ta.geo2 = geo2;
+      ta.omega = ws_ptr<float>(ws, L.so_omega[layer - 1]);
+      ta.omega1 = ws_ptr<float>(ws, L.so_omega[0]);
+      ta.vin = layer > 1 ? ws_ptr<float>(ws, L.so_v[layer - 2]) : nullptr;
+      ta.vout = layer < d.NL ? ws_ptr<float>(ws, L.so_v[layer - 1]) : nullptr;
+      ta.s = ws_ptr<float>(ws, L.so_s[layer - 1]);
+      ta.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
+      ta.gammad = ws_ptr<float>(ws, L.so_gammad[layer - 1]);
+      ta.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;
+      ta.inv_sqrt_nbar = inb;
+      tp2_kernel_t kf = pick_tp2(d.lmax, d.NL, layer, d.c, false);
+      if (!kf) { set_error("second-order tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
+      hipLaunchKernelGGL(kf, dim3(grid_for(s.N, 1, 65536)), dim3(256), 0, st, ta);
+      AFM_LAUNCH_CHECK();
+      const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
+      for (int k = 0; k < d.depth; ++k) {
+        float* pre = ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k]);
+        if (k == 0)
+          sgemm<true>(st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
+                      EpSt{pre, d.w}, stack);
+        else
+          sgemm<true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
+                      LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, EpSt{pre, d.w}, stack);
+      }
+      float* xn = ws_ptr<float>(ws, L.so_x[layer]);
+      hipLaunchKernelGGL(k_lat2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack,
+                         d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), xp,
+                         (const float*)geo, (const float*)geo2, xn);
+      if (layer < d.NL)
+        sgemm<true>(st, rr, E2, d.w, env, m->W.env[layer], d.w, LdPlain{xn, d.w},
+                    EpSt{ws_ptr<float>(ws, L.so_omega[layer]), env}, stack);
+      AFM_LAUNCH_CHECK();
+    }
+    // ---- energies and the first adjoints ----
+    const float* xN = ws_ptr<float>(ws, L.so_x[d.NL]);
+    hipLaunchKernelGGL(k_energy2, dim3(grid_for(stack, 4, 16384)), dim3(256), 0, st, rr, stack, d.w, xN, m->W.w_eff,
+                       (const int32_t*)eidx, s.species, m->W.sp_scale, d.S, d.escale, s.seg, s.B, gE, eps2, coef, gx);
+    hipLaunchKernelGGL(k_atom2, dim3(grid_for(s.N, 256, 4096)), dim3(256), 0, st, rr, stack, (const float*)eps2,
+                       s.species, d.S, d.escale, s.seg, s.B, gE, ws_ptr<double>(ws, L.so_asig),
+                       ws_ptr<double>(ws, L.so_amu));
+    AFM_LAUNCH_CHECK();
+    // q[f] = sum_m coef_m x[m][f]  (accumulated in the q slot of gacc's tail)
+    rc = wgrad(st, rr, stack, 1, d.w, LdCoef{coef}, LdPlain{xN, d.w}, partial, ws_ptr<double>(ws, L.so_q), 0);
+    if (rc) return rc;
+    // ---- reverse ----
+    char nm[32];
+    for (int layer = d.NL; layer >= 1; --layer) {
+      const LayerPlan& lp = P.layer[layer - 1];
+      const int ls = lp.n0e * d.c;
+      const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
+      if (layer < d.NL) {
+        sgemm<false>(st, rr, E2, env, d.w, m->W.env[layer], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+        snprintf(nm, sizeof nm, "layer%d.env", layer + 1);
+        rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{ws_ptr<float>(ws, L.so_x[layer]), d.w},
+                   partial, gacc, block_offset(m, nm), d.c, d.lmax + 1);
+        if (rc) return rc;
+      }
+      hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack,
+                         d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), gx, ga,
+                         (const float*)geo, (const float*)geo2, 1, 0.70710678118654752f, 0.70710678118654752f);
+      AFM_LAUNCH_CHECK();
+      for (int k = d.depth - 1; k >= 0; --k) {
+        snprintf(nm, sizeof nm, "layer%d.latent.%d", layer, k);
+        const int64_t off = block_offset(m, nm);
+        if (k > 0) {
+          rc = wgrad(st, rr, stack, d.w, d.w, LdPlain{ga, d.w},
+                     LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, partial, gacc, off);
+          if (rc) return rc;
+          sgemm<false>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
+          hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr,
+                             stack, d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), gh, ga,
+                             (const float*)geo, (const float*)geo2, 0, 1.0f, 0.0f);
+          AFM_LAUNCH_CHECK();
+        } else {
+          rc = wgrad(st, rr, stack, d.w, d.w + ls, LdPlain{ga, d.w},
+                     LdCat{xp, d.w, ws_ptr<float>(ws, L.so_s[layer - 1]), ls}, partial, gacc, off);
+          if (rc) return rc;
+          sgemm<false>(st, rr, E2, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LdPlain{ga, d.w},
+                       EpSplit2{gx, d.w, gs2, ls}, stack);
+          AFM_LAUNCH_CHECK();
+        }
+      }
+      TP2Args ta{};
+      ta.rr = rr; ta.stack = stack; ta.geo = geo; ta.geo2 = geo2;
+      ta.omega = ws_ptr<float>(ws, L.so_omega[layer - 1]);
+      ta.omega1 = ws_ptr<float>(ws, L.so_omega[0]);
+      ta.vin = layer > 1 ? ws_ptr<float>(ws, L.so_v[layer - 2]) : nullptr;
+      ta.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
+      ta.gammad = ws_ptr<float>(ws, L.so_gammad[layer - 1]);
+      ta.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;
+      ta.inv_sqrt_nbar = inb;
+      ta.gs = gs2;
+      float* gva = ws_ptr<float>(ws, L.so_gv0);
+      float* gvb = ws_ptr<float>(ws, L.so_gv1);
+      ta.gvout = (layer < d.NL) ? (((d.NL - layer) % 2 == 1) ? gva : gvb) : nullptr;
+      ta.gvin = (layer > 1) ? (((d.NL - layer) % 2 == 0) ? gva : gvb) : nullptr;
+      ta.gomega = gom;
+      ta.galpha = layer < d.NL ? ws_ptr<float>(ws, L.so_galpha[layer - 1]) : nullptr;
+      tp2_kernel_t kb = pick_tp2(d.lmax, d.NL, layer, d.c, true);
+      if (!kb) { set_error("second-order tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
+      hipLaunchKernelGGL(kb, dim3(grid_for(s.N, 1, 65536)), dim3(256), 0, st, ta);
+      AFM_LAUNCH_CHECK();
+      // alpha shares are per atom (chunks do not overlap): reduced after the last chunk
+    }
+    // two-body reverse
+    sgemm<false>(st, rr, E2, env, d.w, m->W.env[0], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+    rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{x0, d.w}, partial, gacc,
+               block_offset(m, "layer1.env"), d.c, d.lmax + 1);
+    if (rc) return rc;
+    {
+      const int F = d.tb[d.ntb - 1];
+      hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * F, 256, 65536)), dim3(256), 0, st, rr, stack, F,
+                         (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), gx, ga, (const float*)geo,
+                         (const float*)geo2, 1, 1.0f, 0.0f);
+      AFM_LAUNCH_CHECK();
+      for (int k = d.ntb - 1; k >= 0; --k) {
+        snprintf(nm, sizeof nm, "twobody.%d", k);
+        const int64_t off = block_offset(m, nm);
+        if (k > 0) {
+          rc = wgrad(st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+                     LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack}, partial, gacc, off);
+          if (rc) return rc;
+          sgemm<false>(st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+                       EpSt{gh, d.tb[k - 1]}, stack);
+          hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.tb[k - 1], 256, 65536)), dim3(256), 0, st,
+                             rr, stack, d.tb[k - 1], (const float*)ws_ptr<float>(ws, L.so_tb_pre[k - 1]), gh, ga,
+                             (const float*)geo, (const float*)geo2, 0, 1.0f, 0.0f);
+          AFM_LAUNCH_CHECK();
+        } else {
+          LdZ lz{geo, geo2, eidx, nl.col, s.species, 0, rr, stack, d.S, d.nb, d.p, (float)d.r_cut};
+          rc = wgrad(st, rr, stack, d.tb[0], 2 * d.S + d.nb, LdPlain{ga, d.tb[0]}, lz, partial, gacc, off);
+          if (rc) return rc;
+        }
+      }
+    }
+  }
+  // per-atom shares: alpha, species scale / shift; edge-energy matrices
+  char nm[32];
+  for (int layer = 1; layer < d.NL; ++layer) {
+    snprintf(nm, sizeof nm, "layer%d.alpha", layer);
+    const int64_t width = (int64_t)P.layer[layer - 1].n_paths * d.c;
+    hipLaunchKernelGGL(k_reduce_atoms, dim3(grid_for(width, 256, 4096)), dim3(256), 0, st,
+                       (const float*)ws_ptr<float>(ws, L.so_galpha[layer - 1]), s.N, width, gacc,
+                       block_offset(m, nm));
+  }
+  hipLaunchKernelGGL(k_species_grad, dim3(grid_for(d.S, 128)), dim3(128), 0, st,
+                     (const double*)ws_ptr<double>(ws, L.so_asig), (const double*)ws_ptr<double>(ws, L.so_amu),
+                     s.species, s.N, d.S, gacc, block_offset(m, "species.scale"), block_offset(m, "species.shift"));
+  hipLaunchKernelGGL(k_edge_grad, dim3(grid_for((int64_t)d.h * d.w + d.h, 256, 4096)), dim3(256), 0, st,
+                     (const double*)ws_ptr<double>(ws, L.so_q), m->W.e0, m->W.e1, d.h, d.w, gacc,
+                     block_offset(m, "edge.0"), block_offset(m, "edge.1"));
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(m->n_params, 256, 4096)), dim3(256), 0, st, (const double*)gacc,
+                     grad_out, m->n_params);
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
+}  // namespace afm

@@ -1,0 +1,103 @@
+"""GPU double backward (weight gradients of force matching) against the
+FP64 oracle's double backward (itself pinned by finite differences), and the
+training loss gradient end to end through the autograd binding."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import weights_for
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-4          # FP32 relative norm
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _calc(hp, w, s, precision="fp32"):
+    import paper_2502_06073_amd as afm
+    model = afm.Model(hp, w, precision=precision)
+    sysd = afm.DeviceSystem.from_synth(s)
+    calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]), second_order=True)
+    calc.build_neighbors()
+    return calc
+
+
+CASES = {
+    "A": lambda: (synth.load_hparams("A"), synth.config_a()),
+    "C_6clusters": lambda: (synth.load_hparams("C"), synth.clusters(6, 20, 80, 0.1, 0.9, 10, 111)),
+    "C_periodic_small": lambda: (synth.load_hparams("C"), synth.cubic_lattice(4, 2.4, 0.2, 10, 112)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_second_order_matches_oracle(name):
+    import torch
+    from oracle import model as M
+    hp, s = CASES[name]()
+    w = weights_for(hp, 31)
+    rng = np.random.default_rng(3)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    calc = _calc(hp, w, s)
+    g = calc.forces_backward(torch.tensor(gE, device="cuda"), torch.tensor(gF, device="cuda"))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    ref = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, gF)["grad_weights"]
+    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    lay = M.param_layout(M.HParams.from_dict(hp))
+    worst, off = [], 0
+    for b in lay:
+        seg = slice(off, off + b["size"])
+        den = max(np.linalg.norm(ref[seg]), 1e-30)
+        worst.append((np.linalg.norm(g[seg] - ref[seg]) / den, b["name"]))
+        off += b["size"]
+    worst.sort(reverse=True)
+    _say(f"[d2] {name}: rel {err:.2e}; worst blocks {worst[:3]}")
+    assert err < TOL
+    assert worst[0][0] < 10 * TOL
+
+
+def test_second_order_force_term_only_and_energy_term_only():
+    import torch
+    from oracle import model as M
+    hp, s = CASES["C_6clusters"]()
+    w = weights_for(hp, 32)
+    calc = _calc(hp, w, s)
+    rng = np.random.default_rng(4)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    ge_only = calc.forces_backward(torch.tensor(gE, device="cuda"), None).cpu().numpy()
+    gf_only = calc.forces_backward(None, torch.tensor(gF, device="cuda")).cpu().numpy()
+    both = calc.forces_backward(torch.tensor(gE, device="cuda"), torch.tensor(gF, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(ge_only + gf_only, both, rtol=1e-4, atol=1e-6 * np.abs(both).max())
+    ref = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, np.zeros_like(gF))["grad_weights"]
+    assert np.linalg.norm(ge_only - ref) / np.linalg.norm(ref) < TOL
+
+
+def test_training_loss_gradient_through_autograd():
+    import torch
+    import paper_2502_06073_amd as afm
+    from oracle import model as M
+    hp, s = CASES["C_6clusters"]()
+    w = weights_for(hp, 33)
+    e_hat, f_hat = synth.training_targets(s, 5)
+    calc = _calc(hp, w, s)
+    theta = torch.zeros(w.shape[0], dtype=torch.float64, requires_grad=True)
+    E, F = afm.energy_forces_for_training(calc, theta)
+    n_s = torch.tensor(np.diff(s.seg), dtype=torch.float64, device="cuda")
+    de = (E - torch.tensor(e_hat, device="cuda")) / n_s
+    df = F - torch.tensor(f_hat, device="cuda")
+    loss = (de * de).mean() + (df * df).sum() / (3.0 * s.n_atoms)
+    loss.backward()
+    ref = M.loss_and_grad(M.HParams.from_dict(hp), w, s, e_hat, f_hat)
+    g = theta.grad.cpu().numpy()
+    err = np.linalg.norm(g - ref["grad_weights"]) / np.linalg.norm(ref["grad_weights"])
+    _say(f"[train] loss gpu {loss.item():.6f} oracle {ref['loss']:.6f}; grad rel {err:.2e}")
+    assert abs(loss.item() - ref["loss"]) < 1e-5 * abs(ref["loss"])
+    assert err < TOL
