@@ -35,25 +35,32 @@ PEAK_BF16 = 2.5e15      # dense BF16 MFMA, FLOP/s
 PEAK_FP32 = 157.3e12    # FP32 vector, FLOP/s
 
 
-def mlp_macs_per_edge(hp):
-    """Multiply-accumulates per edge of each GEMM stage (algorithmic work of
-    the MLP kernels; the forward of a stage and its input-gradient adjoint
-    do the same number)."""
-    from oracle import model as M  # noqa: F401  (path enumeration only in the oracle)
-    w, c, lm = hp["latent"], hp["channels"], hp["l_max"]
-    env = (lm + 1) * c
-    tb = hp["twobody"]
-    S, nb = hp["n_species"], hp["n_bessel"]
-    n0e = 3 if lm == 2 else lm + 1
-    tb_macs = nb * tb[0] + sum(tb[k - 1] * tb[k] for k in range(1, len(tb))) + w * env
-    lat = (w + n0e * c) * w + (hp["latent_depth"] - 1) * w * w
-    out = {"twobody_fwd": tb_macs, "twobody_bwd": tb_macs}
-    NL = hp["n_layers"]
-    for L in range(1, NL + 1):
-        extra_f = w * env if L < NL else w
-        extra_b = w * env if L < NL else 0
-        out[f"latent_fwd{L}"] = lat + extra_f
-        out[f"latent_bwd{L}"] = lat + extra_b
+PEAK_HBM = 8.0e12       # HBM3E, B/s
+
+
+def stage_roofline(costs, stats, n_edges, n_atoms):
+    """Per traced stage: algorithmic work / average launch time against the
+    roofline that bounds it (MFMA stages: dense BF16 peak; vector stages:
+    whichever of FP32 ALU and HBM needs more time for the algorithmic
+    flops and bytes)."""
+    out = {}
+    for name, st in stats.items():
+        c = costs.get(name)
+        if c is None or st["launches"] == 0:
+            continue
+        avg_s = st["total_ms"] / st["launches"] * 1e-3
+        flops = c["flops_per_edge"] * n_edges
+        nbytes = c["bytes_per_edge"] * n_edges + c["bytes_per_atom"] * n_atoms
+        if c["kind"] == "mfma":
+            bound, peak, work, unit = "mfma", PEAK_BF16, flops, "TFLOP/s"
+        elif flops / PEAK_FP32 >= nbytes / PEAK_HBM:
+            bound, peak, work, unit = "alu", PEAK_FP32, flops, "TFLOP/s"
+        else:
+            bound, peak, work, unit = "hbm", PEAK_HBM, nbytes, "GB/s"
+        ach = work / avg_s
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        out[name] = dict(bound=bound, achieved=ach / scale, peak=peak / scale, unit=unit, frac=ach / peak,
+                         avg_ms=avg_s * 1e3, flops_per_launch=flops, bytes_per_launch=nbytes)
     return out
 
 
@@ -153,12 +160,25 @@ def main(argv=None):
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
+    if a.copy_probe:
+        import torch
+        n = a.copy_probe // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=4 * n)), flush=True)
+        return 0
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
     import torch
+    import paper_2502_06073_amd as afm
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
@@ -169,20 +189,15 @@ def main(argv=None):
     ms = dt / a.steps * 1e3
     value = s.n_atoms * a.steps / dt
     print(f"[bench] bf16: {ms:.3f} ms/step, {value:.4g} atom-steps/s", file=sys.stderr, flush=True)
-    macs = mlp_macs_per_edge(hp)
+    costs = afm.stage_costs(hp)
+    roofs = stage_roofline(costs, stats, n_edges, s.n_atoms)
     # dominant kernel: the stage with the largest GPU time
-    dom = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
-    dom_name, dom_st = dom
-    avg_ms = dom_st["total_ms"] / dom_st["launches"]
-    roof = None
-    if dom_name in macs:
-        flops = 2.0 * macs[dom_name] * n_edges
-        ach = flops / (avg_ms * 1e-3)
-        roof = dict(bound="mfma", kernel=dom_name, achieved=ach / 1e12, peak=PEAK_BF16 / 1e12,
-                    unit="TFLOP/s", frac=ach / PEAK_BF16, traffic=load_traffic(dom_name),
-                    flops_per_launch=flops, avg_ms=avg_ms)
-    # whole-step MLP FLOP rate (all MFMA stages)
-    mlp_flops = sum(2.0 * v * n_edges for v in macs.values())
+    dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
+    r = roofs[dom_name]
+    roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"], frac=r["frac"],
+                traffic=load_traffic(dom_name), kernel=dom_name, avg_ms=r["avg_ms"],
+                per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]))
+    mlp_flops = sum(roofs[k]["flops_per_launch"] for k in roofs if costs[k]["kind"] == "mfma")
     stage_ms = {k: round(v["total_ms"] / v["launches"], 4) for k, v in stats.items()}
     out = dict(metric="atom-steps/s energy+forces, BF16-MFMA vs FP32 plain; force RMS err vs FP64",
                value=value, unit="atom-steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=ms,
@@ -193,6 +208,8 @@ def main(argv=None):
                                     f"incl. edge-list build" if a.config == "B" else f"config {a.config}",
                            n_atoms=s.n_atoms, n_edges=n_edges, parallelism="single GPU"),
                roofline=roof, stage_ms=stage_ms,
+               stage_roofline={k: dict(bound=v["bound"], frac=round(v["frac"], 4),
+                                       achieved=round(v["achieved"], 2), unit=v["unit"]) for k, v in roofs.items()},
                mlp_tflops_per_step=mlp_flops / (ms * 1e-3) / 1e12)
     outs = {"bf16": out_bf16}
     if not a.no_fp32:

@@ -285,6 +285,27 @@ typedef struct {
 int afm_trace_enable(int32_t enable);
 int afm_trace_read(afm_trace_stat* out /*host*/, int32_t max, int32_t* n /*host*/);
 
+/* Algorithmic work of each traced stage of afm_energy_forces for a model of
+ * hyper-parameters `hp` (host; no device needed),
+ * for roofline accounting (one entry per stage name that afm_trace_read
+ * reports, e.g. "tp_bwd1").  Counts are what the mathematics needs, not what
+ * the kernels issue: flops = 2 x multiply-adds of the stage's products (for
+ * the MLP stages once per weight, although the BF16 path issues every
+ * product as a hi + lo pair of MFMAs); bytes = compulsory HBM traffic, each
+ * input read once and each output written once (float32 features, bf16
+ * stored pre-activations, per-atom tensors once per central atom).
+ * kind: 0 = dense contraction (MFMA in the BF16 path), 1 = vector ALU /
+ * memory stage.  out: host, `max` entries; *n receives the stage count.  */
+typedef struct {
+  char name[32];
+  int32_t kind;
+  double flops_per_edge;
+  double bytes_per_edge;
+  double bytes_per_atom;
+} afm_stage_cost;
+int afm_stage_costs(const afm_hparams* hp /*host*/, afm_stage_cost* out /*host*/, int32_t max,
+                    int32_t* n /*host*/);
+
 /* ---- diagnostics ------------------------------------------------------- */
 const char* afm_strerror(int code);
 const char* afm_last_error(void);

@@ -25,7 +25,7 @@ from . import _abi
 from ._abi import AfmError, check, load
 
 __all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
-           "param_layout", "cg_real", "hparams_struct", "energy_and_forces", "AfmError",
+           "param_layout", "cg_real", "hparams_struct", "stage_costs", "energy_and_forces", "AfmError",
            "trace_enable", "trace_read", "energy_forces_for_training", "MD"]
 
 
@@ -42,6 +42,22 @@ def trace_read() -> Dict[str, Dict[str, float]]:
     arr = (_abi.TraceStat * max(1, n.value))()
     check("afm_trace_read", lib.afm_trace_read(arr, n.value, C.byref(n)))
     return {arr[k].name.decode(): dict(launches=arr[k].launches, total_ms=arr[k].total_ms)
+            for k in range(n.value)}
+
+
+def stage_costs(hp: Dict) -> Dict[str, Dict[str, float]]:
+    """Algorithmic flops/bytes per edge (and bytes per atom) of each traced
+    stage of energy_forces for hyper-parameters `hp`, keyed like trace_read()."""
+    lib = load()
+    h = hparams_struct(hp)
+    n = C.c_int32()
+    check("afm_stage_costs", lib.afm_stage_costs(C.byref(h), None, 0, C.byref(n)))
+    arr = (_abi.StageCost * max(1, n.value))()
+    check("afm_stage_costs", lib.afm_stage_costs(C.byref(h), arr, n.value, C.byref(n)))
+    return {arr[k].name.decode(): dict(kind=("mfma" if arr[k].kind == 0 else "vector"),
+                                       flops_per_edge=arr[k].flops_per_edge,
+                                       bytes_per_edge=arr[k].bytes_per_edge,
+                                       bytes_per_atom=arr[k].bytes_per_atom)
             for k in range(n.value)}
 
 
@@ -328,12 +344,14 @@ class _ForceMatchFn(torch.autograd.Function):
     def forward(ctx, theta, calc):
         out = calc.energy_forces(virial=False)
         ctx.calc = calc
+        ctx.theta_meta = (theta.device, theta.dtype)
         return out["e_struct"], out["forces"]
 
     @staticmethod
     def backward(ctx, gE, gF):
         g = _forces_backward(ctx.calc, gE, gF)
-        return g.to(torch.float64), None
+        dev, dt = ctx.theta_meta
+        return g.to(device=dev, dtype=dt), None
 
 
 def energy_forces_for_training(calc: "Calculator", theta: torch.Tensor):

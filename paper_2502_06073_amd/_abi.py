@@ -51,6 +51,11 @@ class TraceStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int32), ("total_ms", C.c_double)]
 
 
+class StageCost(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("kind", C.c_int32), ("flops_per_edge", C.c_double),
+                ("bytes_per_edge", C.c_double), ("bytes_per_atom", C.c_double)]
+
+
 class MdState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("forces", C.c_void_p),
                 ("mass_by_species", C.c_void_p), ("dt_fs", C.c_double), ("skin", C.c_double),
@@ -83,6 +88,7 @@ EXPORTS = {
                     C.POINTER(Workspace), C.c_void_p],
     "afm_trace_enable": [C.c_int32],
     "afm_trace_read": [C.POINTER(TraceStat), C.c_int32, C.POINTER(C.c_int32)],
+    "afm_stage_costs": [C.POINTER(Hparams), C.POINTER(StageCost), C.c_int32, C.POINTER(C.c_int32)],
     "afm_strerror": [C.c_int],
     "afm_last_error": [],
     "afm_version": [],

@@ -13,8 +13,14 @@
 //   phi(kb, g, i) = 32 kb + 4 g + (i & 3) + 16 (i >> 2),
 // and every weight fragment is packed on the host with the same permutation
 // (MFMA pairs A and B k-slots identically, so the product is unchanged).
-// Weights stream from L2 as 16-byte fragment loads; pre-activations are
-// stored as bf16 in a tile-native layout read back by the adjoint.
+// Every weight is held as an unevaluated sum of two bf16 numbers (hi + lo,
+// lo = bf16(w - hi)) and each fragment product is issued as two MFMAs into
+// the same FP32 accumulator, so the weights keep ~16 mantissa bits while
+// activations are rounded to bf16 once per layer.  Rounding the weights
+// alone would perturb the model itself, an error common to every edge that
+// does not average out over a structure; activation rounding is independent
+// per edge.  Pre-activations are stored as bf16 in a tile-native layout read
+// back by the adjoint.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -34,6 +40,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int JW = 2;             // 16-edge column blocks per wavefront
 constexpr int TILE = 16 * JW;     // edges per wavefront
 constexpr int WAVES = 4;          // wavefronts per workgroup
+constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -48,13 +55,21 @@ static uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// M(r, k) = transpose ? W[k * R + r] : W[r * K + k]; fragments [RB][KB][64][8]
+static double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+// M(r, k) = transpose ? W[k * R + r] : W[r * K + k]; fragments
+// [RB][KB][2][64][8] with the hi part of the weight pairs first, lo second
 static void pack_matrix(const double* W, int R, int K, bool transpose, std::vector<char>& out,
                         int64_t* off) {
   const int RB = cdiv(R, 16), KB = cdiv(K, 32);
   int64_t o = (int64_t)out.size();
   o = (o + 255) & ~int64_t(255);
-  out.resize(o + (int64_t)RB * KB * 64 * 16, 0);
+  out.resize(o + (int64_t)RB * KB * kSplit * 64 * 16, 0);
   uint16_t* p = reinterpret_cast<uint16_t*>(out.data() + o);
   for (int rb = 0; rb < RB; ++rb)
     for (int kb = 0; kb < KB; ++kb)
@@ -64,7 +79,11 @@ static void pack_matrix(const double* W, int R, int K, bool transpose, std::vect
           const int k = 32 * kb + 4 * g + (i & 3) + 16 * (i >> 2);
           double v = 0.0;
           if (r < R && k < K) v = transpose ? W[(int64_t)k * R + r] : W[(int64_t)r * K + k];
-          p[(((int64_t)rb * KB + kb) * 64 + lane) * 8 + i] = bf16_rne((float)v);
+          const uint16_t hi = bf16_rne((float)v);
+          const uint16_t lo = bf16_rne((float)(v - bf16_value(hi)));
+          const int64_t base = (((int64_t)rb * KB + kb) * kSplit * 64 + lane) * 8 + i;
+          p[base] = hi;
+          p[base + 64 * 8] = lo;
         }
       }
   *off = o;
@@ -119,10 +138,6 @@ void pack_bf16_frags(const afm_model* m, const double* base, std::vector<char>& 
 // ---------------------------------------------------------------------------
 // device building blocks
 
-__device__ __forceinline__ bf16x8 ldA(const uint4* __restrict__ W, int KB, int rb, int kb, int lane) {
-  return __builtin_bit_cast(bf16x8, W[((int64_t)rb * KB + kb) * 64 + lane]);
-}
-
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
@@ -170,21 +185,78 @@ __device__ __forceinline__ void zero(f32x4 (&a)[RB][JW]) {
     for (int j = 0; j < JW; ++j) a[rb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
-// acc[rb - R0] = sum_kb W[rb][kb] x in[kb] for rb in [R0, R0 + RB)
-template <int RB, int KB, int R0 = 0>
-__device__ __forceinline__ void gemm_reg(const uint4* __restrict__ W, const bf16x8 (&in)[KB][JW],
-                                         f32x4 (&acc)[RB][JW], int lane) {
-  zero(acc);
+// Weight fragments are staged through LDS, one k-block (RB hi/lo fragment
+// pairs of 2 KB) per stage, double buffered: every wavefront of the workgroup loads a
+// share of stage kb+1 into registers while the MFMAs of stage kb run, then
+// writes it to the other buffer.  All wavefronts of a workgroup call the
+// GEMMs with the same shapes (barriers inside).
+constexpr int kStageMax = 16;                 // row blocks per stage (RB <= 16)
+constexpr int kFragPerRB = kSplit * 64;       // uint4 per (row block, k-block)
+struct Stage {
+  uint4 buf[2][kStageMax * kFragPerRB];
+};
+
+template <int RB>
+constexpr int stage_regs() { return cdiv(RB * kFragPerRB, 256); }
+
+template <int RB, int KB, int R0>
+__device__ __forceinline__ void stage_load(const uint4* __restrict__ W, int kb, uint4 (&reg)[stage_regs<RB>()],
+                                           int tid) {
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const bf16x8 a = ldA(W, KB, R0 + rb, kb, lane);
-#pragma unroll
-      for (int j = 0; j < JW; ++j) acc[rb][j] = mfma(a, in[kb][j], acc[rb][j]);
-    }
+  for (int q = 0; q < stage_regs<RB>(); ++q) {
+    // clamped rather than predicated: the loads stay unconditional, so the
+    // staging registers never leave the register file
+    const int idx = min(tid + 256 * q, RB * kFragPerRB - 1);
+    reg[q] = W[((int64_t)(R0 + idx / kFragPerRB) * KB + kb) * kFragPerRB + (idx % kFragPerRB)];
   }
 }
+template <int RB>
+__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, const uint4 (&reg)[stage_regs<RB>()], int tid) {
+#pragma unroll
+  for (int q = 0; q < stage_regs<RB>(); ++q) {
+    const int idx = tid + 256 * q;
+    if (idx < RB * kFragPerRB) dst[idx] = reg[q];
+  }
+}
+
+// acc[rb] = sum_kb W[R0 + rb][kb] x B(kb) for rb < RB; B(kb, j) supplies
+// the B fragments (registers or memory)
+template <int RB, int KB, int R0, class BF>
+__device__ __forceinline__ void gemm_lds(const uint4* __restrict__ W, Stage& S, BF bfrag, f32x4 (&acc)[RB][JW],
+                                         int lane, int tid) {
+  static_assert(RB <= kStageMax, "stage too small");
+  zero(acc);
+  uint4 reg[stage_regs<RB>()];
+  stage_load<RB, KB, R0>(W, 0, reg, tid);
+  stage_store<RB>(S.buf[0], reg, tid);
+  __syncthreads();
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb + 1 < KB) stage_load<RB, KB, R0>(W, kb + 1, reg, tid);
+    bf16x8 b[JW];
+#pragma unroll
+    for (int j = 0; j < JW; ++j) b[j] = bfrag(kb, j);
+    const uint4* cur = S.buf[kb & 1];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+      for (int h = 0; h < kSplit; ++h) {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, cur[rb * kFragPerRB + h * 64 + lane]);
+#pragma unroll
+        for (int j = 0; j < JW; ++j) acc[rb][j] = mfma(a, b[j], acc[rb][j]);
+      }
+    }
+    if (kb + 1 < KB) stage_store<RB>(S.buf[(kb + 1) & 1], reg, tid);
+    __syncthreads();
+  }
+}
+
+// B fragments held in registers
+template <int KB>
+struct RegB {
+  const bf16x8 (&in)[KB][JW];
+  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const { return in[kb][j]; }
+};
 
 // B fragment of features [32 kb, 32 kb + 32) of a float32 row-major matrix
 // X[t][ld] restricted to columns < kpart (zeros beyond, and for invalid t)
@@ -197,27 +269,58 @@ __device__ __forceinline__ bf16x8 ld_frag32(const float* __restrict__ X, int ld,
   return pack8(lo, hi);
 }
 
-// acc = W [x | s] with x: [t][W] and s: [t][KS] (both float32)
-template <int RB, int KB, int WX, int KS>
-__device__ __forceinline__ void gemm_mem_cat(const uint4* __restrict__ Wt, const float* __restrict__ x,
-                                             const float* __restrict__ s, const int64_t (&t)[JW],
-                                             const bool (&valid)[JW], f32x4 (&acc)[RB][JW], int lane) {
-  const int g = lane >> 4;
-  zero(acc);
-  for (int kb = 0; kb < KB; ++kb) {
-    bf16x8 b[JW];
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      if (32 * kb < WX) b[j] = ld_frag32(x, WX, t[j], valid[j], kb, WX, g);
-      else b[j] = ld_frag32(s, KS, t[j], valid[j], kb - WX / 32, KS, g);
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const bf16x8 a = ldA(Wt, KB, rb, kb, lane);
-#pragma unroll
-      for (int j = 0; j < JW; ++j) acc[rb][j] = mfma(a, b[j], acc[rb][j]);
-    }
+// B fragments of [x | s] (x: [t][WX], s: [t][KS], float32) from memory
+template <int WX, int KS>
+struct CatB {
+  const float* x;
+  const float* s;
+  const int64_t* t;
+  const bool* valid;
+  int g;
+  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const {
+    if (32 * kb < WX) return ld_frag32(x, WX, t[j], valid[j], kb, WX, g);
+    return ld_frag32(s, KS, t[j], valid[j], kb - WX / 32, KS, g);
   }
+};
+
+template <int K>
+struct MemB {
+  const float* x;
+  const int64_t* t;
+  const bool* valid;
+  int g;
+  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const { return ld_frag32(x, K, t[j], valid[j], kb, K, g); }
+};
+
+// Register-fed layer computed in NP passes over its RBO output row blocks
+// (accumulators for RBO/NP blocks at a time; every weight fragment is still
+// loaded once).  epi(rb, j, v) finalises a block in place; with FRAGS the
+// finalised values also become the B fragments `out` of the next layer.
+constexpr int np_of(int rbo) { return rbo >= 8 ? 2 : 1; }
+
+template <int RBO, int KB, int NP, bool FRAGS, class EPI>
+__device__ __forceinline__ void layer_reg(const uint4* __restrict__ W, Stage& S, const bf16x8 (&in)[KB][JW],
+                                          bf16x8 (&out)[cdiv(RBO, 2)][JW], EPI epi, int lane, int tid) {
+  static_assert(RBO % NP == 0, "passes must split the rows evenly");
+  constexpr int RP = RBO / NP;
+  static_assert(NP == 1 || RP % 2 == 0, "a pass must hold whole k-blocks of the next layer");
+  static_for<0, NP>([&](auto P) __attribute__((always_inline)) {
+    constexpr int p = decltype(P)::value;
+    f32x4 acc[RP][JW];
+    gemm_lds<RP, KB, p * RP>(W, S, RegB<KB>{in}, acc, lane, tid);
+#pragma unroll
+    for (int rb = 0; rb < RP; ++rb)
+#pragma unroll
+      for (int j = 0; j < JW; ++j) epi(p * RP + rb, j, acc[rb][j]);
+    if constexpr (FRAGS) {
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < cdiv(RP, 2); ++kb)
+#pragma unroll
+        for (int j = 0; j < JW; ++j)
+          out[p * RP / 2 + kb][j] = pack8(acc[2 * kb][j], (2 * kb + 1 < RP) ? acc[2 * kb + 1][j] : z);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -263,11 +366,14 @@ struct Cols {
   float u[JW];
 };
 
+// Columns of this wavefront's tile.  Returns false (for the whole
+// workgroup, uniformly) when the workgroup has no edges; wavefronts past the
+// end run with all columns invalid so the workgroup's barriers stay matched.
 __device__ __forceinline__ bool tile_cols(const ChainArgs& a, int64_t tile, int lane, int64_t& e0, Cols& c) {
   int64_t e1;
   a.rr.get(e0, e1);
   const int64_t M = e1 - e0;
-  if (tile * TILE >= M) return false;
+  if ((int64_t)blockIdx.x * WAVES * TILE >= M) return false;
 #pragma unroll
   for (int j = 0; j < JW; ++j) {
     c.t[j] = tile * TILE + 16 * j + (lane & 15);
@@ -277,36 +383,43 @@ __device__ __forceinline__ bool tile_cols(const ChainArgs& a, int64_t tile, int 
   return true;
 }
 
+#define AFM_CHAIN_PROLOGUE                                                   \
+  __shared__ Stage S;                                                        \
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;               \
+  const int64_t tile = (int64_t)blockIdx.x * WAVES + (tid >> 6);             \
+  int64_t e0;                                                                \
+  Cols c;                                                                    \
+  if (!tile_cols(a, tile, lane, e0, c)) return;
+
 // ---------------------------------------------------------------------------
 // two-body MLP + environment embedding of layer 1 (forward)
 
 template <int T0, int T1, int T2, int W, int ENV>
 __global__ void __launch_bounds__(256) k_tb_fwd(ChainArgs a) {
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
-  int64_t e0;
-  Cols c;
-  if (!tile_cols(a, tile, lane, e0, c)) return;
+  AFM_CHAIN_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int TL = NT == 3 ? T2 : T1;
   static_assert(TL == W, "last two-body width must equal the latent width");
   // first layer on the vector ALUs: gathers of the one-hot columns + rho
   constexpr int RB0 = cdiv(T0, 16);
-  f32x4 h0[RB0][JW];
+  bf16x8 in0[cdiv(RB0, 2)][JW];
   {
+    f32x4 h0[RB0][JW];
     const int K0 = 2 * a.S + a.nb;
 #pragma unroll
     for (int j = 0; j < JW; ++j) {
       float rho[16];
       int zi = 0, zj = 0;
+#pragma unroll
+      for (int n = 0; n < 16; ++n) rho[n] = 0.0f;
       if (c.valid[j]) {
         const float r = a.geo[c.t[j] * GEO_STRIDE + GEO_D];
         const float pre = sqrtf(2.0f / a.r_cut) / r * c.u[j];
-        for (int n = 0; n < a.nb; ++n) rho[n] = pre * __sinf((n + 1) * 3.14159265358979323846f * r / a.r_cut);
+#pragma unroll
+        for (int n = 0; n < 16; ++n)
+          if (n < a.nb) rho[n] = pre * __sinf((n + 1) * 3.14159265358979323846f * r / a.r_cut);
         zi = min(max(a.species[a.eidx[c.t[j]]], 0), a.S - 1);
         zj = min(max(a.species[a.col[e0 + c.t[j]]], 0), a.S - 1);
-      } else {
-        for (int n = 0; n < 16; ++n) rho[n] = 0.0f;
       }
 #pragma unroll
       for (int rb = 0; rb < RB0; ++rb) {
@@ -314,13 +427,15 @@ __global__ void __launch_bounds__(256) k_tb_fwd(ChainArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int f = 16 * rb + 4 * g + q;
-          float s = 0.0f;
+          float sacc = 0.0f;
           if (f < T0 && c.valid[j]) {
             const float* w = a.w0 + (int64_t)f * K0;
-            s = w[zi] + w[a.S + zj];
-            for (int n = 0; n < a.nb; ++n) s += w[2 * a.S + n] * rho[n];
+            sacc = w[zi] + w[a.S + zj];
+#pragma unroll
+            for (int n = 0; n < 16; ++n)
+              if (n < a.nb) sacc += w[2 * a.S + n] * rho[n];
           }
-          v[q] = s;
+          v[q] = sacc;
         }
         st_pre(a.pre[0], tile, RB0, rb, j, lane, v);
 #pragma unroll
@@ -328,61 +443,35 @@ __global__ void __launch_bounds__(256) k_tb_fwd(ChainArgs a) {
         h0[rb][j] = v;
       }
     }
+    to_frags<RB0>(h0, in0);
   }
-  bf16x8 in0[cdiv(RB0, 2)][JW];
-  to_frags<RB0>(h0, in0);
   constexpr int RB1 = cdiv(T1, 16);
-  f32x4 h1[RB1][JW];
-  gemm_reg<RB1, cdiv(RB0, 2)>(a.tbf[1], in0, h1, lane);
-  constexpr bool LAST1 = NT == 2;
-#pragma unroll
-  for (int rb = 0; rb < RB1; ++rb)
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      st_pre(a.pre[1], tile, RB1, rb, j, lane, h1[rb][j]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float v = h1[rb][j][q];
-        h1[rb][j][q] = LAST1 ? c.u[j] * v * sigm(v) : v * sigm(v);
-      }
-    }
   constexpr int RBW = W / 16;
+  auto silu_epi = [&](uint2* pre, int RB, bool env_out) {
+    return [=, &c](int rb, int j, f32x4& v) {
+      st_pre(pre, tile, RB, rb, j, lane, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = env_out ? c.u[j] * v[q] * sigm(v[q]) : v[q] * sigm(v[q]);
+      if (env_out && c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, v);
+    };
+  };
   bf16x8 xin[W / 32][JW];
   if constexpr (NT == 3) {
     bf16x8 in1[cdiv(RB1, 2)][JW];
-    to_frags<RB1>(h1, in1);
-    f32x4 h2[RBW][JW];
-    gemm_reg<RBW, cdiv(RB1, 2)>(a.tbf[2], in1, h2, lane);
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        st_pre(a.pre[2], tile, RBW, rb, j, lane, h2[rb][j]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float v = h2[rb][j][q];
-          h2[rb][j][q] = c.u[j] * v * sigm(v);
-        }
-        if (c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, h2[rb][j]);
-      }
-    to_frags<RBW>(h2, xin);
+    layer_reg<RB1, cdiv(RB0, 2), 1, true>(a.tbf[1], S, in0, in1, silu_epi(a.pre[1], RB1, false), lane, tid);
+    layer_reg<RBW, cdiv(RB1, 2), np_of(RBW), true>(a.tbf[2], S, in1, xin, silu_epi(a.pre[2], RBW, true), lane, tid);
   } else {
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, h1[rb][j]);
-    to_frags<RB1>(h1, xin);
+    layer_reg<RB1, cdiv(RB0, 2), 1, true>(a.tbf[1], S, in0, xin, silu_epi(a.pre[1], RB1, true), lane, tid);
   }
   // omega^1 = W_env^1 x^0
   constexpr int RBE = ENV / 16;
-  f32x4 om[RBE][JW];
-  gemm_reg<RBE, W / 32>(a.envf, xin, om, lane);
-#pragma unroll
-  for (int rb = 0; rb < RBE; ++rb)
-#pragma unroll
-    for (int j = 0; j < JW; ++j)
-      if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, om[rb][j]);
+  bf16x8 unused[cdiv(RBE, 2)][JW];
+  layer_reg<RBE, W / 32, np_of(RBE), false>(
+      a.envf, S, xin, unused,
+      [&](int rb, int j, f32x4& v) {
+        if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, v);
+      },
+      lane, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,72 +479,78 @@ __global__ void __launch_bounds__(256) k_tb_fwd(ChainArgs a) {
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
 __global__ void __launch_bounds__(256) k_lat_fwd(ChainArgs a) {
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
-  int64_t e0;
-  Cols c;
-  if (!tile_cols(a, tile, lane, e0, c)) return;
+  AFM_CHAIN_PROLOGUE
   constexpr int RBW = W / 16, KBW = W / 32;
   constexpr int KIN = W + KS;
-  f32x4 h[RBW][JW];
-  gemm_mem_cat<RBW, cdiv(KIN, 32), W, KS>(a.latf[0], a.xprev, a.s, c.t, c.valid, h, lane);
   const float r2 = 0.70710678118654752f;
-#pragma unroll
-  for (int k = 0; k < DEPTH; ++k) {
-    if (k > 0) {
-      bf16x8 in[KBW][JW];
-      to_frags<RBW>(h, in);
-      gemm_reg<RBW, KBW>(a.latf[k], in, h, lane);
-    }
-    const bool last = k == DEPTH - 1;
+  bf16x8 in[KBW][JW];
+  {
+    f32x4 h[RBW][JW];
+    gemm_lds<RBW, cdiv(KIN, 32), 0>(a.latf[0], S, CatB<W, KS>{a.xprev, a.s, c.t, c.valid, g}, h, lane, tid);
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
       for (int j = 0; j < JW; ++j) {
-        st_pre(a.pre[k], tile, RBW, rb, j, lane, h[rb][j]);
-        if (!last) {
+        st_pre(a.pre[0], tile, RBW, rb, j, lane, h[rb][j]);
+        if (DEPTH > 1) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float v = h[rb][j][q];
-            h[rb][j][q] = v * sigm(v);
-          }
+          for (int q = 0; q < 4; ++q) h[rb][j][q] = h[rb][j][q] * sigm(h[rb][j][q]);
         } else {
           const f32x4 xp = c.valid[j] ? ld4(a.xprev + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float v = h[rb][j][q];
-            h[rb][j][q] = (xp[q] + c.u[j] * v * sigm(v)) * r2;
-          }
+          for (int q = 0; q < 4; ++q) h[rb][j][q] = (xp[q] + c.u[j] * h[rb][j][q] * sigm(h[rb][j][q])) * r2;
+          if (!LAST && c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, h[rb][j]);
         }
       }
+    to_frags<RBW>(h, in);
   }
+  float ep[JW];
+#pragma unroll
+  for (int j = 0; j < JW; ++j) ep[j] = 0.0f;
+  static_for<1, DEPTH>([&](auto K) __attribute__((always_inline)) {
+    constexpr int k = decltype(K)::value;
+    constexpr bool last = k == DEPTH - 1;
+    bf16x8 out[KBW][JW];
+    layer_reg<RBW, KBW, np_of(RBW), true>(
+        a.latf[k], S, in, out,
+        [&](int rb, int j, f32x4& v) {
+          st_pre(a.pre[k], tile, RBW, rb, j, lane, v);
+          if constexpr (!last) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
+          } else {
+            const f32x4 xp = c.valid[j] ? ld4(a.xprev + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = (xp[q] + c.u[j] * v[q] * sigm(v[q])) * r2;
+            if constexpr (!LAST) {
+              if (c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, v);
+            } else {
+              const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) ep[j] += we[q] * v[q];
+            }
+          }
+        },
+        lane, tid);
+#pragma unroll
+    for (int kb = 0; kb < KBW; ++kb)
+#pragma unroll
+      for (int j = 0; j < JW; ++j) in[kb][j] = out[kb][j];
+  });
   if constexpr (!LAST) {
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, h[rb][j]);
-    bf16x8 xin[KBW][JW];
-    to_frags<RBW>(h, xin);
     constexpr int RBE = ENV / 16;
-    f32x4 om[RBE][JW];
-    gemm_reg<RBE, KBW>(a.envf, xin, om, lane);
-#pragma unroll
-    for (int rb = 0; rb < RBE; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, om[rb][j]);
+    bf16x8 unused[cdiv(RBE, 2)][JW];
+    layer_reg<RBE, KBW, np_of(RBE), false>(
+        a.envf, S, in, unused,
+        [&](int rb, int j, f32x4& v) {
+          if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, v);
+        },
+        lane, tid);
   } else {
     // eps_e = w_eff . x^{N_L}
 #pragma unroll
     for (int j = 0; j < JW; ++j) {
-      float p = 0.0f;
-#pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-        const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) p += we[q] * h[rb][j][q];
-      }
+      float p = ep[j];
       p += __shfl_xor(p, 16, 64);
       p += __shfl_xor(p, 32, 64);
       if (g == 0 && c.valid[j]) a.eps[e0 + c.t[j]] = p;
@@ -468,122 +563,111 @@ __global__ void __launch_bounds__(256) k_lat_fwd(ChainArgs a) {
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
 __global__ void __launch_bounds__(256) k_lat_bwd(ChainArgs a) {
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
-  int64_t e0;
-  Cols c;
-  if (!tile_cols(a, tile, lane, e0, c)) return;
+  AFM_CHAIN_PROLOGUE
   constexpr int RBW = W / 16, KBW = W / 32;
   const float r2 = 0.70710678118654752f;
-  f32x4 G[RBW][JW];
-  if constexpr (LAST) {
-    // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
+  bf16x8 in[KBW][JW];
+  {
+    f32x4 G[RBW][JW];
+    if constexpr (LAST) {
+      // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
 #pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      float ce = 0.0f;
-      if (c.valid[j]) {
-        const int64_t i = a.eidx[c.t[j]];
-        ce = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
-        if (a.ges) {
-          int64_t lo = 0, hi = a.B;
-          while (hi - lo > 1) {
-            int64_t mid = (lo + hi) >> 1;
-            if (a.seg[mid] <= i) lo = mid; else hi = mid;
+      for (int j = 0; j < JW; ++j) {
+        float ce = 0.0f;
+        if (c.valid[j]) {
+          const int64_t i = a.eidx[c.t[j]];
+          ce = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
+          if (a.ges) {
+            int64_t lo = 0, hi = a.B;
+            while (hi - lo > 1) {
+              int64_t mid = (lo + hi) >> 1;
+              if (a.seg[mid] <= i) lo = mid; else hi = mid;
+            }
+            ce *= (float)a.ges[lo];
           }
-          ce *= (float)a.ges[lo];
+        }
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb) {
+          const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) G[rb][j][q] = ce * we[q];
         }
       }
+    } else {
+      // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
+      gemm_lds<RBW, cdiv(ENV, 32), 0>(a.envb, S, MemB<ENV>{a.gomega, c.t, c.valid, g}, G, lane, tid);
 #pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-        const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+      for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) G[rb][j][q] = ce * we[q];
-      }
+        for (int j = 0; j < JW; ++j)
+          if (c.valid[j]) G[rb][j] += ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g);
     }
-  } else {
-    // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
-    zero(G);
-    for (int kb = 0; kb < cdiv(ENV, 32); ++kb) {
-      bf16x8 b[JW];
+    // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2
+    float gu[JW];
 #pragma unroll
-      for (int j = 0; j < JW; ++j) b[j] = ld_frag32(a.gomega, ENV, c.t[j], c.valid[j], kb, ENV, g);
-#pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-        const bf16x8 A = ldA(a.envb, cdiv(ENV, 32), rb, kb, lane);
-#pragma unroll
-        for (int j = 0; j < JW; ++j) G[rb][j] = mfma(A, b[j], G[rb][j]);
-      }
-    }
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) G[rb][j] += ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g);
-  }
-  // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2
-  float gu[JW];
-#pragma unroll
-  for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
-#pragma unroll
-  for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, j, lane);
-      f32x4 res;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float gs_ = G[rb][j][q] * r2;
-        const float sg = sigm(pa[q]);
-        res[q] = gs_;
-        gu[j] += gs_ * pa[q] * sg;
-        G[rb][j][q] = gs_ * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
-      }
-      if (c.valid[j]) st4(a.gx + c.t[j] * W + 16 * rb + 4 * g, res);
-    }
-#pragma unroll
-  for (int j = 0; j < JW; ++j) {
-    float v = gu[j];
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
-  }
-  // inner layers: ga_{k-1} = (W_k^T ga_k) * silu'(a_{k-1})
-#pragma unroll
-  for (int k = DEPTH - 1; k >= 1; --k) {
-    bf16x8 in[KBW][JW];
-    to_frags<RBW>(G, in);
-    gemm_reg<RBW, KBW>(a.latb[k], in, G, lane);
+    for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
       for (int j = 0; j < JW; ++j) {
-        const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, j, lane);
+        const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, j, lane);
+        f32x4 res;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          const float gs_ = G[rb][j][q] * r2;
           const float sg = sigm(pa[q]);
-          G[rb][j][q] *= sg * (1.0f + pa[q] * (1.0f - sg));
+          res[q] = gs_;
+          gu[j] += gs_ * pa[q] * sg;
+          G[rb][j][q] = gs_ * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
         }
+        if (c.valid[j]) st4(a.gx + c.t[j] * W + 16 * rb + 4 * g, res);
       }
+#pragma unroll
+    for (int j = 0; j < JW; ++j) {
+      float v = gu[j];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
+    }
+    to_frags<RBW>(G, in);
   }
-  // dE/d[x | s] = W_1^T ga_1, in two passes (x rows, then s rows)
-  bf16x8 in[KBW][JW];
-  to_frags<RBW>(G, in);
+  // inner layers: ga_{k-1} = (W_k^T ga_k) * silu'(a_{k-1})
+  static_for<1, DEPTH>([&](auto KK) __attribute__((always_inline)) {
+    constexpr int k = DEPTH - decltype(KK)::value;
+    bf16x8 out[KBW][JW];
+    layer_reg<RBW, KBW, np_of(RBW), true>(
+        a.latb[k], S, in, out,
+        [&](int rb, int j, f32x4& v) {
+          const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, j, lane);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float sg = sigm(pa[q]);
+            v[q] *= sg * (1.0f + pa[q] * (1.0f - sg));
+          }
+        },
+        lane, tid);
+#pragma unroll
+    for (int kb = 0; kb < KBW; ++kb)
+#pragma unroll
+      for (int j = 0; j < JW; ++j) in[kb][j] = out[kb][j];
+  });
+  // dE/d[x | s] = W_1^T ga_1: x rows added to the residual share, s rows stored
   {
-    f32x4 ox[RBW][JW];
-    gemm_reg<RBW, KBW, 0>(a.latb[0], in, ox, lane);
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) {
-          float* p = a.gx + c.t[j] * W + 16 * rb + 4 * g;
-          st4(p, ld4(p) + ox[rb][j]);
-        }
+    bf16x8 unused[KBW][JW];
+    layer_reg<RBW, KBW, np_of(RBW), false>(
+        a.latb[0], S, in, unused,
+        [&](int rb, int j, f32x4& v) {
+          if (c.valid[j]) {
+            float* p = a.gx + c.t[j] * W + 16 * rb + 4 * g;
+            st4(p, ld4(p) + v);
+          }
+        },
+        lane, tid);
   }
   {
     constexpr int RBS = KS / 16;
     f32x4 os[RBS][JW];
-    gemm_reg<RBS, KBW, RBW>(a.latb[0], in, os, lane);
+    gemm_lds<RBS, KBW, RBW>(a.latb[0], S, RegB<KBW>{in}, os, lane, tid);
 #pragma unroll
     for (int rb = 0; rb < RBS; ++rb)
 #pragma unroll
@@ -597,91 +681,74 @@ __global__ void __launch_bounds__(256) k_lat_bwd(ChainArgs a) {
 
 template <int T0, int T1, int T2, int W, int ENV>
 __global__ void __launch_bounds__(256) k_tb_bwd(ChainArgs a) {
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
-  int64_t e0;
-  Cols c;
-  if (!tile_cols(a, tile, lane, e0, c)) return;
+  AFM_CHAIN_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int RBW = W / 16;
-  f32x4 G[RBW][JW];
-  zero(G);
-  for (int kb = 0; kb < cdiv(ENV, 32); ++kb) {
-    bf16x8 b[JW];
+  constexpr int RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16);
+  bf16x8 in[RBW / 2][JW];
+  {
+    f32x4 G[RBW][JW];
+    gemm_lds<RBW, cdiv(ENV, 32), 0>(a.envb, S, MemB<ENV>{a.gomega, c.t, c.valid, g}, G, lane, tid);
+    // head: x^0 = u silu(a_last)
+    float gu[JW];
 #pragma unroll
-    for (int j = 0; j < JW; ++j) b[j] = ld_frag32(a.gomega, ENV, c.t[j], c.valid[j], kb, ENV, g);
+    for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb) {
-      const bf16x8 A = ldA(a.envb, cdiv(ENV, 32), rb, kb, lane);
+    for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
-      for (int j = 0; j < JW; ++j) G[rb][j] = mfma(A, b[j], G[rb][j]);
-    }
-  }
-  // head: x^0 = u silu(a_last)
-  float gu[JW];
+      for (int j = 0; j < JW; ++j) {
+        const f32x4 gx = c.valid[j] ? ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, j, lane);
 #pragma unroll
-  for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
-#pragma unroll
-  for (int rb = 0; rb < RBW; ++rb)
+        for (int q = 0; q < 4; ++q) {
+          const float gv = G[rb][j][q] + gx[q];
+          const float sg = sigm(pa[q]);
+          gu[j] += gv * pa[q] * sg;
+          G[rb][j][q] = gv * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
+        }
+      }
 #pragma unroll
     for (int j = 0; j < JW; ++j) {
-      const f32x4 gx = c.valid[j] ? ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
-      const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, j, lane);
+      float v = gu[j];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
+    }
+    to_frags<RBW>(G, in);
+  }
+  auto dsilu_epi = [&](uint2* pre, int RB) {
+    return [=](int rb, int j, f32x4& v) {
+      const f32x4 pa = ld_pre(pre, tile, RB, rb, j, lane);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float gv = G[rb][j][q] + gx[q];
         const float sg = sigm(pa[q]);
-        gu[j] += gv * pa[q] * sg;
-        G[rb][j][q] = gv * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
+        v[q] *= sg * (1.0f + pa[q] * (1.0f - sg));
       }
-    }
-#pragma unroll
-  for (int j = 0; j < JW; ++j) {
-    float v = gu[j];
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
-  }
-  constexpr int RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16);
-  f32x4 G1[RB1][JW];
+    };
+  };
+  bf16x8 in1[cdiv(RB1, 2)][JW];
   if constexpr (NT == 3) {
-    bf16x8 in[RBW / 2][JW];
-    to_frags<RBW>(G, in);
-    gemm_reg<RB1, RBW / 2>(a.tbb[2], in, G1, lane);
-#pragma unroll
-    for (int rb = 0; rb < RB1; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        const f32x4 pa = ld_pre(a.pre[1], tile, RB1, rb, j, lane);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float sg = sigm(pa[q]);
-          G1[rb][j][q] *= sg * (1.0f + pa[q] * (1.0f - sg));
-        }
-      }
+    layer_reg<RB1, RBW / 2, np_of(RB1), true>(a.tbb[2], S, in, in1, dsilu_epi(a.pre[1], RB1), lane,
+                                                          tid);
   } else {
 #pragma unroll
-    for (int rb = 0; rb < RB1; ++rb)
+    for (int kb = 0; kb < cdiv(RB1, 2); ++kb)
 #pragma unroll
-      for (int j = 0; j < JW; ++j) G1[rb][j] = G[rb][j];
+      for (int j = 0; j < JW; ++j) in1[kb][j] = in[kb][j];
   }
   f32x4 G0[RB0][JW];
-  {
-    bf16x8 in[cdiv(RB1, 2)][JW];
-    to_frags<RB1>(G1, in);
-    gemm_reg<RB0, cdiv(RB1, 2)>(a.tbb[1], in, G0, lane);
+  gemm_lds<RB0, cdiv(RB1, 2), 0>(a.tbb[1], S, RegB<cdiv(RB1, 2)>{in1}, G0, lane, tid);
 #pragma unroll
-    for (int rb = 0; rb < RB0; ++rb)
+  for (int rb = 0; rb < RB0; ++rb)
 #pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, j, lane);
+    for (int j = 0; j < JW; ++j) {
+      const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, j, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float sg = sigm(pa[q]);
-          G0[rb][j][q] *= sg * (1.0f + pa[q] * (1.0f - sg));
-        }
+      for (int q = 0; q < 4; ++q) {
+        const float sg = sigm(pa[q]);
+        G0[rb][j][q] *= sg * (1.0f + pa[q] * (1.0f - sg));
       }
-  }
+    }
   // dE/drho_n = sum_f W_0[f][2S + n] ga_0[f]
   const int K0 = 2 * a.S + a.nb;
 #pragma unroll

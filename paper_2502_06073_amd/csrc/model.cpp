@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "cg_ct.h"
+#include "edge_layout.h"
 #include "internal.h"
 
 namespace afm {
@@ -186,6 +188,20 @@ int real_cg(int l1, int l2, int l3, double* out) {
   if (first < 0)
     for (int q = 0; q < d1 * d2 * d3; ++q) out[q] = -out[q] + 0.0;
   return AFM_OK;
+}
+
+// the kernels' compile-time tables must equal the runtime derivation
+static bool cg_tables_agree() {
+  double buf[125];
+  for (int a = 0; a <= kMaxLmax; ++a)
+    for (int b = 0; b <= kMaxLmax; ++b)
+      for (int c = abs(a - b); c <= a + b && c <= kMaxLmax; ++c) {
+        real_cg(a, b, c, buf);
+        const ct::Tensor T = ct::real_cg(a, b, c);
+        for (int q = 0; q < (2 * a + 1) * (2 * b + 1) * (2 * c + 1); ++q)
+          if (fabs(T.v[q] - buf[q]) > 1e-12) return false;
+      }
+  return true;
 }
 
 static std::vector<float> cg_table_f32() {
@@ -383,11 +399,81 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
   if (e != hipSuccess) { set_error(hipGetErrorString(e)); delete m; return AFM_E_HIP; }
   rc = pack_weights(m, weights);
   if (rc) { if (m->dev_mem) (void)hipFree(m->dev_mem); delete m; return rc; }
+  if (!cg_tables_agree()) {
+    set_error("internal: compile-time and runtime CG tables differ");
+    (void)hipFree(m->dev_mem);
+    delete m;
+    return AFM_E_INVALID;
+  }
   std::vector<float> cg = cg_table_f32();
   rc = upload_cg_table(cg.data());
   if (!rc) rc = upload_cg_table_second_order(cg.data());
   if (rc) { (void)hipFree(m->dev_mem); delete m; return rc; }
   *out = m;
+  return AFM_OK;
+}
+
+int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int32_t* n) {
+  if (!hp || !n || (max > 0 && !out)) { set_error("null argument"); return AFM_E_INVALID; }
+  ModelDims d{};
+  int rc = dims_of(hp, &d);
+  if (rc) return rc;
+  const Plan P = make_plan(d.lmax, d.NL);
+  const double C = d.c, W = d.w, ENV = (d.lmax + 1) * d.c, NLM = (d.lmax + 1) * (d.lmax + 1);
+  double tbm = (double)d.nb * d.tb[0], tbpre = d.tb[0];
+  for (int k = 1; k < d.ntb; ++k) {
+    tbm += (double)d.tb[k - 1] * d.tb[k];
+    tbpre += d.tb[k];
+  }
+  std::vector<afm_stage_cost> v;
+  auto add = [&](const char* name, int idx, int kind, double fl, double be, double ba) {
+    afm_stage_cost c{};
+    if (idx > 0) snprintf(c.name, sizeof c.name, "%s%d", name, idx);
+    else snprintf(c.name, sizeof c.name, "%s", name);
+    c.kind = kind;
+    c.flops_per_edge = fl;
+    c.bytes_per_edge = be;
+    c.bytes_per_atom = ba;
+    v.push_back(c);
+  };
+  // col + shift + two positions in, geometry record + row index out
+  add("geometry", 0, 1, 60.0, 4 + 3 + 48 + 4.0 * (GEO_Y + 9) + 4, 0);
+  // x^0, omega^1 and the stored pre-activations out
+  add("twobody_fwd", 0, 0, 2.0 * (tbm + W * ENV), 8 + 4 * (W + ENV) + 2 * tbpre, 0);
+  add("twobody_bwd", 0, 0, 2.0 * (tbm + W * ENV), 4 * (ENV + W) + 2 * tbpre + 4 * (d.nb + 1), 0);
+  for (int L = 1; L <= d.NL; ++L) {
+    const LayerPlan& lp = P.layer[L - 1];
+    const bool last = L == d.NL;
+    double nz = 0, outc = 0;
+    std::vector<double> buf(125);
+    for (int k = 0; k < lp.n_paths; ++k) {
+      const PathT& t = lp.p[k];
+      real_cg(t.l1, t.l2, t.l3, buf.data());
+      for (int q = 0; q < (2 * t.l1 + 1) * (2 * t.l2 + 1) * (2 * t.l3 + 1); ++q) nz += std::fabs(buf[q]) > 1e-12;
+      outc += 2 * t.l3 + 1;
+    }
+    const double vin = L == 1 ? 0.0 : lp.n_in_comps * C;      // V^L read from memory (layer 1: built from omega)
+    const double vout = last ? 0.0 : lp.n_out_comps * C;
+    const double s_out = lp.n0e * C;
+    // environment sum (NLM C fma) + nonzero CG products (2 mul + add each) + alpha mixing
+    const double tpf = 2 * NLM * C + 3 * nz * C + (last ? 0 : 2 * outc * C) + (L == 1 ? NLM * C : 0);
+    add("tp_fwd", L, 1, tpf, 4 * (ENV + NLM + vin + s_out + vout), 4 * NLM * C);
+    // adjoint: twice the products (dV and dGamma), the mixing, the environment-sum adjoint
+    const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + (L == 1 ? 2 * NLM * C : 0);
+    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + vin + s_out + vout + ENV + vin + NLM), 4 * NLM * C);
+    const double lat = (W + lp.n0e * C) * W + (d.depth - 1) * W * W;
+    add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),
+        4 * (W + s_out + (last ? 1 : W + ENV) + 1) + 2 * d.depth * W, 0);
+    add("latent_bwd", L, 0, 2.0 * (lat + (last ? 0 : W * ENV)),
+        4 * ((last ? 0 : ENV) + W + W + s_out + 1) + 2 * d.depth * W + 4, 0);
+  }
+  // rho and u adjoints in, dE/d delta out
+  add("geometry_bwd", 0, 1, 40.0 + 4.0 * d.nb, 4.0 * (GEO_Y + 9) + 4 * (16 + 16) + 12, 0);
+  add("energy", 0, 1, 1.0, 4, 8 + 4 + 8);
+  // dE/d delta of the edge and of its reverse, col, rev, shift in; forces + virial per atom out
+  add("force_scatter", 0, 1, 12.0 + 18.0, 12 + 12 + 4 + 4 + 3, 24 + 72);
+  *n = (int32_t)v.size();
+  for (int32_t k = 0; k < max && k < (int32_t)v.size(); ++k) out[k] = v[k];
   return AFM_OK;
 }
 

@@ -5,18 +5,19 @@
 // (256 / C) edge slots x C channels, channel fastest so every load is
 // coalesced over channels.
 //   forward:  Gamma_i[lm][n] = nbar^-1/2 sum_{e in row i} omega_e[l][n] Y_e[lm]
-//             M^pi_i[m1][m3][n] = sum_m2 C^{l1 l2 l3}[m1][m2][m3] Gamma_i[l2 m2][n]
-//             T^pi_e[m3][n] = sum_m1 V_e[l1 p1, m1][n] M^pi_i[m1][m3][n]
+//             T^pi_e[m3][n] = sum C^{l1 l2 l3}[m1][m2][m3] V_e[l1 p1, m1][n] Gamma_i[l2 m2][n]
 //             s_e (0e paths), V'_e = sum_pi alpha[pi][n] T^pi_e   (next layer)
-//   backward: the adjoints of the three lines above; the adjoint of M is
-//             accumulated per thread in registers over the row's edges,
-//             reduced over slots in LDS, then contracted back to Gamma.
-// The per-atom precontraction M turns the per-edge product into small dense
-// (2l1+1) x (2l3+1) products with compile-time shapes.
+//   backward: the adjoints of both lines; dE/dGamma_i is accumulated per
+//             thread over the row's edges (9 registers) and reduced over the
+//             edge slots in LDS.
+// The sums run over the nonzero CG entries only, unrolled with immediate
+// coefficients from the compile-time tables (cg_ct.h); Gamma_i of the
+// thread's channel stays in registers for the whole row.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
 #include "gemm_f32.h"
+#include "cg_ct.h"
 #include "internal.h"
 
 namespace afm {
@@ -35,35 +36,8 @@ struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
 };
 
-// M^pi for every path of the layer into LDS (paths split over slots)
 template <int LMAX, int NL, int L, int C>
-__device__ __forceinline__ void build_M(float* Ms, const float* gam, int n, int slot) {
-  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
-  constexpr int NS = 256 / C;
-  static_for<0, LP.n_paths>([&](auto K) {
-    constexpr PathT pt = LP.p[decltype(K)::value];
-    constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
-    constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
-    if (decltype(K)::value % NS == slot) {
-      float g[d2];
-#pragma unroll
-      for (int m2 = 0; m2 < d2; ++m2) g[m2] = gam[(pt.l2 * pt.l2 + m2) * C + n];
-#pragma unroll
-      for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-        for (int m3 = 0; m3 < d3; ++m3) {
-          float acc = 0.0f;
-#pragma unroll
-          for (int m2 = 0; m2 < d2; ++m2) acc += c_cg[off + (m1 * d2 + m2) * d3 + m3] * g[m2];
-          Ms[(pt.m_off + m1 * d3 + m3) * C + n] = acc;
-        }
-    }
-  });
-}
-
-template <int LMAX, int NL, int L, int C>
-__device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const float* Y,
-                                       float* V) {
+__device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const float* Y, float* V) {
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   if constexpr (L == 1) {
 #pragma unroll
@@ -78,13 +52,25 @@ __device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const 
   }
 }
 
+// T^pi[m3] = sum over the nonzeros of C^{l1 l2 l3}: C V[m1] Gamma[m2]
+template <int LMAX, int NL, int L, int K>
+__device__ __forceinline__ void path_fwd(const float* V, const float* G, float* T) {
+  constexpr PathT pt = LayerCT<LMAX, NL, L>::lp.p[K];
+  constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+#pragma unroll
+  for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) T[m3] = 0.0f;
+  static_for<0, nz.n>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    T[nz.m3[q]] += nz.c[q] * V[pt.in_off + nz.m1[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+  });
+}
+
 template <int LMAX, int NL, int L, int C>
 __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NS = 256 / C;
   constexpr int NCI = LP.n_in_comps, NCO = LP.n_out_comps > 0 ? LP.n_out_comps : 1;
-  __shared__ float Ms[LP.m_size * C];
   __shared__ float red[NS * NLM * C];
   __shared__ float gam[NLM * C];
   const int n = threadIdx.x % C, slot = threadIdx.x / C;
@@ -117,8 +103,9 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
       a.gamma[(i * NLM + q) * C + n] = g;
     }
     __syncthreads();
-    build_M<LMAX, NL, L, C>(Ms, gam, n, slot);
-    __syncthreads();
+    float G[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
@@ -130,20 +117,13 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
       static_for<0, LP.n_paths>([&](auto K) {
         constexpr int k = decltype(K)::value;
         constexpr PathT pt = LP.p[k];
-        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
-        float T[d3];
-#pragma unroll
-        for (int m3 = 0; m3 < d3; ++m3) {
-          float v = 0.0f;
-#pragma unroll
-          for (int m1 = 0; m1 < d1; ++m1) v += V[pt.in_off + m1] * Ms[(pt.m_off + m1 * d3 + m3) * C + n];
-          T[m3] = v;
-        }
+        float T[2 * pt.l3 + 1];
+        path_fwd<LMAX, NL, L, k>(V, G, T);
         if constexpr (pt.s_idx >= 0) a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
         if constexpr (pt.out_off >= 0) {
           const float al = a.alpha[k * C + n];
 #pragma unroll
-          for (int m3 = 0; m3 < d3; ++m3) out[pt.out_off + m3] += al * T[m3];
+          for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) out[pt.out_off + m3] += al * T[m3];
         }
       });
       if constexpr (LP.n_out_comps > 0) {
@@ -161,36 +141,30 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NS = 256 / C;
   constexpr int NCI = LP.n_in_comps;
-  constexpr int MS = LP.m_size;
-  constexpr int MAXB = 25;   // largest (2l1+1)(2l3+1) block
-  __shared__ float Ms[MS * C];
-  __shared__ float Gm[MS * C];
-  __shared__ float red[NS * MAXB * C];
-  __shared__ float gam[NLM * C];
+  __shared__ float red[NS * NLM * C];
   const int n = threadIdx.x % C, slot = threadIdx.x / C;
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
   for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
     const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
-    for (int q = slot; q < NLM; q += NS) gam[q * C + n] = a.gamma[(i * NLM + q) * C + n];
-    __syncthreads();
-    build_M<LMAX, NL, L, C>(Ms, gam, n, slot);
-    __syncthreads();
-    float GM[MS];
+    float G[NLM], GG[NLM];
 #pragma unroll
-    for (int q = 0; q < MS; ++q) GM[q] = 0.0f;
+    for (int q = 0; q < NLM; ++q) {
+      G[q] = a.gamma[(i * NLM + q) * C + n];
+      GG[q] = 0.0f;
+    }
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
-      float V[NCI];
+      float V[NCI], GV[NCI];
       load_V<LMAX, NL, L, C>(a, t, n, Y, V);
-      float GV[NCI];
 #pragma unroll
       for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
       static_for<0, LP.n_paths>([&](auto K) {
         constexpr int k = decltype(K)::value;
         constexpr PathT pt = LP.p[k];
-        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        constexpr int d3 = 2 * pt.l3 + 1;
+        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
         float GT[d3];
 #pragma unroll
         for (int m3 = 0; m3 < d3; ++m3) GT[m3] = 0.0f;
@@ -201,13 +175,12 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
           for (int m3 = 0; m3 < d3; ++m3)
             GT[m3] += al * a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
         }
-#pragma unroll
-        for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-          for (int m3 = 0; m3 < d3; ++m3) {
-            GV[pt.in_off + m1] += Ms[(pt.m_off + m1 * d3 + m3) * C + n] * GT[m3];
-            GM[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GT[m3];
-          }
+        static_for<0, nz.n>([&](auto Q) {
+          constexpr int q = decltype(Q)::value;
+          const float cg = nz.c[q] * GT[nz.m3[q]];
+          GV[pt.in_off + nz.m1[q]] += cg * G[pt.l2 * pt.l2 + nz.m2[q]];
+          GG[pt.l2 * pt.l2 + nz.m2[q]] += cg * V[pt.in_off + nz.m1[q]];
+        });
       });
       if constexpr (L > 1) {
 #pragma unroll
@@ -228,40 +201,17 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         }
       }
     }
-    // reduce GM over slots, path by path
-    static_for<0, LP.n_paths>([&](auto K) {
-      constexpr PathT pt = LP.p[decltype(K)::value];
-      constexpr int blk = (2 * pt.l1 + 1) * (2 * pt.l3 + 1);
+    // dE/dGamma summed over the slots, scaled by nbar^-1/2
 #pragma unroll
-      for (int q = 0; q < blk; ++q) red[(slot * MAXB + q) * C + n] = GM[pt.m_off + q];
-      __syncthreads();
-      for (int q = slot; q < blk; q += NS) {
-        float v = 0.0f;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) v += red[(s * MAXB + q) * C + n];
-        Gm[(pt.m_off + q) * C + n] = v;
-      }
-      __syncthreads();
-    });
-    // dE/dGamma, scaled by nbar^-1/2, into gam
-    for (int q = slot; q < NLM; q += NS) {
-      float g = 0.0f;
-      static_for<0, LP.n_paths>([&](auto K) {
-        constexpr PathT pt = LP.p[decltype(K)::value];
-        constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
-        constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
-        const int m2 = q - pt.l2 * pt.l2;
-        if (m2 >= 0 && m2 < d2) {
-#pragma unroll
-          for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-            for (int m3 = 0; m3 < d3; ++m3)
-              g += c_cg[off + (m1 * d2 + m2) * d3 + m3] * Gm[(pt.m_off + m1 * d3 + m3) * C + n];
-        }
-      });
-      red[q * C + n] = g * a.inv_sqrt_nbar;
-    }
+    for (int q = 0; q < NLM; ++q) red[(slot * NLM + q) * C + n] = GG[q];
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      float g = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) g += red[(s * NLM + q) * C + n];
+      GG[q] = g * a.inv_sqrt_nbar;
+    }
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
@@ -271,7 +221,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         float go = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
-          const float gg = red[(l * l + m) * C + n];
+          const float gg = GG[l * l + m];
           go += gg * Y[l * l + m];
           const float gyv = group_sum<C>(gg * w);
           if (n == 0) a.gy[t * GEO_STRIDE + l * l + m] += gyv;

@@ -94,3 +94,25 @@ def test_host_error_paths():
     rc = lib.afm_model_create(C.byref(h), nanw.ctypes.data_as(C.POINTER(C.c_double)), nanw.shape[0], 1,
                               C.byref(out))
     assert rc == -3                                 # AFM_E_NONFINITE
+
+
+def test_stage_costs_cover_traced_stages():
+    """The cost model names every traced stage of energy_forces and its MLP
+    figures equal the multiply-adds of the layer widths."""
+    import paper_2502_06073_amd as afm
+    hp = synth.load_hparams("B")
+    c = afm.stage_costs(hp)
+    names = {"geometry", "twobody_fwd", "twobody_bwd", "geometry_bwd", "energy", "force_scatter"}
+    for L in (1, 2):
+        names |= {f"tp_fwd{L}", f"tp_bwd{L}", f"latent_fwd{L}", f"latent_bwd{L}"}
+    assert set(c) == names
+    W, C, D = hp["latent"], hp["channels"], hp["latent_depth"]
+    env = (hp["l_max"] + 1) * C
+    lat1 = (W + 3 * C) * W + (D - 1) * W * W
+    assert c["latent_fwd1"]["flops_per_edge"] == 2 * (lat1 + W * env)
+    assert c["latent_fwd2"]["flops_per_edge"] == 2 * (lat1 + W)
+    assert c["latent_bwd2"]["flops_per_edge"] == 2 * lat1
+    tb = hp["twobody"]
+    assert c["twobody_fwd"]["flops_per_edge"] == 2 * (hp["n_bessel"] * tb[0] + tb[0] * tb[1] + tb[1] * tb[2] + W * env)
+    assert all(v["kind"] == ("mfma" if k.startswith(("latent", "twobody")) else "vector") for k, v in c.items())
+    assert all(v["bytes_per_edge"] > 0 for v in c.values())

@@ -75,7 +75,10 @@ def test_md_skin_flag_forced_from_host():
 
 def test_md_bf16_energy_drift_small():
     s = synth.cubic_lattice(6, 2.3, 0.25, 4, 99)
-    hp, w, s, masses, v0, md = _setup("bf16", s=s, cfg="E")
+    # the random-weight lattice heats up to ~1700 K; light atoms then move
+    # up to ~0.07 A/fs, so the list is rebuilt every 2 fs to stay within the
+    # half-skin bound
+    hp, w, s, masses, v0, md = _setup("bf16", s=s, cfg="E", rebuild=4)
     log = md.run(100).cpu().numpy()
     e = log.sum(1)
     drift = np.abs(e - e[0]).max() / s.n_atoms
