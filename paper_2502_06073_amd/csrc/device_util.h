@@ -31,6 +31,56 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Sums of up to 16 values over the 64 lanes of a wavefront, as a
+// reduce-scatter: each exchange step halves the values a lane carries, so 16
+// sums cost 8 + 4 cross-row swaps (v_permlane32/16_swap) and 3 in-row DPP
+// steps instead of 16 x 6 cross-lane shuffles.  On return, lane l holds the
+// total of value (l >> 2) (lanes 4k..4k+3 all hold value k).
+__device__ __forceinline__ float dpp_f(float v, int ctrl_id) {
+  const int x = __builtin_bit_cast(int, v);
+  int r;
+  switch (ctrl_id) {  // dpp_ctrl must be an immediate
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false); break;  // row_mirror (l <-> 15-l)
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false); break;  // row_half_mirror (l <-> 7-l)
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); break;   // quad_perm [2,3,0,1]
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); break;  // quad_perm [1,0,3,2]
+  }
+  return __builtin_bit_cast(float, r);
+}
+
+__device__ __forceinline__ float wave_sum16(float (&v)[16], int lane) {
+  // lanes [0,32) end up with values 0..7, lanes [32,64) with 8..15
+  float u[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, v[k]), __builtin_bit_cast(int, v[k + 8]),
+                                                    false, false);
+    u[k] = __builtin_bit_cast(float, (int)r[0]) + __builtin_bit_cast(float, (int)r[1]);
+  }
+  // even rows of 16 keep 0..3 (of the eight), odd rows 4..7
+  float w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, u[k]), __builtin_bit_cast(int, u[k + 4]),
+                                                    false, false);
+    w[k] = __builtin_bit_cast(float, (int)r[0]) + __builtin_bit_cast(float, (int)r[1]);
+  }
+  // in-row halves (partner l <-> 15 - l differs in bit 3): keep 0,1 or 2,3
+  const bool b3 = lane & 8, b2 = lane & 4;
+  float x[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float keep = b3 ? w[k + 2] : w[k], send = b3 ? w[k] : w[k + 2];
+    x[k] = keep + dpp_f(send, 0);
+  }
+  // quarter rows (partner l <-> 7 - l within 8 lanes differs in bit 2)
+  const float keep = b2 ? x[1] : x[0], send = b2 ? x[0] : x[1];
+  float y = keep + dpp_f(send, 1);
+  y += dpp_f(y, 2);
+  y += dpp_f(y, 3);
+  return y;
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v);
 
 // Zero `bytes` (multiple of 4) with a kernel (safe inside captured graphs).

@@ -4,14 +4,20 @@
 // two-body latent MLP, "embedding MLP ... linear projection", latent MLP,
 // SiLU), forward and adjoint.
 //
-// Mapping.  Each layer is computed transposed, Y^T = W X^T: the weights are
-// the MFMA A operand (16 output features x 32 input features per fragment)
-// and a wavefront's edges are the B/C columns (JW blocks of 16 edges).  The
-// C result of one layer becomes the B operand of the next without leaving
-// registers: lane group g of a 16-row output block holds features 4g..4g+3,
-// so a 32-feature input block is fed as k-slots (g, i) <-> feature
-//   phi(kb, g, i) = 32 kb + 4 g + (i & 3) + 16 (i >> 2),
-// and every weight fragment is packed on the host with the same permutation
+// Mapping.  A workgroup of 8 wavefronts owns a tile of 128 edges (8 column
+// blocks of 16).  Each layer is computed transposed, Y^T = W X^T: the
+// weights are the MFMA A operand (16 output features x 32 input features
+// per fragment), the edges the B/C columns.  The tile's activations live in
+// LDS as bf16 B fragments (two ping-pong buffers), written once by the
+// wavefront that computed them and read by all eight; each wavefront owns
+// pairs of 16-row output blocks and streams its own weight fragments from
+// L2 into registers, so a weight byte is fetched once per 128 edges and an
+// LDS fragment feeds 2 x (rows per wavefront) MFMAs.  One barrier per layer.
+// A C block's lane group g holds output features 4g..4g+3, so the pair of
+// blocks (2p, 2p+1) packs into the B fragment of k-block p of the next layer
+// when input k-slot (g, i) carries feature
+//   phi(kb, g, i) = 32 kb + 4 g + (i & 3) + 16 (i >> 2);
+// every weight fragment is packed on the host with the same permutation
 // (MFMA pairs A and B k-slots identically, so the product is unchanged).
 // Every weight is held as an unevaluated sum of two bf16 numbers (hi + lo,
 // lo = bf16(w - hi)) and each fragment product is issued as two MFMAs into
@@ -37,9 +43,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int JW = 2;             // 16-edge column blocks per wavefront
-constexpr int TILE = 16 * JW;     // edges per wavefront
-constexpr int WAVES = 4;          // wavefronts per workgroup
+constexpr int NCB = 8;            // 16-edge column blocks per workgroup tile
+constexpr int TILE = 16 * NCB;    // edges per workgroup
+constexpr int NWAVE = 8;          // wavefronts per workgroup
+constexpr int NTHR = 64 * NWAVE;
 constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -63,10 +70,11 @@ static double bf16_value(uint16_t h) {
 }
 
 // M(r, k) = transpose ? W[k * R + r] : W[r * K + k]; fragments
-// [RB][KB][2][64][8] with the hi part of the weight pairs first, lo second
+// [RB][KB][2][64][8] with the hi part of the weight pairs first, lo second;
+// RB is rounded up to an even count (zero rows)
 static void pack_matrix(const double* W, int R, int K, bool transpose, std::vector<char>& out,
                         int64_t* off) {
-  const int RB = cdiv(R, 16), KB = cdiv(K, 32);
+  const int RB = 2 * cdiv(R, 32), KB = cdiv(K, 32);   // row blocks padded to whole pairs
   int64_t o = (int64_t)out.size();
   o = (o + 255) & ~int64_t(255);
   out.resize(o + (int64_t)RB * KB * kSplit * 64 * 16, 0);
@@ -143,6 +151,11 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 __device__ __forceinline__ float sigm(float a) { return __builtin_amdgcn_rcpf(1.0f + __expf(-a)); }
+// silu'(a) = s (1 + a (1 - s)), s = sigmoid(a)
+__device__ __forceinline__ float dsilu_of(float a) {
+  const float sg = sigm(a);
+  return sg * (1.0f + a * (1.0f - sg));
+}
 
 __device__ __forceinline__ bf16x8 pack8(f32x4 lo, f32x4 hi) {
   bf16x8 r;
@@ -153,174 +166,130 @@ __device__ __forceinline__ bf16x8 pack8(f32x4 lo, f32x4 hi) {
 
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 __device__ __forceinline__ void st4(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
-// pre-activation tile storage: [tile][RB][JW][64 lanes][4] bf16
-__device__ __forceinline__ void st_pre(uint2* pre, int64_t tile, int RB, int rb, int j, int lane, f32x4 v) {
+// pre-activation tile storage: [tile][RB][NCB][64 lanes][4] bf16
+__device__ __forceinline__ void st_pre(uint2* pre, int64_t tile, int RB, int rb, int cb, int lane, f32x4 v) {
   bf16x4 h;
   h[0] = (__bf16)v[0]; h[1] = (__bf16)v[1]; h[2] = (__bf16)v[2]; h[3] = (__bf16)v[3];
-  pre[((tile * RB + rb) * JW + j) * 64 + lane] = __builtin_bit_cast(uint2, h);
+  pre[((tile * RB + rb) * NCB + cb) * 64 + lane] = __builtin_bit_cast(uint2, h);
 }
-__device__ __forceinline__ f32x4 ld_pre(const uint2* pre, int64_t tile, int RB, int rb, int j, int lane) {
-  bf16x4 h = __builtin_bit_cast(bf16x4, pre[((tile * RB + rb) * JW + j) * 64 + lane]);
+__device__ __forceinline__ f32x4 ld_pre(const uint2* pre, int64_t tile, int RB, int rb, int cb, int lane) {
+  const bf16x4 h = __builtin_bit_cast(bf16x4, pre[((tile * RB + rb) * NCB + cb) * 64 + lane]);
   f32x4 v;
   v[0] = (float)h[0]; v[1] = (float)h[1]; v[2] = (float)h[2]; v[3] = (float)h[3];
   return v;
 }
 
-// acc (C layout, RB row blocks) -> B fragments of the next layer
-template <int RB>
-__device__ __forceinline__ void to_frags(const f32x4 (&h)[RB][JW], bf16x8 (&o)[cdiv(RB, 2)][JW]) {
-  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kb = 0; kb < cdiv(RB, 2); ++kb)
-#pragma unroll
-    for (int j = 0; j < JW; ++j) o[kb][j] = pack8(h[2 * kb][j], (2 * kb + 1 < RB) ? h[2 * kb + 1][j] : z);
-}
-
-template <int RB>
-__device__ __forceinline__ void zero(f32x4 (&a)[RB][JW]) {
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int j = 0; j < JW; ++j) a[rb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-}
-
-// Weight fragments are staged through LDS, one k-block (RB hi/lo fragment
-// pairs of 2 KB) per stage, double buffered: every wavefront of the workgroup loads a
-// share of stage kb+1 into registers while the MFMAs of stage kb run, then
-// writes it to the other buffer.  All wavefronts of a workgroup call the
-// GEMMs with the same shapes (barriers inside).
-constexpr int kStageMax = 16;                 // row blocks per stage (RB <= 16)
-constexpr int kFragPerRB = kSplit * 64;       // uint4 per (row block, k-block)
-struct Stage {
-  uint4 buf[2][kStageMax * kFragPerRB];
+// LDS: two activation buffers of B fragments [kb][cb][64 lanes] (bf16 x 8
+// each) and a [wavefront][edge] scratch row for cross-wavefront sums
+template <int KMAX>
+struct ChainSmem {
+  uint4 act[2][cdiv(KMAX, 32) * NCB * 64];
+  float red[NWAVE][TILE];
 };
+__device__ __forceinline__ int frag_idx(int kb, int cb, int lane) { return (kb * NCB + cb) * 64 + lane; }
 
-template <int RB>
-constexpr int stage_regs() { return cdiv(RB * kFragPerRB, 256); }
-
-template <int RB, int KB, int R0>
-__device__ __forceinline__ void stage_load(const uint4* __restrict__ W, int kb, uint4 (&reg)[stage_regs<RB>()],
-                                           int tid) {
-#pragma unroll
-  for (int q = 0; q < stage_regs<RB>(); ++q) {
-    // clamped rather than predicated: the loads stay unconditional, so the
-    // staging registers never leave the register file
-    const int idx = min(tid + 256 * q, RB * kFragPerRB - 1);
-    reg[q] = W[((int64_t)(R0 + idx / kFragPerRB) * KB + kb) * kFragPerRB + (idx % kFragPerRB)];
-  }
-}
-template <int RB>
-__device__ __forceinline__ void stage_store(uint4* __restrict__ dst, const uint4 (&reg)[stage_regs<RB>()], int tid) {
-#pragma unroll
-  for (int q = 0; q < stage_regs<RB>(); ++q) {
-    const int idx = tid + 256 * q;
-    if (idx < RB * kFragPerRB) dst[idx] = reg[q];
-  }
-}
-
-// acc[rb] = sum_kb W[R0 + rb][kb] x B(kb) for rb < RB; B(kb, j) supplies
-// the B fragments (registers or memory)
-template <int RB, int KB, int R0, class BF>
-__device__ __forceinline__ void gemm_lds(const uint4* __restrict__ W, Stage& S, BF bfrag, f32x4 (&acc)[RB][JW],
-                                         int lane, int tid) {
-  static_assert(RB <= kStageMax, "stage too small");
-  zero(acc);
-  uint4 reg[stage_regs<RB>()];
-  stage_load<RB, KB, R0>(W, 0, reg, tid);
-  stage_store<RB>(S.buf[0], reg, tid);
-  __syncthreads();
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    if (kb + 1 < KB) stage_load<RB, KB, R0>(W, kb + 1, reg, tid);
-    bf16x8 b[JW];
-#pragma unroll
-    for (int j = 0; j < JW; ++j) b[j] = bfrag(kb, j);
-    const uint4* cur = S.buf[kb & 1];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-      for (int h = 0; h < kSplit; ++h) {
-        const bf16x8 a = __builtin_bit_cast(bf16x8, cur[rb * kFragPerRB + h * 64 + lane]);
-#pragma unroll
-        for (int j = 0; j < JW; ++j) acc[rb][j] = mfma(a, b[j], acc[rb][j]);
-      }
-    }
-    if (kb + 1 < KB) stage_store<RB>(S.buf[(kb + 1) & 1], reg, tid);
-    __syncthreads();
-  }
-}
-
-// B fragments held in registers
-template <int KB>
-struct RegB {
-  const bf16x8 (&in)[KB][JW];
-  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const { return in[kb][j]; }
-};
-
-// B fragment of features [32 kb, 32 kb + 32) of a float32 row-major matrix
-// X[t][ld] restricted to columns < kpart (zeros beyond, and for invalid t)
-__device__ __forceinline__ bf16x8 ld_frag32(const float* __restrict__ X, int ld, int64_t t, bool valid, int kb,
-                                            int kpart, int g) {
-  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+// B fragment of features [32 kb, 32 kb + 32) of row t of a float32
+// row-major matrix X[t][K] (zeros beyond K and for invalid rows)
+template <int K>
+__device__ __forceinline__ bf16x8 ld_frag32(const float* __restrict__ X, int64_t t, bool valid, int kb, int g) {
   const int fa = 32 * kb + 4 * g, fb = fa + 16;
-  f32x4 lo = (valid && fa + 4 <= kpart) ? ld4(X + t * ld + fa) : z;
-  f32x4 hi = (valid && fb + 4 <= kpart) ? ld4(X + t * ld + fb) : z;
+  const f32x4 lo = (valid && fa + 4 <= K) ? ld4(X + t * K + fa) : zero4();
+  const f32x4 hi = (valid && fb + 4 <= K) ? ld4(X + t * K + fb) : zero4();
   return pack8(lo, hi);
 }
 
-// B fragments of [x | s] (x: [t][WX], s: [t][KS], float32) from memory
-template <int WX, int KS>
-struct CatB {
-  const float* x;
-  const float* s;
-  const int64_t* t;
-  const bool* valid;
-  int g;
-  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const {
-    if (32 * kb < WX) return ld_frag32(x, WX, t[j], valid[j], kb, WX, g);
-    return ld_frag32(s, KS, t[j], valid[j], kb - WX / 32, KS, g);
-  }
-};
-
+// Stage rows [tile*TILE, tile*TILE + TILE) of X[t][K] into LDS fragments.
 template <int K>
-struct MemB {
-  const float* x;
-  const int64_t* t;
-  const bool* valid;
-  int g;
-  __device__ __forceinline__ bf16x8 operator()(int kb, int j) const { return ld_frag32(x, K, t[j], valid[j], kb, K, g); }
-};
+__device__ __forceinline__ void stage_rows(uint4* __restrict__ act, const float* __restrict__ X, int64_t tile,
+                                           int64_t M, int tid) {
+  constexpr int NF = cdiv(K, 32) * NCB * 64;
+  for (int idx = tid; idx < NF; idx += NTHR) {
+    const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB);
+    const int64_t t = tile * TILE + 16 * cb + (l & 15);
+    act[idx] = __builtin_bit_cast(uint4, ld_frag32<K>(X, t, t < M, kb, l >> 4));
+  }
+}
 
-// Register-fed layer computed in NP passes over its RBO output row blocks
-// (accumulators for RBO/NP blocks at a time; every weight fragment is still
-// loaded once).  epi(rb, j, v) finalises a block in place; with FRAGS the
-// finalised values also become the B fragments `out` of the next layer.
-constexpr int np_of(int rbo) { return rbo >= 8 ? 2 : 1; }
+// acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
+//   W[2 pair + r][kb] x act[kb - kb0][cb]
+// W: packed weight fragments [RB][KBW][hi, lo][64]; act: LDS fragments.
+// Weight fragments stream from L2 one k-block ahead; per k-block the hi
+// products of both row blocks and all column blocks are issued before the
+// lo products, so the two MFMAs into one accumulator are 16 apart.
+template <int KBW, int NKB>
+__device__ __forceinline__ void mma_pair(const uint4* __restrict__ W, int pair, int kb0, const uint4* act,
+                                         f32x4 (&acc)[2][NCB], int lane) {
+  const uint4* w0 = W + ((int64_t)(2 * pair) * KBW + kb0) * (kSplit * 64) + lane;
+  const uint4* w1 = w0 + (int64_t)KBW * (kSplit * 64);
+  uint4 cur[4], nxt[4];
+  cur[0] = w0[0]; cur[1] = w0[64]; cur[2] = w1[0]; cur[3] = w1[64];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) {
+    if (kb + 1 < NKB) {
+      const int o = (kb + 1) * (kSplit * 64);
+      nxt[0] = w0[o]; nxt[1] = w0[o + 64]; nxt[2] = w1[o]; nxt[3] = w1[o + 64];
+    }
+    bf16x8 b[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) b[cb] = __builtin_bit_cast(bf16x8, act[frag_idx(kb, cb, lane)]);
+#pragma unroll
+    for (int h = 0; h < kSplit; ++h)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const bf16x8 A = __builtin_bit_cast(bf16x8, cur[2 * r + h]);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = mfma(A, b[cb], acc[r][cb]);
+      }
+    if (kb + 1 < NKB) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+    }
+  }
+}
 
-template <int RBO, int KB, int NP, bool FRAGS, class EPI>
-__device__ __forceinline__ void layer_reg(const uint4* __restrict__ W, Stage& S, const bf16x8 (&in)[KB][JW],
-                                          bf16x8 (&out)[cdiv(RBO, 2)][JW], EPI epi, int lane, int tid) {
-  static_assert(RBO % NP == 0, "passes must split the rows evenly");
-  constexpr int RP = RBO / NP;
-  static_assert(NP == 1 || RP % 2 == 0, "a pass must hold whole k-blocks of the next layer");
-  static_for<0, NP>([&](auto P) __attribute__((always_inline)) {
-    constexpr int p = decltype(P)::value;
-    f32x4 acc[RP][JW];
-    gemm_lds<RP, KB, p * RP>(W, S, RegB<KB>{in}, acc, lane, tid);
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[2][NCB]) {
 #pragma unroll
-    for (int rb = 0; rb < RP; ++rb)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int j = 0; j < JW; ++j) epi(p * RP + rb, j, acc[rb][j]);
-    if constexpr (FRAGS) {
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = zero4();
+}
+
+// Finalise a pair of row blocks: epi(rb, cb, v) in place for both blocks,
+// then (if out) the pair becomes k-block `pair` of the next layer's input.
+template <class EPI>
+__device__ __forceinline__ void finish_pair(int pair, f32x4 (&acc)[2][NCB], uint4* out, EPI&& epi, int lane) {
 #pragma unroll
-      for (int kb = 0; kb < cdiv(RP, 2); ++kb)
-#pragma unroll
-        for (int j = 0; j < JW; ++j)
-          out[p * RP / 2 + kb][j] = pack8(acc[2 * kb][j], (2 * kb + 1 < RP) ? acc[2 * kb + 1][j] : z);
+  for (int cb = 0; cb < NCB; ++cb) {
+    epi(2 * pair, cb, acc[0][cb]);
+    epi(2 * pair + 1, cb, acc[1][cb]);
+    if (out) out[frag_idx(pair, cb, lane)] = __builtin_bit_cast(uint4, pack8(acc[0][cb], acc[1][cb]));
+  }
+}
+
+// A whole layer from LDS: rows of NPAIR pairs, wavefront w owns pairs
+// w, w + NWAVE, ...; no barrier inside.
+template <int NPAIR, int KBW, class EPI>
+__device__ __forceinline__ void layer_lds(const uint4* __restrict__ W, const uint4* in, uint4* out, EPI&& epi,
+                                          int wave, int lane) {
+  static_for<0, cdiv(NPAIR, NWAVE)>([&](auto P) __attribute__((always_inline)) {
+    const int pair = decltype(P)::value * NWAVE + wave;
+    if (pair < NPAIR) {
+      f32x4 acc[2][NCB];
+      zero_acc(acc);
+      mma_pair<KBW, KBW>(W, pair, 0, in, acc, lane);
+      finish_pair(pair, acc, out, epi, lane);
     }
   });
+}
+
+// Sum of v over the lane groups g (the 4 row quarters of a C block); the
+// result is valid in every lane.
+__device__ __forceinline__ float sum_groups(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,201 +329,211 @@ struct ChainArgs {
   float* grho;            // [t][16]
 };
 
-struct Cols {
-  int64_t t[JW];
-  bool valid[JW];
-  float u[JW];
-};
+// Workgroup prologue: tile, edge count of the chunk, this lane's envelope
+// factor per column block.  The whole workgroup returns when its tile is
+// empty (uniform, before any barrier).
+#define AFM_TILE_PROLOGUE                                                          \
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;    \
+  int64_t e0, e1;                                                                  \
+  a.rr.get(e0, e1);                                                                \
+  const int64_t M = e1 - e0;                                                       \
+  const int64_t tile = blockIdx.x;                                                 \
+  if (tile * TILE >= M) return;                                                    \
+  float u[NCB];                                                                    \
+  _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) {                             \
+    const int64_t t = tile * TILE + 16 * cb + (lane & 15);                         \
+    u[cb] = t < M ? a.geo[t * GEO_STRIDE + GEO_U] : 0.0f;                          \
+  }                                                                                \
+  auto col_t = [&](int cb) { return tile * TILE + 16 * cb + (lane & 15); };
 
-// Columns of this wavefront's tile.  Returns false (for the whole
-// workgroup, uniformly) when the workgroup has no edges; wavefronts past the
-// end run with all columns invalid so the workgroup's barriers stay matched.
-__device__ __forceinline__ bool tile_cols(const ChainArgs& a, int64_t tile, int lane, int64_t& e0, Cols& c) {
-  int64_t e1;
-  a.rr.get(e0, e1);
-  const int64_t M = e1 - e0;
-  if ((int64_t)blockIdx.x * WAVES * TILE >= M) return false;
+// Per-edge sums of this wavefront's partials part[cb] (lane groups already
+// summed) over all wavefronts; fn(t, total) runs once per valid edge.
+template <class FN>
+__device__ __forceinline__ void wg_edge_sum(float (&red)[NWAVE][TILE], const float (&part)[NCB], int64_t tile,
+                                            int64_t M, int tid, FN&& fn) {
+  const int lane = tid & 63, wave = tid >> 6;
+  if ((lane >> 4) == 0) {
 #pragma unroll
-  for (int j = 0; j < JW; ++j) {
-    c.t[j] = tile * TILE + 16 * j + (lane & 15);
-    c.valid[j] = c.t[j] < M;
-    c.u[j] = c.valid[j] ? a.geo[c.t[j] * GEO_STRIDE + GEO_U] : 0.0f;
+    for (int cb = 0; cb < NCB; ++cb) red[wave][16 * cb + lane] = part[cb];
   }
-  return true;
+  __syncthreads();
+  if (tid < TILE) {
+    float s = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) s += red[w][tid];
+    const int64_t t = tile * TILE + tid;
+    if (t < M) fn(t, s);
+  }
+  __syncthreads();
 }
 
-#define AFM_CHAIN_PROLOGUE                                                   \
-  __shared__ Stage S;                                                        \
-  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;               \
-  const int64_t tile = (int64_t)blockIdx.x * WAVES + (tid >> 6);             \
-  int64_t e0;                                                                \
-  Cols c;                                                                    \
-  if (!tile_cols(a, tile, lane, e0, c)) return;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------------------
 // two-body MLP + environment embedding of layer 1 (forward)
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(256) k_tb_fwd(ChainArgs a) {
-  AFM_CHAIN_PROLOGUE
+__global__ void __launch_bounds__(NTHR) k_tb_fwd(ChainArgs a) {
+  AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int TL = NT == 3 ? T2 : T1;
   static_assert(TL == W, "last two-body width must equal the latent width");
-  // first layer on the vector ALUs: gathers of the one-hot columns + rho
-  constexpr int RB0 = cdiv(T0, 16);
-  bf16x8 in0[cdiv(RB0, 2)][JW];
+  __shared__ ChainSmem<cmax(cmax(T0, T1), W)> S;
+  constexpr int RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), RBW = W / 16;
+  // first layer on the vector ALUs (one-hot columns are gathers), SiLU,
+  // straight into LDS fragments
   {
-    f32x4 h0[RB0][JW];
     const int K0 = 2 * a.S + a.nb;
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
+    constexpr int NF = cdiv(T0, 32) * NCB * 64;
+    for (int idx = tid; idx < NF; idx += NTHR) {
+      const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB), gl = l >> 4;
+      const int64_t t = tile * TILE + 16 * cb + (l & 15);
+      const bool valid = t < M;
       float rho[16];
       int zi = 0, zj = 0;
 #pragma unroll
       for (int n = 0; n < 16; ++n) rho[n] = 0.0f;
-      if (c.valid[j]) {
-        const float r = a.geo[c.t[j] * GEO_STRIDE + GEO_D];
-        const float pre = sqrtf(2.0f / a.r_cut) / r * c.u[j];
+      if (valid) {
+        const float r = a.geo[t * GEO_STRIDE + GEO_D];
+        const float ut = a.geo[t * GEO_STRIDE + GEO_U];
+        const float pre = sqrtf(2.0f / a.r_cut) / r * ut;
 #pragma unroll
         for (int n = 0; n < 16; ++n)
           if (n < a.nb) rho[n] = pre * __sinf((n + 1) * 3.14159265358979323846f * r / a.r_cut);
-        zi = min(max(a.species[a.eidx[c.t[j]]], 0), a.S - 1);
-        zj = min(max(a.species[a.col[e0 + c.t[j]]], 0), a.S - 1);
+        zi = min(max(a.species[a.eidx[t]], 0), a.S - 1);
+        zj = min(max(a.species[a.col[e0 + t]], 0), a.S - 1);
       }
+      f32x4 v[2];
 #pragma unroll
-      for (int rb = 0; rb < RB0; ++rb) {
-        f32x4 v;
+      for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int f = 16 * rb + 4 * g + q;
+          const int f = 32 * kb + 16 * h + 4 * gl + q;
           float sacc = 0.0f;
-          if (f < T0 && c.valid[j]) {
+          if (f < T0 && valid) {
             const float* w = a.w0 + (int64_t)f * K0;
             sacc = w[zi] + w[a.S + zj];
 #pragma unroll
             for (int n = 0; n < 16; ++n)
               if (n < a.nb) sacc += w[2 * a.S + n] * rho[n];
           }
-          v[q] = sacc;
+          v[h][q] = sacc;
         }
-        st_pre(a.pre[0], tile, RB0, rb, j, lane, v);
+        if (2 * kb + h < RB0) st_pre(a.pre[0], tile, RB0, 2 * kb + h, cb, l, v[h]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
-        h0[rb][j] = v;
+        for (int q = 0; q < 4; ++q) v[h][q] = v[h][q] * sigm(v[h][q]);
       }
+      S.act[0][idx] = __builtin_bit_cast(uint4, pack8(v[0], v[1]));
     }
-    to_frags<RB0>(h0, in0);
   }
-  constexpr int RB1 = cdiv(T1, 16);
-  constexpr int RBW = W / 16;
-  auto silu_epi = [&](uint2* pre, int RB, bool env_out) {
-    return [=, &c](int rb, int j, f32x4& v) {
-      st_pre(pre, tile, RB, rb, j, lane, v);
+  __syncthreads();
+  // hidden / output layers: SiLU; the last one x^0 = u silu(a) to HBM
+  auto hidden = [&](uint2* pre, int RB, bool out_layer) {
+    return [&, pre, RB, out_layer](int rb, int cb, f32x4& v) {
+      if (rb >= RB) return;
+      st_pre(pre, tile, RB, rb, cb, lane, v);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = env_out ? c.u[j] * v[q] * sigm(v[q]) : v[q] * sigm(v[q]);
-      if (env_out && c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, v);
+      for (int q = 0; q < 4; ++q) v[q] = out_layer ? u[cb] * v[q] * sigm(v[q]) : v[q] * sigm(v[q]);
+      if (out_layer) {
+        const int64_t t = tile * TILE + 16 * cb + (lane & 15);
+        if (t < M) st4(a.xnew + t * W + 16 * rb + 4 * g, v);
+      }
     };
   };
-  bf16x8 xin[W / 32][JW];
+  layer_lds<cdiv(T1, 32), cdiv(T0, 32)>(a.tbf[1], S.act[0], S.act[1], hidden(a.pre[1], RB1, NT == 2), wave, lane);
+  __syncthreads();
+  int cur = 1;
   if constexpr (NT == 3) {
-    bf16x8 in1[cdiv(RB1, 2)][JW];
-    layer_reg<RB1, cdiv(RB0, 2), 1, true>(a.tbf[1], S, in0, in1, silu_epi(a.pre[1], RB1, false), lane, tid);
-    layer_reg<RBW, cdiv(RB1, 2), np_of(RBW), true>(a.tbf[2], S, in1, xin, silu_epi(a.pre[2], RBW, true), lane, tid);
-  } else {
-    layer_reg<RB1, cdiv(RB0, 2), 1, true>(a.tbf[1], S, in0, xin, silu_epi(a.pre[1], RB1, true), lane, tid);
+    layer_lds<W / 32, cdiv(T1, 32)>(a.tbf[2], S.act[1], S.act[0], hidden(a.pre[2], RBW, true), wave, lane);
+    __syncthreads();
+    cur = 0;
   }
   // omega^1 = W_env^1 x^0
-  constexpr int RBE = ENV / 16;
-  bf16x8 unused[cdiv(RBE, 2)][JW];
-  layer_reg<RBE, W / 32, np_of(RBE), false>(
-      a.envf, S, xin, unused,
-      [&](int rb, int j, f32x4& v) {
-        if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, v);
+  layer_lds<cdiv(ENV, 32), W / 32>(
+      a.envf, S.act[cur], nullptr,
+      [&](int rb, int cb, f32x4& v) {
+        const int64_t t = col_t(cb);
+        if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
       },
-      lane, tid);
+      wave, lane);
 }
 
 // ---------------------------------------------------------------------------
 // latent MLP of one layer (forward) + next environment embedding or energies
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(256) k_lat_fwd(ChainArgs a) {
-  AFM_CHAIN_PROLOGUE
-  constexpr int RBW = W / 16, KBW = W / 32;
-  constexpr int KIN = W + KS;
+__global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
+  AFM_TILE_PROLOGUE
+  constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
+  static_assert(NPW <= NWAVE, "one pair per wavefront");
   const float r2 = 0.70710678118654752f;
-  bf16x8 in[KBW][JW];
-  {
-    f32x4 h[RBW][JW];
-    gemm_lds<RBW, cdiv(KIN, 32), 0>(a.latf[0], S, CatB<W, KS>{a.xprev, a.s, c.t, c.valid, g}, h, lane, tid);
+  __shared__ ChainSmem<cmax(W, KS)> S;
+  const int pair = wave;
+  const bool mine = pair < NPW;
+  float ep[NCB];
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
+  for (int cb = 0; cb < NCB; ++cb) ep[cb] = 0.0f;
+  // epilogue of latent layer k: SiLU, or the residual update after the last
+  auto epi = [&](int k) {
+    return [&, k](int rb, int cb, f32x4& v) {
+      st_pre(a.pre[k], tile, RBW, rb, cb, lane, v);
+      if (k < DEPTH - 1) {
 #pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        st_pre(a.pre[0], tile, RBW, rb, j, lane, h[rb][j]);
-        if (DEPTH > 1) {
+        for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
+      } else {
+        const int64_t t = col_t(cb);
+        const bool valid = t < M;
+        const f32x4 xp = valid ? ld4(a.xprev + t * W + 16 * rb + 4 * g) : zero4();
 #pragma unroll
-          for (int q = 0; q < 4; ++q) h[rb][j][q] = h[rb][j][q] * sigm(h[rb][j][q]);
+        for (int q = 0; q < 4; ++q) v[q] = (xp[q] + u[cb] * v[q] * sigm(v[q])) * r2;
+        if constexpr (!LAST) {
+          if (valid) st4(a.xnew + t * W + 16 * rb + 4 * g, v);
         } else {
-          const f32x4 xp = c.valid[j] ? ld4(a.xprev + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+          const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) h[rb][j][q] = (xp[q] + c.u[j] * h[rb][j][q] * sigm(h[rb][j][q])) * r2;
-          if (!LAST && c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, h[rb][j]);
+          for (int q = 0; q < 4; ++q) ep[cb] += we[q] * v[q];
         }
       }
-    to_frags<RBW>(h, in);
+    };
+  };
+  // layer 0 over [x | s]: x k-blocks, then s k-blocks through the same buffer
+  f32x4 acc[2][NCB];
+  zero_acc(acc);
+  stage_rows<W>(S.act[0], a.xprev, tile, M, tid);
+  __syncthreads();
+  if (mine) mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, lane);
+  __syncthreads();
+  stage_rows<KS>(S.act[0], a.s, tile, M, tid);
+  __syncthreads();
+  if (mine) {
+    mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[0], acc, lane);
+    finish_pair(pair, acc, (LAST && DEPTH == 1) ? nullptr : S.act[1], epi(0), lane);
   }
-  float ep[JW];
-#pragma unroll
-  for (int j = 0; j < JW; ++j) ep[j] = 0.0f;
+  __syncthreads();
+  int cur = 1;
   static_for<1, DEPTH>([&](auto K) __attribute__((always_inline)) {
     constexpr int k = decltype(K)::value;
-    constexpr bool last = k == DEPTH - 1;
-    bf16x8 out[KBW][JW];
-    layer_reg<RBW, KBW, np_of(RBW), true>(
-        a.latf[k], S, in, out,
-        [&](int rb, int j, f32x4& v) {
-          st_pre(a.pre[k], tile, RBW, rb, j, lane, v);
-          if constexpr (!last) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
-          } else {
-            const f32x4 xp = c.valid[j] ? ld4(a.xprev + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (xp[q] + c.u[j] * v[q] * sigm(v[q])) * r2;
-            if constexpr (!LAST) {
-              if (c.valid[j]) st4(a.xnew + c.t[j] * W + 16 * rb + 4 * g, v);
-            } else {
-              const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
-#pragma unroll
-              for (int q = 0; q < 4; ++q) ep[j] += we[q] * v[q];
-            }
-          }
-        },
-        lane, tid);
-#pragma unroll
-    for (int kb = 0; kb < KBW; ++kb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) in[kb][j] = out[kb][j];
+    if (mine) {
+      zero_acc(acc);
+      mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, lane);
+      finish_pair(pair, acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(k), lane);
+    }
+    __syncthreads();
+    cur ^= 1;
   });
   if constexpr (!LAST) {
-    constexpr int RBE = ENV / 16;
-    bf16x8 unused[cdiv(RBE, 2)][JW];
-    layer_reg<RBE, KBW, np_of(RBE), false>(
-        a.envf, S, in, unused,
-        [&](int rb, int j, f32x4& v) {
-          if (c.valid[j]) st4(a.omega + c.t[j] * ENV + 16 * rb + 4 * g, v);
+    layer_lds<cdiv(ENV, 32), KBX>(
+        a.envf, S.act[cur], nullptr,
+        [&](int rb, int cb, f32x4& v) {
+          const int64_t t = col_t(cb);
+          if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
         },
-        lane, tid);
+        wave, lane);
   } else {
     // eps_e = w_eff . x^{N_L}
 #pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      float p = ep[j];
-      p += __shfl_xor(p, 16, 64);
-      p += __shfl_xor(p, 32, 64);
-      if (g == 0 && c.valid[j]) a.eps[e0 + c.t[j]] = p;
-    }
+    for (int cb = 0; cb < NCB; ++cb) ep[cb] = sum_groups(ep[cb]);
+    wg_edge_sum(S.red, ep, tile, M, tid, [&](int64_t t, float v) { a.eps[e0 + t] = v; });
   }
 }
 
@@ -562,210 +541,217 @@ __global__ void __launch_bounds__(256) k_lat_fwd(ChainArgs a) {
 // adjoint of one latent layer: dE/dx^L -> dE/dx^{L-1}, dE/ds^L, dE/du
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(256) k_lat_bwd(ChainArgs a) {
-  AFM_CHAIN_PROLOGUE
-  constexpr int RBW = W / 16, KBW = W / 32;
+__global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
+  AFM_TILE_PROLOGUE
+  constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
+  static_assert(NPW <= NWAVE, "one pair per wavefront");
   const float r2 = 0.70710678118654752f;
-  bf16x8 in[KBW][JW];
-  {
-    f32x4 G[RBW][JW];
-    if constexpr (LAST) {
-      // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
+  __shared__ ChainSmem<cmax(W, ENV)> S;
+  const int pair = wave;
+  const bool mine = pair < NPW;
+  float gu[NCB];
 #pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        float ce = 0.0f;
-        if (c.valid[j]) {
-          const int64_t i = a.eidx[c.t[j]];
-          ce = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
+  for (int cb = 0; cb < NCB; ++cb) gu[cb] = 0.0f;
+  // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2; v = dE/dx^L on entry
+  auto head = [&](int rb, int cb, f32x4& v) {
+    const int64_t t = col_t(cb);
+    const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, cb, lane);
+    f32x4 res;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float gs_ = v[q] * r2;
+      const float sg = sigm(pa[q]);
+      res[q] = gs_;
+      gu[cb] += gs_ * pa[q] * sg;
+      v[q] = gs_ * u[cb] * sg * (1.0f + pa[q] * (1.0f - sg));
+    }
+    if (t < M) st4(a.gx + t * W + 16 * rb + 4 * g, res);
+  };
+  if constexpr (LAST) {
+    // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
+    if (mine) {
+      float ce[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int64_t t = col_t(cb);
+        ce[cb] = 0.0f;
+        if (t < M) {
+          const int64_t i = a.eidx[t];
+          ce[cb] = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
           if (a.ges) {
             int64_t lo = 0, hi = a.B;
             while (hi - lo > 1) {
               int64_t mid = (lo + hi) >> 1;
               if (a.seg[mid] <= i) lo = mid; else hi = mid;
             }
-            ce *= (float)a.ges[lo];
+            ce[cb] *= (float)a.ges[lo];
           }
         }
-#pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-          const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) G[rb][j][q] = ce * we[q];
-        }
       }
-    } else {
-      // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
-      gemm_lds<RBW, cdiv(ENV, 32), 0>(a.envb, S, MemB<ENV>{a.gomega, c.t, c.valid, g}, G, lane, tid);
+      f32x4 acc[2][NCB];
 #pragma unroll
-      for (int rb = 0; rb < RBW; ++rb)
+      for (int r = 0; r < 2; ++r) {
+        const f32x4 we = ld4(a.w_eff + 16 * (2 * pair + r) + 4 * g);
 #pragma unroll
-        for (int j = 0; j < JW; ++j)
-          if (c.valid[j]) G[rb][j] += ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g);
-    }
-    // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2
-    float gu[JW];
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-    for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, j, lane);
-        f32x4 res;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float gs_ = G[rb][j][q] * r2;
-          const float sg = sigm(pa[q]);
-          res[q] = gs_;
-          gu[j] += gs_ * pa[q] * sg;
-          G[rb][j][q] = gs_ * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
-        }
-        if (c.valid[j]) st4(a.gx + c.t[j] * W + 16 * rb + 4 * g, res);
+          for (int q = 0; q < 4; ++q) acc[r][cb][q] = ce[cb] * we[q];
       }
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      float v = gu[j];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
+      finish_pair(pair, acc, S.act[0], head, lane);
     }
-    to_frags<RBW>(G, in);
+  } else {
+    // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
+    stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
+    __syncthreads();
+    if (mine) {
+      f32x4 acc[2][NCB];
+      zero_acc(acc);
+      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, lane);
+      finish_pair(
+          pair, acc, S.act[0],
+          [&](int rb, int cb, f32x4& v) {
+            const int64_t t = col_t(cb);
+            if (t < M) v += ld4(a.gx + t * W + 16 * rb + 4 * g);
+            head(rb, cb, v);
+          },
+          lane);
+    }
   }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) gu[cb] = sum_groups(gu[cb]);
+  // (the barrier inside also publishes the head's fragments)
+  wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
   // inner layers: ga_{k-1} = (W_k^T ga_k) * silu'(a_{k-1})
+  int cur = 0;
   static_for<1, DEPTH>([&](auto KK) __attribute__((always_inline)) {
     constexpr int k = DEPTH - decltype(KK)::value;
-    bf16x8 out[KBW][JW];
-    layer_reg<RBW, KBW, np_of(RBW), true>(
-        a.latb[k], S, in, out,
-        [&](int rb, int j, f32x4& v) {
-          const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, j, lane);
+    if (mine) {
+      f32x4 acc[2][NCB];
+      zero_acc(acc);
+      mma_pair<KBX, KBX>(a.latb[k], pair, 0, S.act[cur], acc, lane);
+      finish_pair(
+          pair, acc, S.act[cur ^ 1],
+          [&](int rb, int cb, f32x4& v) {
+            const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, cb, lane);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float sg = sigm(pa[q]);
-            v[q] *= sg * (1.0f + pa[q] * (1.0f - sg));
-          }
-        },
-        lane, tid);
-#pragma unroll
-    for (int kb = 0; kb < KBW; ++kb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) in[kb][j] = out[kb][j];
+            for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
+          },
+          lane);
+    }
+    __syncthreads();
+    cur ^= 1;
   });
   // dE/d[x | s] = W_1^T ga_1: x rows added to the residual share, s rows stored
-  {
-    bf16x8 unused[KBW][JW];
-    layer_reg<RBW, KBW, np_of(RBW), false>(
-        a.latb[0], S, in, unused,
-        [&](int rb, int j, f32x4& v) {
-          if (c.valid[j]) {
-            float* p = a.gx + c.t[j] * W + 16 * rb + 4 * g;
-            st4(p, ld4(p) + v);
-          }
-        },
-        lane, tid);
-  }
-  {
-    constexpr int RBS = KS / 16;
-    f32x4 os[RBS][JW];
-    gemm_lds<RBS, KBW, RBW>(a.latb[0], S, RegB<KBW>{in}, os, lane, tid);
-#pragma unroll
-    for (int rb = 0; rb < RBS; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j)
-        if (c.valid[j]) st4(a.gs + c.t[j] * KS + 16 * rb + 4 * g, os[rb][j]);
-  }
+  layer_lds<cdiv(W + KS, 32), KBX>(
+      a.latb[0], S.act[cur], nullptr,
+      [&](int rb, int cb, f32x4& v) {
+        const int64_t t = col_t(cb);
+        if (t >= M) return;
+        if (rb < RBW) {
+          float* p = a.gx + t * W + 16 * rb + 4 * g;
+          st4(p, ld4(p) + v);
+        } else if (16 * (rb - RBW) < KS) {
+          st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
+        }
+      },
+      wave, lane);
 }
 
 // ---------------------------------------------------------------------------
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(256) k_tb_bwd(ChainArgs a) {
-  AFM_CHAIN_PROLOGUE
+__global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
+  AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
-  constexpr int RBW = W / 16;
-  constexpr int RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16);
-  bf16x8 in[RBW / 2][JW];
-  {
-    f32x4 G[RBW][JW];
-    gemm_lds<RBW, cdiv(ENV, 32), 0>(a.envb, S, MemB<ENV>{a.gomega, c.t, c.valid, g}, G, lane, tid);
-    // head: x^0 = u silu(a_last)
-    float gu[JW];
+  constexpr int RBW = W / 16, RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), NPW = W / 32;
+  static_assert(NPW <= NWAVE, "one pair per wavefront");
+  __shared__ ChainSmem<cmax(cmax(ENV, W), T1)> S;
+  const int pair = wave;
+  const bool mine = pair < NPW;
+  float gu[NCB];
 #pragma unroll
-    for (int j = 0; j < JW; ++j) gu[j] = 0.0f;
+  for (int cb = 0; cb < NCB; ++cb) gu[cb] = 0.0f;
+  // head: x^0 = u silu(a_last); dE/dx^0 = stored + W_env^1T dE/domega^1
+  stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
+  __syncthreads();
+  if (mine) {
+    f32x4 acc[2][NCB];
+    zero_acc(acc);
+    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, lane);
+    finish_pair(
+        pair, acc, S.act[0],
+        [&](int rb, int cb, f32x4& v) {
+          const int64_t t = col_t(cb);
+          const f32x4 gx = t < M ? ld4(a.gx + t * W + 16 * rb + 4 * g) : zero4();
+          const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, cb, lane);
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) {
-        const f32x4 gx = c.valid[j] ? ld4(a.gx + c.t[j] * W + 16 * rb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
-        const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, j, lane);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float gv = G[rb][j][q] + gx[q];
-          const float sg = sigm(pa[q]);
-          gu[j] += gv * pa[q] * sg;
-          G[rb][j][q] = gv * c.u[j] * sg * (1.0f + pa[q] * (1.0f - sg));
-        }
-      }
-#pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      float v = gu[j];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      if (g == 0 && c.valid[j]) a.gy[c.t[j] * GEO_STRIDE + 9] += v;
-    }
-    to_frags<RBW>(G, in);
+          for (int q = 0; q < 4; ++q) {
+            const float gv = v[q] + gx[q];
+            const float sg = sigm(pa[q]);
+            gu[cb] += gv * pa[q] * sg;
+            v[q] = gv * u[cb] * sg * (1.0f + pa[q] * (1.0f - sg));
+          }
+        },
+        lane);
   }
-  auto dsilu_epi = [&](uint2* pre, int RB) {
-    return [=](int rb, int j, f32x4& v) {
-      const f32x4 pa = ld_pre(pre, tile, RB, rb, j, lane);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float sg = sigm(pa[q]);
-        v[q] *= sg * (1.0f + pa[q] * (1.0f - sg));
-      }
-    };
-  };
-  bf16x8 in1[cdiv(RB1, 2)][JW];
+  for (int cb = 0; cb < NCB; ++cb) gu[cb] = sum_groups(gu[cb]);
+  wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
+  int cur = 0;
   if constexpr (NT == 3) {
-    layer_reg<RB1, RBW / 2, np_of(RB1), true>(a.tbb[2], S, in, in1, dsilu_epi(a.pre[1], RB1), lane,
-                                                          tid);
-  } else {
+    layer_lds<cdiv(T1, 32), W / 32>(
+        a.tbb[2], S.act[0], S.act[1],
+        [&](int rb, int cb, f32x4& v) {
+          if (rb >= RB1) return;
+          const f32x4 pa = ld_pre(a.pre[1], tile, RB1, rb, cb, lane);
 #pragma unroll
-    for (int kb = 0; kb < cdiv(RB1, 2); ++kb)
-#pragma unroll
-      for (int j = 0; j < JW; ++j) in1[kb][j] = in[kb][j];
+          for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
+        },
+        wave, lane);
+    __syncthreads();
+    cur = 1;
   }
-  f32x4 G0[RB0][JW];
-  gemm_lds<RB0, cdiv(RB1, 2), 0>(a.tbb[1], S, RegB<cdiv(RB1, 2)>{in1}, G0, lane, tid);
+  // ga_0 = (W_1^T ga_1) * silu'(a_0), then dE/drho_n = sum_f W_0[f][2S + n] ga_0[f]
+  constexpr int NP0 = cdiv(T0, 32);
+  static_assert(NP0 <= NWAVE, "one pair per wavefront");
+  f32x4 acc[2][NCB];
+  zero_acc(acc);
+  if (wave < NP0) {
+    mma_pair<cdiv(T1, 32), cdiv(T1, 32)>(a.tbb[1], wave, 0, S.act[cur], acc, lane);
 #pragma unroll
-  for (int rb = 0; rb < RB0; ++rb)
+    for (int r = 0; r < 2; ++r) {
+      const int rb = 2 * wave + r;
 #pragma unroll
-    for (int j = 0; j < JW; ++j) {
-      const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, j, lane);
+      for (int cb = 0; cb < NCB; ++cb) {
+        if (rb < RB0) {
+          const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, cb, lane);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float sg = sigm(pa[q]);
-        G0[rb][j][q] *= sg * (1.0f + pa[q] * (1.0f - sg));
+          for (int q = 0; q < 4; ++q) acc[r][cb][q] *= dsilu_of(pa[q]);
+        } else {
+          acc[r][cb] = zero4();
+        }
       }
     }
-  // dE/drho_n = sum_f W_0[f][2S + n] ga_0[f]
+  }
   const int K0 = 2 * a.S + a.nb;
+  for (int n = 0; n < a.nb; ++n) {
+    float part[NCB];
 #pragma unroll
-  for (int j = 0; j < JW; ++j) {
-    for (int n = 0; n < a.nb; ++n) {
+    for (int cb = 0; cb < NCB; ++cb) {
       float p = 0.0f;
+      if (wave < NP0) {
 #pragma unroll
-      for (int rb = 0; rb < RB0; ++rb)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int f = 16 * rb + 4 * g + q;
-          if (f < T0) p += a.w0[(int64_t)f * K0 + 2 * a.S + n] * G0[rb][j][q];
-        }
-      p += __shfl_xor(p, 16, 64);
-      p += __shfl_xor(p, 32, 64);
-      if (g == 0 && c.valid[j]) a.grho[c.t[j] * 16 + n] = p;
+          for (int q = 0; q < 4; ++q) {
+            const int f = 16 * (2 * wave + r) + 4 * g + q;
+            if (f < T0) p += a.w0[(int64_t)f * K0 + 2 * a.S + n] * acc[r][cb][q];
+          }
+      }
+      part[cb] = sum_groups(p);
     }
+    wg_edge_sum(S.red, part, tile, M, tid, [&](int64_t t, float v) { a.grho[t * 16 + n] = v; });
   }
 }
 
@@ -832,7 +818,7 @@ static const uint4* frag_ptr(const afm_model* m, int64_t off) {
   return reinterpret_cast<const uint4*>(static_cast<const char*>(m->W.frag) + off);
 }
 
-static dim3 chain_grid(const WsLayout& L) { return dim3(grid_for(L.cex, TILE * WAVES)); }
+static dim3 chain_grid(const WsLayout& L) { return dim3(grid_for(L.cex, TILE)); }
 
 int mfma_twobody_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
                      const int32_t* species, const int32_t* col, hipStream_t st) {
@@ -846,7 +832,7 @@ int mfma_twobody_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                             \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                  \
-    hipLaunchKernelGGL((k_tb_fwd<a0, a1, a2, w, (l + 1) * c>), chain_grid(L), dim3(256), 0, st, a); \
+    hipLaunchKernelGGL((k_tb_fwd<a0, a1, a2, w, (l + 1) * c>), chain_grid(L), dim3(NTHR), 0, st, a); \
     AFM_LAUNCH_CHECK();                                                                            \
     return AFM_OK;                                                                                 \
   }
@@ -864,7 +850,7 @@ int mfma_twobody_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                             \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                  \
-    hipLaunchKernelGGL((k_tb_bwd<a0, a1, a2, w, (l + 1) * c>), chain_grid(L), dim3(256), 0, st, a); \
+    hipLaunchKernelGGL((k_tb_bwd<a0, a1, a2, w, (l + 1) * c>), chain_grid(L), dim3(NTHR), 0, st, a); \
     AFM_LAUNCH_CHECK();                                                                            \
     return AFM_OK;                                                                                 \
   }
@@ -890,9 +876,9 @@ int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                                  \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                       \
     if (last)                                                                                           \
-      hipLaunchKernelGGL((k_lat_fwd<w, n0 * c, (l + 1) * c, dp, true>), chain_grid(L), dim3(256), 0, st, a);  \
+      hipLaunchKernelGGL((k_lat_fwd<w, n0 * c, (l + 1) * c, dp, true>), chain_grid(L), dim3(NTHR), 0, st, a);  \
     else                                                                                                \
-      hipLaunchKernelGGL((k_lat_fwd<w, n0 * c, (l + 1) * c, dp, false>), chain_grid(L), dim3(256), 0, st, a); \
+      hipLaunchKernelGGL((k_lat_fwd<w, n0 * c, (l + 1) * c, dp, false>), chain_grid(L), dim3(NTHR), 0, st, a); \
     AFM_LAUNCH_CHECK();                                                                                 \
     return AFM_OK;                                                                                      \
   }
@@ -917,9 +903,9 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                                  \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                       \
     if (last)                                                                                           \
-      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, true>), chain_grid(L), dim3(256), 0, st, a);  \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, true>), chain_grid(L), dim3(NTHR), 0, st, a);  \
     else                                                                                                \
-      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, false>), chain_grid(L), dim3(256), 0, st, a); \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, false>), chain_grid(L), dim3(NTHR), 0, st, a); \
     AFM_LAUNCH_CHECK();                                                                                 \
     return AFM_OK;                                                                                      \
   }

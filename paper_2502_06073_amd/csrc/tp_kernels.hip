@@ -31,6 +31,21 @@ int upload_cg_table(const float* host_table) {
 }
 
 
+// dst[q] += sum over the C channels (lanes n of one group) of v[q], q < NV
+template <int C, int NV>
+__device__ __forceinline__ void add_channel_sums(float (&v)[16], float* dst, int n) {
+  if constexpr (C == 64) {
+    const float y = wave_sum16(v, n);
+    if ((n & 3) == 0 && (n >> 2) < NV) dst[n >> 2] += y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const float y = group_sum<C>(v[q]);
+      if (n == 0) dst[q] += y;
+    }
+  }
+}
+
 template <int LMAX, int NL, int L>
 struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
@@ -187,6 +202,9 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         for (int q = 0; q < NCI; ++q) a.gvin[(t * NCI + q) * C + n] = GV[q];
       } else {
         // V^0 = omega^1 (x) Y
+        float gyc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
           const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
@@ -194,11 +212,11 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
 #pragma unroll
           for (int m = 0; m < 2 * l + 1; ++m) {
             go += GV[l * l + m] * Y[l * l + m];
-            const float gyv = group_sum<C>(GV[l * l + m] * w);
-            if (n == 0) a.gy[t * GEO_STRIDE + l * l + m] += gyv;
+            gyc[l * l + m] = GV[l * l + m] * w;
           }
           a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
         }
+        add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
       }
     }
     // dE/dGamma summed over the slots, scaled by nbar^-1/2
@@ -215,6 +233,9 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      float gyc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
         const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
@@ -223,12 +244,12 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         for (int m = 0; m < 2 * l + 1; ++m) {
           const float gg = GG[l * l + m];
           go += gg * Y[l * l + m];
-          const float gyv = group_sum<C>(gg * w);
-          if (n == 0) a.gy[t * GEO_STRIDE + l * l + m] += gyv;
+          gyc[l * l + m] = gg * w;
         }
         float* dst = a.gomega + (t * (LMAX + 1) + l) * C + n;
         if constexpr (L == 1) *dst += go; else *dst = go;
       }
+      add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
     }
     __syncthreads();
   }
