@@ -10,6 +10,12 @@ step = build the edge list + energies + forces + virial (every step of the
 path), with inputs resident in HBM.  The BF16-MFMA path is timed as the
 headline value; the plain-FP32 path is timed beside it for the speedup.
 
+Other workloads (one JSON line each, same fields):
+    --config E   1M-atom NVE MD, graph-replayed steps incl. rebuilds
+    --config C   force-matching training step (energies, forces, loss and
+                 its weight gradient through the double backward)
+    --config D   batched evaluation of 512 uneven structures
+
 Prints one JSON line with, besides the contract fields, a "roofline" entry
 for the dominant kernel (algorithmic FLOPs per launch / its average HIP-event
 duration during the timed steps) and a "cpu_baseline" entry (the FP64 oracle
@@ -38,19 +44,22 @@ PEAK_FP32 = 157.3e12    # FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12       # HBM3E, B/s
 
 
-def stage_roofline(costs, stats, n_edges, n_atoms):
+def stage_roofline(costs, stats, n_edges, n_atoms, evals):
     """Per traced stage: algorithmic work / average launch time against the
     roofline that bounds it (MFMA stages: dense BF16 peak; vector stages:
     whichever of FP32 ALU and HBM needs more time for the algorithmic
-    flops and bytes)."""
+    flops and bytes).  `evals` full evaluations were traced; with row
+    chunks a stage launches once per chunk, so the work per launch is the
+    evaluation's work divided by launches per evaluation."""
     out = {}
     for name, st in stats.items():
         c = costs.get(name)
         if c is None or st["launches"] == 0:
             continue
         avg_s = st["total_ms"] / st["launches"] * 1e-3
-        flops = c["flops_per_edge"] * n_edges
-        nbytes = c["bytes_per_edge"] * n_edges + c["bytes_per_atom"] * n_atoms
+        share = evals / st["launches"]
+        flops = c["flops_per_edge"] * n_edges * share
+        nbytes = (c["bytes_per_edge"] * n_edges + c["bytes_per_atom"] * n_atoms) * share
         if c["kind"] == "mfma":
             bound, peak, work, unit = "mfma", PEAK_BF16, flops, "TFLOP/s"
         elif flops / PEAK_FP32 >= nbytes / PEAK_HBM:
@@ -151,6 +160,189 @@ def load_traffic(kernel_stage):
         return None
 
 
+def count_edges(calc, r):
+    """Directed edges with d < r (a count-only neighbour build)."""
+    import ctypes as C
+    import torch
+    import paper_2502_06073_amd as afm
+    from paper_2502_06073_amd import _abi
+    N, B = calc.sysd.n_atoms, calc.sysd.n_struct
+    probe = afm.NeighborList(N, 0, calc.model.device)
+    ws = afm.Workspace(None, N, B, 0, device=calc.model.device)
+    _abi.check("afm_build_neighbors", _abi.load().afm_build_neighbors(
+        C.byref(calc.sysd.struct()), float(r), C.byref(probe.struct()), C.byref(ws.ws),
+        C.c_void_p(torch.cuda.current_stream(calc.model.device).cuda_stream)))
+    return int(probe.n_edges.item())
+
+
+def traced_pass(calc):
+    """One eager build + energy_forces with stage tracing (per-stage GPU ms)."""
+    import torch
+    import paper_2502_06073_amd as afm
+    torch.cuda.synchronize()
+    afm.trace_enable(True)
+    calc.build_neighbors()
+    calc.energy_forces(virial=False)
+    stats = afm.trace_read()
+    afm.trace_enable(False)
+    return stats
+
+
+def bench_md(a):
+    """1M-atom NVE MD (velocity Verlet, dt 0.5 fs, rebuild every 10 steps at
+    r_c + 0.5 A), BF16 path, steps replayed from captured graphs."""
+    import torch
+    import synth
+    import paper_2502_06073_amd as afm
+    hp = synth.load_hparams("E")
+    print("[bench] config E: building the 1M-atom system", file=sys.stderr, flush=True)
+    s = synth.SYSTEMS["E"]()
+    w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS["E"])
+    model = afm.Model(hp, w, precision="bf16")
+    sysd = afm.DeviceSystem.from_synth(s)
+    skin = hp["r_list"] - hp["r_cut"]
+    calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=int(a.max_gib * 2 ** 30))
+    masses = synth.species_masses(hp["n_species"], 3005)
+    v0 = synth.maxwell_boltzmann(masses[s.species], 300.0, 3001)
+    md = afm.MD(calc, masses, v0, dt_fs=0.5, skin=skin, rebuild_every=10, use_graph=True)
+    n_listed = int(calc.nl.n_edges.item())
+    n_active = count_edges(calc, hp["r_cut"])
+    print(f"[bench] E: {s.n_atoms} atoms, {n_listed} listed edges, {n_active} within r_c, "
+          f"{calc.ws.ws.n_chunks} chunks", file=sys.stderr, flush=True)
+    block = 10
+    logs = []
+    for _ in range(max(1, a.warmup // block)):
+        logs.append(md.run(block))
+    torch.cuda.synchronize()
+    n_blocks = max(1, a.steps // block)
+    t0 = time.perf_counter()
+    for _ in range(n_blocks):
+        logs.append(md.run(block))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    K = n_blocks * block
+    value = s.n_atoms * K / dt
+    log = torch.cat(logs).cpu().numpy()
+    etot = log.sum(1) / s.n_atoms
+    print(f"[bench] E: {dt / K * 1e3:.1f} ms/step, {value:.4g} atom-steps/s", file=sys.stderr, flush=True)
+    stats = traced_pass(calc)
+    costs = afm.stage_costs(hp)
+    roofs = stage_roofline(costs, stats, n_active, s.n_atoms, 1)
+    dom = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
+    r = roofs[dom]
+    mlp_flops = sum(roofs[k]["flops_per_launch"] * stats[k]["launches"] for k in roofs if costs[k]["kind"] == "mfma")
+    step_ms = sum(v["total_ms"] for v in stats.values())
+    out = dict(metric="atom-steps/s energy+forces, BF16-MFMA vs FP32 plain; force RMS err vs FP64",
+               value=value, unit="atom-steps/s", n_gpus=1, steps=K, warmup=a.warmup, ms_per_step=dt / K * 1e3,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="bf16",
+               data="synthetic (seeded jittered lattice, Maxwell-Boltzmann 300 K velocities, N(0,1/fan_in) weights)",
+               config=dict(workload=f"{s.n_atoms}-atom NVE MD (100^3 SC lattice a=2.3 A, 4 species), dt 0.5 fs, "
+                                    f"rebuild every 10 steps at r_c 5.5 + 0.5 A skin, l_max 2, 3 layers, latent 256, "
+                                    f"graph-replayed steps incl. rebuilds",
+                           n_atoms=s.n_atoms, n_edges_listed=n_listed, n_edges_within_rc=n_active,
+                           n_chunks=int(calc.ws.ws.n_chunks), parallelism="single GPU"),
+               roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
+                             frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
+               mlp_roofline_frac_one_eval=mlp_flops / (step_ms * 1e-3) / PEAK_BF16,
+               stage_ms_one_eval={k: round(v["total_ms"], 3) for k, v in stats.items()},
+               nve=dict(max_abs_drift_mev_per_atom=float(np.abs(etot - etot[0]).max() * 1e3),
+                        slope_mev_per_atom_per_ps=float(np.polyfit(np.arange(len(etot)) * 0.5e-3, etot, 1)[0] * 1e3),
+                        steps=int(len(etot))))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_train(a):
+    """Force-matching training step on the 64-cluster batch: energies and
+    forces, the loss, and its weight gradient through the double backward."""
+    import torch
+    import synth
+    import paper_2502_06073_amd as afm
+    hp = synth.load_hparams("C")
+    s = synth.SYSTEMS["C"]()
+    w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS["C"])
+    e_hat, f_hat = synth.training_targets(s, 4003)
+    model = afm.Model(hp, w, precision="bf16")
+    sysd = afm.DeviceSystem.from_synth(s)
+    calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]), second_order=True)
+    theta = torch.zeros(calc.model_n_params(), dtype=torch.float64, device="cuda", requires_grad=True)
+    n_s = torch.tensor(np.diff(s.seg), dtype=torch.float64, device="cuda")
+    e_t = torch.tensor(e_hat, device="cuda")
+    f_t = torch.tensor(f_hat, device="cuda")
+
+    def step():
+        calc.build_neighbors()
+        E, F = afm.energy_forces_for_training(calc, theta)
+        de = (E - e_t) / n_s
+        df = F - f_t
+        loss = (de * de).mean() + (df * df).sum() / (3.0 * s.n_atoms)
+        theta.grad = None
+        loss.backward()
+        return loss
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    afm.trace_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = afm.trace_read()
+    afm.trace_enable(False)
+    value = s.n_atoms * a.steps / dt
+    out = dict(metric="atom-steps/s energy+forces, BF16-MFMA vs FP32 plain; force RMS err vs FP64",
+               value=value, unit="atom-steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=dt / a.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="bf16+fp32", data="synthetic (seeded clusters, N(0,1) targets, N(0,1/fan_in) weights)",
+               config=dict(workload=f"force-matching training step, {s.n_struct} clusters / {s.n_atoms} atoms, "
+                                    f"l_max 2, 2 layers, latent 128: BF16 energies+forces, FP32 double backward "
+                                    f"for the weight gradient of the E+F loss",
+                           n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=int(calc.nl.n_edges.item()),
+                           n_params=calc.model_n_params(), parallelism="single GPU"),
+               steps_per_s=a.steps / dt, loss=float(loss.item()),
+               stage_ms={k: round(v["total_ms"] / a.steps, 4) for k, v in stats.items()})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(a):
+    """Batched evaluation of 512 uneven structures (half periodic triclinic,
+    half clusters, 89 species) in one call: edge lists + energies + forces +
+    virials."""
+    import torch
+    import synth
+    import paper_2502_06073_amd as afm
+    hp = synth.load_hparams("D")
+    s = synth.SYSTEMS["D"]()
+    w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS["D"])
+    model = afm.Model(hp, w, precision="bf16")
+    sysd = afm.DeviceSystem.from_synth(s)
+    calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]))
+    calc.build_neighbors()
+    dt, out_, stats = time_steps(calc, a.steps, a.warmup, trace=True)
+    n_edges = int(calc.nl.n_edges.item())
+    costs = afm.stage_costs(hp)
+    roofs = stage_roofline(costs, stats, n_edges, s.n_atoms, a.steps)
+    dom = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
+    r = roofs[dom]
+    value = s.n_atoms * a.steps / dt
+    out = dict(metric="atom-steps/s energy+forces, BF16-MFMA vs FP32 plain; force RMS err vs FP64",
+               value=value, unit="atom-steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=dt / a.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="bf16", data="synthetic (seeded triclinic crystals and clusters, N(0,1/fan_in) weights)",
+               config=dict(workload=f"{s.n_struct} uneven structures / {s.n_atoms} atoms (8..300 per structure, "
+                                    f"half periodic triclinic, half clusters, 89 species), r_c 6 A, l_max 2, "
+                                    f"3 layers, latent 256: one batched call per step incl. edge lists",
+                           n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=n_edges, parallelism="single GPU"),
+               roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
+                             frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
+               stage_ms={k: round(v["total_ms"] / v["launches"], 4) for k, v in stats.items()})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +352,8 @@ def main(argv=None):
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--max-gib", type=float, default=96.0,
+                    help="workspace limit for the 1M-atom MD workload (row chunks beyond it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -182,6 +376,12 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if a.config == "E":
+        return bench_md(a)
+    if a.config == "C":
+        return bench_train(a)
+    if a.config == "D":
+        return bench_batch(a)
     print(f"[bench] config {a.config}: setting up bf16", file=sys.stderr, flush=True)
     hp, s, w, calc = setup(a.config, "bf16")
     n_edges = int(calc.nl.n_edges.item())
@@ -190,7 +390,7 @@ def main(argv=None):
     value = s.n_atoms * a.steps / dt
     print(f"[bench] bf16: {ms:.3f} ms/step, {value:.4g} atom-steps/s", file=sys.stderr, flush=True)
     costs = afm.stage_costs(hp)
-    roofs = stage_roofline(costs, stats, n_edges, s.n_atoms)
+    roofs = stage_roofline(costs, stats, n_edges, s.n_atoms, a.steps)
     # dominant kernel: the stage with the largest GPU time
     dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom_name]
