@@ -45,7 +45,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NCB = 8;            // 16-edge column blocks per workgroup tile
 constexpr int TILE = 16 * NCB;    // edges per workgroup
-constexpr int NWAVE = 8;          // wavefronts per workgroup
+constexpr int NPS = 8;            // output-row pair slots per workgroup
+constexpr int NCBW = NCB / 2;     // column blocks per wavefront
+constexpr int NWAVE = 2 * NPS;    // wavefronts: pair slot x column half
 constexpr int NTHR = 64 * NWAVE;
 constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
 
@@ -182,11 +184,11 @@ __device__ __forceinline__ f32x4 ld_pre(const uint2* pre, int64_t tile, int RB, 
 }
 
 // LDS: two activation buffers of B fragments [kb][cb][64 lanes] (bf16 x 8
-// each) and a [wavefront][edge] scratch row for cross-wavefront sums
+// each) and a [pair slot][edge] scratch row for cross-wavefront sums
 template <int KMAX>
 struct ChainSmem {
   uint4 act[2][cdiv(KMAX, 32) * NCB * 64];
-  float red[NWAVE][TILE];
+  float red[NPS][TILE];
 };
 __device__ __forceinline__ int frag_idx(int kb, int cb, int lane) { return (kb * NCB + cb) * 64 + lane; }
 
@@ -205,6 +207,7 @@ template <int K>
 __device__ __forceinline__ void stage_rows(uint4* __restrict__ act, const float* __restrict__ X, int64_t tile,
                                            int64_t M, int tid) {
   constexpr int NF = cdiv(K, 32) * NCB * 64;
+#pragma unroll 1
   for (int idx = tid; idx < NF; idx += NTHR) {
     const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB);
     const int64_t t = tile * TILE + 16 * cb + (l & 15);
@@ -220,7 +223,7 @@ __device__ __forceinline__ void stage_rows(uint4* __restrict__ act, const float*
 // lo products, so the two MFMAs into one accumulator are 16 apart.
 template <int KBW, int NKB>
 __device__ __forceinline__ void mma_pair(const uint4* __restrict__ W, int pair, int kb0, const uint4* act,
-                                         f32x4 (&acc)[2][NCB], int lane) {
+                                         f32x4 (&acc)[2][NCBW], int half, int lane) {
   const uint4* w0 = W + ((int64_t)(2 * pair) * KBW + kb0) * (kSplit * 64) + lane;
   const uint4* w1 = w0 + (int64_t)KBW * (kSplit * 64);
   uint4 cur[4], nxt[4];
@@ -231,55 +234,62 @@ __device__ __forceinline__ void mma_pair(const uint4* __restrict__ W, int pair, 
       const int o = (kb + 1) * (kSplit * 64);
       nxt[0] = w0[o]; nxt[1] = w0[o + 64]; nxt[2] = w1[o]; nxt[3] = w1[o + 64];
     }
-    bf16x8 b[NCB];
+    bf16x8 b[NCBW];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) b[cb] = __builtin_bit_cast(bf16x8, act[frag_idx(kb, cb, lane)]);
+    for (int c = 0; c < NCBW; ++c)
+      b[c] = __builtin_bit_cast(bf16x8, act[frag_idx(kb, half * NCBW + c, lane)]);
 #pragma unroll
     for (int h = 0; h < kSplit; ++h)
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const bf16x8 A = __builtin_bit_cast(bf16x8, cur[2 * r + h]);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = mfma(A, b[cb], acc[r][cb]);
+        for (int c = 0; c < NCBW; ++c) acc[r][c] = mfma(A, b[c], acc[r][c]);
       }
     if (kb + 1 < NKB) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
     }
+    // keep the scheduler from hoisting later k-blocks' loads (register
+    // pressure at 4 wavefronts per SIMD)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-__device__ __forceinline__ void zero_acc(f32x4 (&acc)[2][NCB]) {
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[2][NCBW]) {
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = zero4();
+    for (int c = 0; c < NCBW; ++c) acc[r][c] = zero4();
 }
 
-// Finalise a pair of row blocks: epi(rb, cb, v) in place for both blocks,
-// then (if out) the pair becomes k-block `pair` of the next layer's input.
+// Finalise a pair of row blocks: epi(rb, c, v) in place for both blocks (c
+// indexes this wavefront's column blocks), then (if out) the pair becomes
+// k-block `pair` of the next layer's input.
 template <class EPI>
-__device__ __forceinline__ void finish_pair(int pair, f32x4 (&acc)[2][NCB], uint4* out, EPI&& epi, int lane) {
+__device__ __forceinline__ void finish_pair(int pair, f32x4 (&acc)[2][NCBW], uint4* out, EPI&& epi, int half,
+                                            int lane) {
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    epi(2 * pair, cb, acc[0][cb]);
-    epi(2 * pair + 1, cb, acc[1][cb]);
-    if (out) out[frag_idx(pair, cb, lane)] = __builtin_bit_cast(uint4, pack8(acc[0][cb], acc[1][cb]));
+  for (int c = 0; c < NCBW; ++c) {
+    epi(2 * pair, c, acc[0][c]);
+    epi(2 * pair + 1, c, acc[1][c]);
+    if (out)
+      out[frag_idx(pair, half * NCBW + c, lane)] = __builtin_bit_cast(uint4, pack8(acc[0][c], acc[1][c]));
   }
 }
 
-// A whole layer from LDS: rows of NPAIR pairs, wavefront w owns pairs
-// w, w + NWAVE, ...; no barrier inside.
+// A whole layer from LDS: rows of NPAIR pairs, the wavefronts of pair slot
+// ps own pairs ps, ps + NPS, ...; no barrier inside.
 template <int NPAIR, int KBW, class EPI>
 __device__ __forceinline__ void layer_lds(const uint4* __restrict__ W, const uint4* in, uint4* out, EPI&& epi,
-                                          int wave, int lane) {
-  static_for<0, cdiv(NPAIR, NWAVE)>([&](auto P) __attribute__((always_inline)) {
-    const int pair = decltype(P)::value * NWAVE + wave;
+                                          int pslot, int half, int lane) {
+  static_for<0, cdiv(NPAIR, NPS)>([&](auto P) __attribute__((always_inline)) {
+    const int pair = decltype(P)::value * NPS + pslot;
     if (pair < NPAIR) {
-      f32x4 acc[2][NCB];
+      f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<KBW, KBW>(W, pair, 0, in, acc, lane);
-      finish_pair(pair, acc, out, epi, lane);
+      mma_pair<KBW, KBW>(W, pair, 0, in, acc, half, lane);
+      finish_pair(pair, acc, out, epi, half, lane);
     }
   });
 }
@@ -334,33 +344,35 @@ struct ChainArgs {
 // empty (uniform, before any barrier).
 #define AFM_TILE_PROLOGUE                                                          \
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;    \
+  const int pslot = wave % NPS, half = wave / NPS;                                 \
   int64_t e0, e1;                                                                  \
   a.rr.get(e0, e1);                                                                \
   const int64_t M = e1 - e0;                                                       \
   const int64_t tile = blockIdx.x;                                                 \
   if (tile * TILE >= M) return;                                                    \
-  float u[NCB];                                                                    \
-  _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) {                             \
-    const int64_t t = tile * TILE + 16 * cb + (lane & 15);                         \
-    u[cb] = t < M ? a.geo[t * GEO_STRIDE + GEO_U] : 0.0f;                          \
-  }                                                                                \
-  auto col_t = [&](int cb) { return tile * TILE + 16 * cb + (lane & 15); };
+  auto cbA = [&](int c) { return half * NCBW + c; };                               \
+  auto col_t = [&](int c) { return tile * TILE + 16 * cbA(c) + (lane & 15); };     \
+  float u[NCBW];                                                                   \
+  _Pragma("unroll") for (int c = 0; c < NCBW; ++c) {                               \
+    const int64_t t = col_t(c);                                                    \
+    u[c] = t < M ? a.geo[t * GEO_STRIDE + GEO_U] : 0.0f;                           \
+  }
 
-// Per-edge sums of this wavefront's partials part[cb] (lane groups already
-// summed) over all wavefronts; fn(t, total) runs once per valid edge.
+// Per-edge sums of this wavefront's partials part[c] (lane groups already
+// summed) over the pair slots; fn(t, total) runs once per valid edge.
 template <class FN>
-__device__ __forceinline__ void wg_edge_sum(float (&red)[NWAVE][TILE], const float (&part)[NCB], int64_t tile,
+__device__ __forceinline__ void wg_edge_sum(float (&red)[NPS][TILE], const float (&part)[NCBW], int64_t tile,
                                             int64_t M, int tid, FN&& fn) {
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = tid >> 6, pslot = wave % NPS, half = wave / NPS;
   if ((lane >> 4) == 0) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) red[wave][16 * cb + lane] = part[cb];
+    for (int c = 0; c < NCBW; ++c) red[pslot][16 * (half * NCBW + c) + lane] = part[c];
   }
   __syncthreads();
   if (tid < TILE) {
     float s = 0.0f;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) s += red[w][tid];
+    for (int w = 0; w < NPS; ++w) s += red[w][tid];
     const int64_t t = tile * TILE + tid;
     if (t < M) fn(t, s);
   }
@@ -431,20 +443,20 @@ __global__ void __launch_bounds__(NTHR) k_tb_fwd(ChainArgs a) {
   auto hidden = [&](uint2* pre, int RB, bool out_layer) {
     return [&, pre, RB, out_layer](int rb, int cb, f32x4& v) {
       if (rb >= RB) return;
-      st_pre(pre, tile, RB, rb, cb, lane, v);
+      st_pre(pre, tile, RB, rb, cbA(cb), lane, v);
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] = out_layer ? u[cb] * v[q] * sigm(v[q]) : v[q] * sigm(v[q]);
       if (out_layer) {
-        const int64_t t = tile * TILE + 16 * cb + (lane & 15);
+        const int64_t t = col_t(cb);
         if (t < M) st4(a.xnew + t * W + 16 * rb + 4 * g, v);
       }
     };
   };
-  layer_lds<cdiv(T1, 32), cdiv(T0, 32)>(a.tbf[1], S.act[0], S.act[1], hidden(a.pre[1], RB1, NT == 2), wave, lane);
+  layer_lds<cdiv(T1, 32), cdiv(T0, 32)>(a.tbf[1], S.act[0], S.act[1], hidden(a.pre[1], RB1, NT == 2), pslot, half, lane);
   __syncthreads();
   int cur = 1;
   if constexpr (NT == 3) {
-    layer_lds<W / 32, cdiv(T1, 32)>(a.tbf[2], S.act[1], S.act[0], hidden(a.pre[2], RBW, true), wave, lane);
+    layer_lds<W / 32, cdiv(T1, 32)>(a.tbf[2], S.act[1], S.act[0], hidden(a.pre[2], RBW, true), pslot, half, lane);
     __syncthreads();
     cur = 0;
   }
@@ -455,7 +467,7 @@ __global__ void __launch_bounds__(NTHR) k_tb_fwd(ChainArgs a) {
         const int64_t t = col_t(cb);
         if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
       },
-      wave, lane);
+      pslot, half, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,19 +477,20 @@ template <int W, int KS, int ENV, int DEPTH, bool LAST>
 __global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
-  static_assert(NPW <= NWAVE, "one pair per wavefront");
+  static_assert(NPW <= NPS, "one pair per pair slot");
   const float r2 = 0.70710678118654752f;
   __shared__ ChainSmem<cmax(W, KS)> S;
-  const int pair = wave;
+  const int pair = pslot;
   const bool mine = pair < NPW;
-  float ep[NCB];
+  float ep[NCBW];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) ep[cb] = 0.0f;
+  for (int cb = 0; cb < NCBW; ++cb) ep[cb] = 0.0f;
   // epilogue of latent layer k: SiLU, or the residual update after the last
-  auto epi = [&](int k) {
-    return [&, k](int rb, int cb, f32x4& v) {
-      st_pre(a.pre[k], tile, RBW, rb, cb, lane, v);
-      if (k < DEPTH - 1) {
+  auto epi = [&](auto K) {
+    constexpr int k = decltype(K)::value;
+    return [&](int rb, int cb, f32x4& v) {
+      st_pre(a.pre[k], tile, RBW, rb, cbA(cb), lane, v);
+      if constexpr (k < DEPTH - 1) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
       } else {
@@ -496,27 +509,29 @@ __global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
       }
     };
   };
-  // layer 0 over [x | s]: x k-blocks, then s k-blocks through the same buffer
-  f32x4 acc[2][NCB];
+  // layer 0 over [x | s]: x staged in one buffer, s in the other; the
+  // output overwrites the x buffer after a barrier
+  f32x4 acc[2][NCBW];
   zero_acc(acc);
   stage_rows<W>(S.act[0], a.xprev, tile, M, tid);
-  __syncthreads();
-  if (mine) mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, lane);
-  __syncthreads();
-  stage_rows<KS>(S.act[0], a.s, tile, M, tid);
+  stage_rows<KS>(S.act[1], a.s, tile, M, tid);
   __syncthreads();
   if (mine) {
-    mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[0], acc, lane);
-    finish_pair(pair, acc, (LAST && DEPTH == 1) ? nullptr : S.act[1], epi(0), lane);
+    mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, half, lane);
+    mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[1], acc, half, lane);
   }
   __syncthreads();
-  int cur = 1;
+  if (mine)
+    finish_pair(pair, acc, (LAST && DEPTH == 1) ? nullptr : S.act[0], epi(std::integral_constant<int, 0>{}),
+                half, lane);
+  __syncthreads();
+  int cur = 0;
   static_for<1, DEPTH>([&](auto K) __attribute__((always_inline)) {
     constexpr int k = decltype(K)::value;
     if (mine) {
       zero_acc(acc);
-      mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, lane);
-      finish_pair(pair, acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(k), lane);
+      mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, half, lane);
+      finish_pair(pair, acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(K), half, lane);
     }
     __syncthreads();
     cur ^= 1;
@@ -528,11 +543,11 @@ __global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
           const int64_t t = col_t(cb);
           if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
         },
-        wave, lane);
+        pslot, half, lane);
   } else {
     // eps_e = w_eff . x^{N_L}
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) ep[cb] = sum_groups(ep[cb]);
+    for (int cb = 0; cb < NCBW; ++cb) ep[cb] = sum_groups(ep[cb]);
     wg_edge_sum(S.red, ep, tile, M, tid, [&](int64_t t, float v) { a.eps[e0 + t] = v; });
   }
 }
@@ -544,18 +559,18 @@ template <int W, int KS, int ENV, int DEPTH, bool LAST>
 __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
-  static_assert(NPW <= NWAVE, "one pair per wavefront");
+  static_assert(NPW <= NPS, "one pair per pair slot");
   const float r2 = 0.70710678118654752f;
   __shared__ ChainSmem<cmax(W, ENV)> S;
-  const int pair = wave;
+  const int pair = pslot;
   const bool mine = pair < NPW;
-  float gu[NCB];
+  float gu[NCBW];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) gu[cb] = 0.0f;
+  for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
   // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2; v = dE/dx^L on entry
   auto head = [&](int rb, int cb, f32x4& v) {
     const int64_t t = col_t(cb);
-    const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, cb, lane);
+    const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, cbA(cb), lane);
     f32x4 res;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -570,9 +585,9 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
   if constexpr (LAST) {
     // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
     if (mine) {
-      float ce[NCB];
+      float ce[NCBW];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
+      for (int cb = 0; cb < NCBW; ++cb) {
         const int64_t t = col_t(cb);
         ce[cb] = 0.0f;
         if (t < M) {
@@ -588,25 +603,25 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
           }
         }
       }
-      f32x4 acc[2][NCB];
+      f32x4 acc[2][NCBW];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const f32x4 we = ld4(a.w_eff + 16 * (2 * pair + r) + 4 * g);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
+        for (int cb = 0; cb < NCBW; ++cb)
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[r][cb][q] = ce[cb] * we[q];
       }
-      finish_pair(pair, acc, S.act[0], head, lane);
+      finish_pair(pair, acc, S.act[0], head, half, lane);
     }
   } else {
     // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
     stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
     __syncthreads();
     if (mine) {
-      f32x4 acc[2][NCB];
+      f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, lane);
+      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, half, lane);
       finish_pair(
           pair, acc, S.act[0],
           [&](int rb, int cb, f32x4& v) {
@@ -614,11 +629,11 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
             if (t < M) v += ld4(a.gx + t * W + 16 * rb + 4 * g);
             head(rb, cb, v);
           },
-          lane);
+          half, lane);
     }
   }
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) gu[cb] = sum_groups(gu[cb]);
+  for (int cb = 0; cb < NCBW; ++cb) gu[cb] = sum_groups(gu[cb]);
   // (the barrier inside also publishes the head's fragments)
   wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
   // inner layers: ga_{k-1} = (W_k^T ga_k) * silu'(a_{k-1})
@@ -626,17 +641,17 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
   static_for<1, DEPTH>([&](auto KK) __attribute__((always_inline)) {
     constexpr int k = DEPTH - decltype(KK)::value;
     if (mine) {
-      f32x4 acc[2][NCB];
+      f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<KBX, KBX>(a.latb[k], pair, 0, S.act[cur], acc, lane);
+      mma_pair<KBX, KBX>(a.latb[k], pair, 0, S.act[cur], acc, half, lane);
       finish_pair(
           pair, acc, S.act[cur ^ 1],
           [&](int rb, int cb, f32x4& v) {
-            const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, cb, lane);
+            const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, cbA(cb), lane);
 #pragma unroll
             for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
           },
-          lane);
+          half, lane);
     }
     __syncthreads();
     cur ^= 1;
@@ -654,7 +669,7 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
           st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
         }
       },
-      wave, lane);
+      pslot, half, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,26 +680,26 @@ __global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int RBW = W / 16, RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), NPW = W / 32;
-  static_assert(NPW <= NWAVE, "one pair per wavefront");
+  static_assert(NPW <= NPS, "one pair per pair slot");
   __shared__ ChainSmem<cmax(cmax(ENV, W), T1)> S;
-  const int pair = wave;
+  const int pair = pslot;
   const bool mine = pair < NPW;
-  float gu[NCB];
+  float gu[NCBW];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) gu[cb] = 0.0f;
+  for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
   // head: x^0 = u silu(a_last); dE/dx^0 = stored + W_env^1T dE/domega^1
   stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
   __syncthreads();
   if (mine) {
-    f32x4 acc[2][NCB];
+    f32x4 acc[2][NCBW];
     zero_acc(acc);
-    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, lane);
+    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, half, lane);
     finish_pair(
         pair, acc, S.act[0],
         [&](int rb, int cb, f32x4& v) {
           const int64_t t = col_t(cb);
           const f32x4 gx = t < M ? ld4(a.gx + t * W + 16 * rb + 4 * g) : zero4();
-          const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, cb, lane);
+          const f32x4 pa = ld_pre(a.pre[NT - 1], tile, RBW, rb, cbA(cb), lane);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float gv = v[q] + gx[q];
@@ -693,10 +708,10 @@ __global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
             v[q] = gv * u[cb] * sg * (1.0f + pa[q] * (1.0f - sg));
           }
         },
-        lane);
+        half, lane);
   }
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) gu[cb] = sum_groups(gu[cb]);
+  for (int cb = 0; cb < NCBW; ++cb) gu[cb] = sum_groups(gu[cb]);
   wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
   int cur = 0;
   if constexpr (NT == 3) {
@@ -704,28 +719,28 @@ __global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
         a.tbb[2], S.act[0], S.act[1],
         [&](int rb, int cb, f32x4& v) {
           if (rb >= RB1) return;
-          const f32x4 pa = ld_pre(a.pre[1], tile, RB1, rb, cb, lane);
+          const f32x4 pa = ld_pre(a.pre[1], tile, RB1, rb, cbA(cb), lane);
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
         },
-        wave, lane);
+        pslot, half, lane);
     __syncthreads();
     cur = 1;
   }
   // ga_0 = (W_1^T ga_1) * silu'(a_0), then dE/drho_n = sum_f W_0[f][2S + n] ga_0[f]
   constexpr int NP0 = cdiv(T0, 32);
-  static_assert(NP0 <= NWAVE, "one pair per wavefront");
-  f32x4 acc[2][NCB];
+  static_assert(NP0 <= NPS, "one pair per pair slot");
+  f32x4 acc[2][NCBW];
   zero_acc(acc);
-  if (wave < NP0) {
-    mma_pair<cdiv(T1, 32), cdiv(T1, 32)>(a.tbb[1], wave, 0, S.act[cur], acc, lane);
+  if (pslot < NP0) {
+    mma_pair<cdiv(T1, 32), cdiv(T1, 32)>(a.tbb[1], pslot, 0, S.act[cur], acc, half, lane);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int rb = 2 * wave + r;
+      const int rb = 2 * pslot + r;
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
+      for (int cb = 0; cb < NCBW; ++cb) {
         if (rb < RB0) {
-          const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, cb, lane);
+          const f32x4 pa = ld_pre(a.pre[0], tile, RB0, rb, cbA(cb), lane);
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[r][cb][q] *= dsilu_of(pa[q]);
         } else {
@@ -736,16 +751,16 @@ __global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
   }
   const int K0 = 2 * a.S + a.nb;
   for (int n = 0; n < a.nb; ++n) {
-    float part[NCB];
+    float part[NCBW];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
+    for (int cb = 0; cb < NCBW; ++cb) {
       float p = 0.0f;
-      if (wave < NP0) {
+      if (pslot < NP0) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int f = 16 * (2 * wave + r) + 4 * g + q;
+            const int f = 16 * (2 * pslot + r) + 4 * g + q;
             if (f < T0) p += a.w0[(int64_t)f * K0 + 2 * a.S + n] * acc[r][cb][q];
           }
       }
