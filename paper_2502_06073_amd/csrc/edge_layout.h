@@ -21,16 +21,20 @@ struct RowRange {
 };
 
 // Operands of the environment-sum / tensor-product kernels of one layer.
+constexpr int kMaxTpLayers = 4;
+
 struct TPArgs {
   RowRange rr;
   const float* geo;
   const float* omega;    // omega^L  [t][lmax+1][C]
   const float* omega1;   // omega^1  (features V^0 = omega^1 (x) Y when L == 1)
-  const float* vin;      // V^{L-1}  [t][n_in_comps][C]   (L > 1)
-  float* vout;           // V^L      [t][n_out_comps][C]  (L < NL)
   float* s;              // s^L      [t][n0e][C]
   float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
   const float* alpha;    // [n_paths][C]
+  // layers before L: V^{L-1} is recomputed per edge from V^0 = omega^1 (x) Y
+  // and these per-atom sums and mixing weights instead of being stored
+  const float* gamma_prev[kMaxTpLayers];   // Gamma^1 .. Gamma^{L-1}
+  const float* alpha_prev[kMaxTpLayers];   // alpha^1 .. alpha^{L-1}
   float inv_sqrt_nbar;
   const float* gs;       // dE/ds^L
   const float* gvout;    // dE/dV^L (L < NL)

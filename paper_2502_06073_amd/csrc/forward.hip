@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include "device_util.h"
+#include "edge_geom.h"
 #include "gemm_f32.h"
 #include "internal.h"
 #include "trace.h"
@@ -80,25 +81,10 @@ __global__ void k_geometry(RowRange rr, const double* __restrict__ pos, const do
       if (rr.row_ptr[mid] <= e) lo = mid; else hi = mid;
     }
     const int64_t i = lo, j = col[e];
-    int64_t sl = 0, sh = B;
-    while (sh - sl > 1) {
-      int64_t mid = (sl + sh) >> 1;
-      if (seg[mid] <= i) sl = mid; else sh = mid;
-    }
-    const bool per = pbc[sl] != 0;
-    double d[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      double s = 0.0;
-      if (per) {
-        const double* h = cell + 9 * sl;
-        s = __dadd_rn(__dadd_rn(__dmul_rn((double)shift[3 * e], h[q]), __dmul_rn((double)shift[3 * e + 1], h[3 + q])),
-                      __dmul_rn((double)shift[3 * e + 2], h[6 + q]));
-      }
-      d[q] = __dadd_rn(__dsub_rn(pos[3 * j + q], pos[3 * i + q]), s);
-    }
-    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
-    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const int64_t sl = struct_of(seg, B, i);
+    float dx, dy, dz;
+    edge_vec_f32(pos, cell, pbc[sl] != 0, sl, i, j, shift + 3 * e, dx, dy, dz);
+    const float r = edge_norm_f32(dx, dy, dz);
     const float inv = r > 0.0f ? 1.0f / r : 0.0f;
     const float u = envelope_f(r / r_cut, poly_p);
     const int64_t t = e - e0;
@@ -426,8 +412,10 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   a.geo = ws_ptr<float>(ws, L.geo);
   a.omega = ws_ptr<float>(ws, L.omega[layer - 1]);
   a.omega1 = ws_ptr<float>(ws, L.omega[0]);
-  a.vin = layer > 1 ? ws_ptr<float>(ws, L.v[layer - 2]) : nullptr;
-  a.vout = layer < d.NL ? ws_ptr<float>(ws, L.v[layer - 1]) : nullptr;
+  for (int l = 1; l < layer; ++l) {
+    a.gamma_prev[l - 1] = ws_ptr<float>(ws, L.gamma[l - 1]);
+    a.alpha_prev[l - 1] = m->W.alpha[l - 1];
+  }
   a.s = ws_ptr<float>(ws, L.s[layer - 1]);
   a.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
   a.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;

@@ -93,6 +93,12 @@ struct WsLayout {
   int64_t atom_virial = 0;     // double [N][9]
   int64_t md_ref = 0;          // double [N][3] positions at the last rebuild
   int64_t md_ke = 0;           // double [ceil(N/256)] kinetic-energy partials
+  // edge list restricted to |delta| < r_c (MD with a skin)
+  int64_t c_row_ptr = 0;       // int64 [N + 1]
+  int64_t c_col = 0, c_rev = 0, c_map = 0, c_idx = 0;  // int32 [capacity]
+  int64_t c_shift = 0;         // int8 [capacity][3]
+  int64_t c_flag = 0;          // uint8 [capacity]
+  int64_t c_n_edges = 0;       // int64 [1]
   // per-chunk edge buffers (CEX edges)
   int64_t cex = 0;
   int64_t eidx = 0;            // int32 [CEX] central atom of each local edge
@@ -165,6 +171,10 @@ struct NlDev {
 int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl,
                            const afm_workspace* ws, const WsLayout& L, int n_species,
                            hipStream_t st);
+// `out` (workspace-backed, same capacity and status as `in`) = the edges of
+// `in` with |delta| < r_cut, row order kept, rev remapped.
+int launch_compact_to_cutoff(const SysDev& s, const NlDev& in, float r_cut, const afm_workspace* ws,
+                             const WsLayout& L, NlDev* out, hipStream_t st);
 
 // chunk boundaries (rows) from row_ptr
 int launch_chunk_rows(const SysDev& s, const NlDev& nl, const afm_workspace* ws,

@@ -3,6 +3,7 @@
 //   v += dt/2 F/m k_acc;  r += dt v;
 //   [k % rebuild_every == 0: wrap periodic atoms by whole lattice shifts,
 //    rebuild the edge list at r_cut + skin];
+//   [skin > 0: keep only the edges with |delta| < r_cut];
 //   F = F(r);  v += dt/2 F/m k_acc;  log (KE, PE)
 // with k_acc = 9.648533212e-3 A fs^-2 per (eV A^-1 amu^-1).  An atom that
 // moved more than skin/2 since the last rebuild sets AFM_FLAG_SKIN.  The
@@ -159,7 +160,14 @@ static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, cons
       hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(3 * N, 256, 4096)), dim3(256), 0, st,
                          (const double*)state->pos, ref, 3 * N);
     }
-    int rc = api_energy_forces_dev(m, s, n, state->e_atom, state->e_struct, state->forces, nullptr, ws, L, st);
+    // with a skin, the edges beyond r_cut (exactly zero contributions) are
+    // dropped before the per-edge pipeline
+    NlDev nc = n;
+    if (state->skin > 0) {
+      int rc = launch_compact_to_cutoff(s, n, (float)m->dims.r_cut, ws, L, &nc, st);
+      if (rc) return rc;
+    }
+    int rc = api_energy_forces_dev(m, s, nc, state->e_atom, state->e_struct, state->forces, nullptr, ws, L, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_md_kick, dim3(gb), dim3(kMdBlock), 0, st, state->vel, (const double*)state->forces,
                        s.species, state->mass_by_species, m->dims.S, N, state->dt_fs, ke_part);

@@ -251,6 +251,14 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   L.atom_virial = take(N * 72);
   L.md_ref = take(N * 24);
   L.md_ke = take(((N + 255) / 256 + 1) * 8);
+  L.c_row_ptr = take((N + 1) * 8);
+  L.c_col = take(cap * 4);
+  L.c_rev = take(cap * 4);
+  L.c_map = take(cap * 4);
+  L.c_idx = take(cap * 4);
+  L.c_shift = take(cap * 3);
+  L.c_flag = take(cap);
+  L.c_n_edges = take(8);
   // per-chunk edge buffers hold whole 256-edge tiles
   const int64_t E = ((ws->n_chunks > 1 ? ws->chunk_edges + ws->max_row : cap) + 255) / 256 * 256;
   L.cex = E;
@@ -269,7 +277,6 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   for (int l = 0; l < d.NL; ++l) L.x[l] = take(E * d.w * 4);
   for (int l = 0; l < d.NL; ++l) L.omega[l] = take(E * (d.lmax + 1) * d.c * 4);
   for (int l = 0; l < d.NL; ++l) L.s[l] = take(E * (int64_t)P.layer[l].n0e * d.c * 4);
-  for (int l = 0; l + 1 < d.NL; ++l) L.v[l] = take(E * (int64_t)P.layer[l].n_out_comps * d.c * 4);
   for (int l = 0; l < d.NL; ++l)
     for (int k = 0; k < d.depth; ++k) L.lat_pre[l][k] = take(E * d.w * pre_bytes);
   L.gx = take(E * gwide * 4);
@@ -452,15 +459,27 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
       for (int q = 0; q < (2 * t.l1 + 1) * (2 * t.l2 + 1) * (2 * t.l3 + 1); ++q) nz += std::fabs(buf[q]) > 1e-12;
       outc += 2 * t.l3 + 1;
     }
-    const double vin = L == 1 ? 0.0 : lp.n_in_comps * C;      // V^L read from memory (layer 1: built from omega)
-    const double vout = last ? 0.0 : lp.n_out_comps * C;
+    // V^{L-1} is rebuilt from omega^1 (x) Y and the earlier layers' per-atom
+    // sums, so layers after the first read omega^1 and L - 1 more Gammas
+    const double prev = L == 1 ? 0.0 : ENV;
+    const double gprev = (L - 1) * NLM * C;
+    const double dV = last ? 0.0 : lp.n_out_comps * C;       // dE/dV^L in (adjoint)
+    const double dVin = L == 1 ? 0.0 : lp.n_in_comps * C;    // dE/dV^{L-1} out (adjoint)
     const double s_out = lp.n0e * C;
-    // environment sum (NLM C fma) + nonzero CG products (2 mul + add each) + alpha mixing
-    const double tpf = 2 * NLM * C + 3 * nz * C + (last ? 0 : 2 * outc * C) + (L == 1 ? NLM * C : 0);
-    add("tp_fwd", L, 1, tpf, 4 * (ENV + NLM + vin + s_out + vout), 4 * NLM * C);
+    // environment sum (NLM C fma) + nonzero CG products (2 mul + add each);
+    // the recomputation of earlier layers is not counted (algorithmic work)
+    double nz0 = 0;
+    for (int k = 0; k < lp.n_paths; ++k) {
+      const PathT& t = lp.p[k];
+      if (t.s_idx < 0) continue;
+      real_cg(t.l1, t.l2, t.l3, buf.data());
+      for (int q = 0; q < (2 * t.l1 + 1) * (2 * t.l2 + 1) * (2 * t.l3 + 1); ++q) nz0 += std::fabs(buf[q]) > 1e-12;
+    }
+    const double tpf = 2 * NLM * C + 3 * (last ? nz0 : nz) * C + (last ? 0 : 2 * outc * C) + NLM * C;
+    add("tp_fwd", L, 1, tpf, 4 * (ENV + NLM + prev + s_out), 4 * (NLM * C + gprev));
     // adjoint: twice the products (dV and dGamma), the mixing, the environment-sum adjoint
-    const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + (L == 1 ? 2 * NLM * C : 0);
-    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + vin + s_out + vout + ENV + vin + NLM), 4 * NLM * C);
+    const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + 2 * NLM * C;
+    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + prev + s_out + dV + dVin + ENV + NLM), 4 * (NLM * C + gprev));
     const double lat = (W + lp.n0e * C) * W + (d.depth - 1) * W * W;
     add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),
         4 * (W + s_out + (last ? 1 : W + ENV) + 1) + 2 * d.depth * W, 0);

@@ -22,6 +22,7 @@
 #include "internal.h"
 #include "trace.h"
 #include "device_util.h"
+#include "edge_geom.h"
 
 namespace afm {
 
@@ -437,6 +438,124 @@ __global__ void k_capacity_flag(const int64_t* row_ptr, int64_t N, int64_t capac
 }
 
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b > 0 ? (n + b - 1) / b : 1); }
+
+// ---- restriction to the cutoff: one wavefront per row ----
+// flag[e] = |delta_e| < r_cut (the geometry kernel's arithmetic); cnt[i] =
+// active edges of row i.  Nothing is written if the list overflowed.
+__global__ void __launch_bounds__(256) k_active_rows(const int64_t* __restrict__ row_ptr, int64_t N,
+                                                     int64_t capacity, const double* __restrict__ pos,
+                                                     const double* __restrict__ cell,
+                                                     const uint8_t* __restrict__ pbc,
+                                                     const int64_t* __restrict__ seg, int64_t B,
+                                                     const int32_t* __restrict__ col,
+                                                     const int8_t* __restrict__ shift, float r_cut,
+                                                     uint8_t* __restrict__ flag, int64_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i > N) return;
+  if (row_ptr[N] > capacity) return;
+  if (i == N) {
+    if (lane == 0) cnt[N] = 0;
+    return;
+  }
+  const int64_t sl = struct_of(seg, B, i);
+  const bool per = pbc[sl] != 0;
+  int n = 0;
+  for (int64_t e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) {
+    float dx, dy, dz;
+    edge_vec_f32(pos, cell, per, sl, i, col[e], shift + 3 * e, dx, dy, dz);
+    const bool act = edge_norm_f32(dx, dy, dz) / r_cut < 1.0f;
+    flag[e] = act ? 1 : 0;
+    n += act ? 1 : 0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  if (lane == 0) cnt[i] = n;
+}
+
+// compacted col/shift in row order; map[c] = listed edge, idx[e] = its slot
+__global__ void __launch_bounds__(256) k_compact_rows(const int64_t* __restrict__ row_ptr, int64_t N,
+                                                      int64_t capacity, const int64_t* __restrict__ crow,
+                                                      const uint8_t* __restrict__ flag,
+                                                      const int32_t* __restrict__ col,
+                                                      const int8_t* __restrict__ shift, int32_t* __restrict__ ccol,
+                                                      int8_t* __restrict__ cshift, int32_t* __restrict__ map,
+                                                      int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  if (row_ptr[N] > capacity) return;
+  int64_t base = crow[i];
+  for (int64_t e0 = row_ptr[i]; e0 < row_ptr[i + 1]; e0 += 64) {
+    const int64_t e = e0 + lane;
+    const bool act = e < row_ptr[i + 1] && flag[e];
+    const uint64_t m = __ballot(act);
+    if (act) {
+      const int64_t c = base + __popcll(m & ((uint64_t(1) << lane) - 1));
+      ccol[c] = col[e];
+      cshift[3 * c] = shift[3 * e];
+      cshift[3 * c + 1] = shift[3 * e + 1];
+      cshift[3 * c + 2] = shift[3 * e + 2];
+      map[c] = (int32_t)e;
+      idx[e] = (int32_t)c;
+    }
+    base += __popcll(m);
+  }
+}
+
+// rev of a kept edge is kept (delta_rev = -delta_e bit for bit, so the
+// norms agree); the flag test only guards the index
+__global__ void k_compact_rev(const int64_t* __restrict__ row_ptr, int64_t N, int64_t capacity,
+                              const int64_t* __restrict__ crow, const int32_t* __restrict__ map,
+                              const int32_t* __restrict__ rev, const uint8_t* __restrict__ flag,
+                              const int32_t* __restrict__ idx, int32_t* __restrict__ crev,
+                              int64_t* __restrict__ n_edges) {
+  if (row_ptr[N] > capacity) return;
+  const int64_t E = crow[N];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_edges = E;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < E; c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = rev[map[c]];
+    crev[c] = flag[r] ? idx[r] : (int32_t)c;
+  }
+}
+
+int launch_compact_to_cutoff(const SysDev& s, const NlDev& in, float r_cut, const afm_workspace* ws,
+                             const WsLayout& L, NlDev* out, hipStream_t st) {
+  TraceScope tr(st, "compact");
+  const int64_t N = s.N;
+  int64_t* crow = ws_ptr<int64_t>(ws, L.c_row_ptr);
+  uint8_t* flag = ws_ptr<uint8_t>(ws, L.c_flag);
+  int64_t* cnt = ws_ptr<int64_t>(ws, L.nb_counts);
+  int64_t* sums = ws_ptr<int64_t>(ws, L.nb_scan);
+  NlDev o = in;
+  o.row_ptr = crow;
+  o.col = ws_ptr<int32_t>(ws, L.c_col);
+  o.shift = ws_ptr<int8_t>(ws, L.c_shift);
+  o.rev = ws_ptr<int32_t>(ws, L.c_rev);
+  o.n_edges = ws_ptr<int64_t>(ws, L.c_n_edges);
+  // an overflowed list leaves an empty compacted list (the status flag is set)
+  int rc = zero_async(crow, (N + 1) * 8, st);
+  if (!rc) rc = zero_async(cnt, (N + 1) * 8, st);
+  if (rc) return rc;
+  if (in.capacity > 0) {
+    hipLaunchKernelGGL(k_active_rows, dim3(nblk(N + 1, 4)), dim3(256), 0, st, (const int64_t*)in.row_ptr, N,
+                       in.capacity, s.pos, s.cell, s.pbc, s.seg, s.B, (const int32_t*)in.col,
+                       (const int8_t*)in.shift, r_cut, flag, cnt);
+    rc = exclusive_scan<int64_t>(cnt, crow, N + 1, sums, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_compact_rows, dim3(nblk(N, 4)), dim3(256), 0, st, (const int64_t*)in.row_ptr, N,
+                       in.capacity, (const int64_t*)crow, (const uint8_t*)flag, (const int32_t*)in.col,
+                       (const int8_t*)in.shift, o.col, o.shift, ws_ptr<int32_t>(ws, L.c_map),
+                       ws_ptr<int32_t>(ws, L.c_idx));
+    hipLaunchKernelGGL(k_compact_rev, dim3(2048), dim3(256), 0, st, (const int64_t*)in.row_ptr, N, in.capacity,
+                       (const int64_t*)crow, (const int32_t*)ws_ptr<int32_t>(ws, L.c_map),
+                       (const int32_t*)in.rev, (const uint8_t*)flag, (const int32_t*)ws_ptr<int32_t>(ws, L.c_idx),
+                       o.rev, o.n_edges);
+  }
+  AFM_LAUNCH_CHECK();
+  *out = o;
+  return AFM_OK;
+}
 
 int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, const afm_workspace* ws,
                            const WsLayout& L, int n_species, hipStream_t st) {

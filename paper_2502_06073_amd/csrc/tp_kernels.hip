@@ -51,10 +51,27 @@ struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
 };
 
-template <int LMAX, int NL, int L, int C>
-__device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const float* Y, float* V) {
-  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
-  if constexpr (L == 1) {
+// Gamma^1 .. Gamma^{L-1} of atom i, channel n (registers)
+template <int LMAX, int L, int C>
+__device__ __forceinline__ void load_gamma_prev(const TPArgs& a, int64_t i, int n,
+                                                float (&Gp)[L > 1 ? L - 1 : 1][(LMAX + 1) * (LMAX + 1)]) {
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+#pragma unroll
+  for (int l = 0; l + 1 < L; ++l)
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) Gp[l][q] = a.gamma_prev[l][(i * NLM + q) * C + n];
+}
+
+template <int LMAX, int NL, int L, int K>
+__device__ __forceinline__ void path_fwd(const float* V, const float* G, float* T);
+
+// Output features of layer K (V^K, the input of layer K + 1) for edge t,
+// channel n, recomputed from V^0 = omega^1 (x) Y through layers 1..K with
+// Gamma^l = Gp[l - 1] and the mixing weights alpha^l.
+template <int LMAX, int NL, int K, int C, int NG>
+__device__ __forceinline__ void recompute_V(const TPArgs& a, int64_t t, int n, const float* Y,
+                                            const float (&Gp)[NG][(LMAX + 1) * (LMAX + 1)], float* V) {
+  if constexpr (K == 0) {
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
@@ -62,8 +79,22 @@ __device__ __forceinline__ void load_V(const TPArgs& a, int64_t t, int n, const 
       for (int m = 0; m < 2 * l + 1; ++m) V[l * l + m] = w * Y[l * l + m];
     }
   } else {
+    constexpr LayerPlan LP = PlanCT<LMAX, NL>::plan.layer[K - 1];
+    float Vin[LP.n_in_comps];
+    recompute_V<LMAX, NL, K - 1, C, NG>(a, t, n, Y, Gp, Vin);
 #pragma unroll
-    for (int q = 0; q < LP.n_in_comps; ++q) V[q] = a.vin[(t * LP.n_in_comps + q) * C + n];
+    for (int q = 0; q < LP.n_out_comps; ++q) V[q] = 0.0f;
+    static_for<0, LP.n_paths>([&](auto P) {
+      constexpr int k = decltype(P)::value;
+      constexpr PathT pt = LP.p[k];
+      if constexpr (pt.out_off >= 0) {
+        float T[2 * pt.l3 + 1];
+        path_fwd<LMAX, NL, K, k>(Vin, Gp[K - 1], T);
+        const float al = a.alpha_prev[K - 1][k * C + n];
+#pragma unroll
+        for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) V[pt.out_off + m3] += al * T[m3];
+      }
+    });
   }
 }
 
@@ -121,30 +152,24 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     float G[NLM];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
+    float Gp[L > 1 ? L - 1 : 1][NLM];
+    load_gamma_prev<LMAX, L, C>(a, i, n, Gp);
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI];
-      load_V<LMAX, NL, L, C>(a, t, n, Y, V);
-      float out[NCO];
-#pragma unroll
-      for (int q = 0; q < NCO; ++q) out[q] = 0.0f;
+      recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
+      // only the scalar (0e) paths leave the kernel; V^L is recomputed by
+      // the layers that read it
       static_for<0, LP.n_paths>([&](auto K) {
         constexpr int k = decltype(K)::value;
         constexpr PathT pt = LP.p[k];
-        float T[2 * pt.l3 + 1];
-        path_fwd<LMAX, NL, L, k>(V, G, T);
-        if constexpr (pt.s_idx >= 0) a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
-        if constexpr (pt.out_off >= 0) {
-          const float al = a.alpha[k * C + n];
-#pragma unroll
-          for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) out[pt.out_off + m3] += al * T[m3];
+        if constexpr (pt.s_idx >= 0) {
+          float T[2 * pt.l3 + 1];
+          path_fwd<LMAX, NL, L, k>(V, G, T);
+          a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
         }
       });
-      if constexpr (LP.n_out_comps > 0) {
-#pragma unroll
-        for (int q = 0; q < LP.n_out_comps; ++q) a.vout[(t * LP.n_out_comps + q) * C + n] = out[q];
-      }
     }
     __syncthreads();
   }
@@ -168,11 +193,13 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       G[q] = a.gamma[(i * NLM + q) * C + n];
       GG[q] = 0.0f;
     }
+    float Gp[L > 1 ? L - 1 : 1][NLM];
+    load_gamma_prev<LMAX, L, C>(a, i, n, Gp);
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI], GV[NCI];
-      load_V<LMAX, NL, L, C>(a, t, n, Y, V);
+      recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
 #pragma unroll
       for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
       static_for<0, LP.n_paths>([&](auto K) {
