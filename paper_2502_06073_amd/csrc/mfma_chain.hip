@@ -43,11 +43,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NCB = 8;            // 16-edge column blocks per workgroup tile
+constexpr int NCB = 4;            // 16-edge column blocks per workgroup tile
 constexpr int TILE = 16 * NCB;    // edges per workgroup
 constexpr int NPS = 8;            // output-row pair slots per workgroup
-constexpr int NCBW = NCB / 2;     // column blocks per wavefront
-constexpr int NWAVE = 2 * NPS;    // wavefronts: pair slot x column half
+constexpr int NCBW = NCB;         // column blocks per wavefront
+constexpr int NWAVE = NPS * (NCB / NCBW);  // wavefronts: pair slot x column group
 constexpr int NTHR = 64 * NWAVE;
 constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
 
@@ -385,7 +385,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // two-body MLP + environment embedding of layer 1 (forward)
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(NTHR) k_tb_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_tb_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int TL = NT == 3 ? T2 : T1;
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(NTHR) k_tb_fwd(ChainArgs a) {
 // latent MLP of one layer (forward) + next environment embedding or energies
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_lat_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
   static_assert(NPW <= NPS, "one pair per pair slot");
@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(NTHR) k_lat_fwd(ChainArgs a) {
 // adjoint of one latent layer: dE/dx^L -> dE/dx^{L-1}, dE/ds^L, dE/du
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_lat_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
   static_assert(NPW <= NPS, "one pair per pair slot");
@@ -676,7 +676,7 @@ __global__ void __launch_bounds__(NTHR) k_lat_bwd(ChainArgs a) {
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(NTHR) k_tb_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_tb_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int RBW = W / 16, RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), NPW = W / 32;
