@@ -315,7 +315,7 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
       const int64_t in = k ? d.tb[k - 1] : 2 * d.S + d.nb;
       maxw = maxw > in * d.tb[k] ? maxw : in * d.tb[k];
     }
-    L.so_partial = take(32 * maxw * 4);
+    L.so_partial = take(256 * maxw * 4);   // up to 256 row slices of one weight gradient
     L.so_gacc = take(m->n_params * 8);
     L.so_q = take((int64_t)d.w * 8);
     for (int l = 0; l + 1 < d.NL; ++l) L.so_galpha[l] = take(N * (int64_t)P.layer[l].n_paths * d.c * 4);

@@ -28,7 +28,9 @@
 
 namespace afm {
 
-constexpr int kSlices = 32;
+// weight gradients reduce over edge rows in slices summed afterwards in a
+// fixed order; enough slices that a launch has ~1024 workgroups
+constexpr int kMaxSlices = 256;
 
 __device__ __forceinline__ float sig_f(float a) { return 1.0f / (1.0f + expf(-a)); }
 __device__ __forceinline__ float d1silu(float a) {
@@ -740,26 +742,51 @@ __global__ void k_reduce_slices(const float* __restrict__ P, int slices, int N, 
   }
 }
 
-// per-atom shares -> gacc (fixed order over atoms)
-__global__ void k_reduce_atoms(const float* __restrict__ part, int64_t N, int64_t width, double* __restrict__ gacc,
-                               int64_t off) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < width; q += (int64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    for (int64_t i = 0; i < N; ++i) v += (double)part[i * width + q];
-    gacc[off + q] += v;
+// per-atom shares -> gacc (fixed order over atoms): a block owns 64
+// columns; its 16 row groups sum atoms g, g + 16, ... and are combined in
+// a fixed order
+__global__ void __launch_bounds__(1024) k_reduce_atoms(const float* __restrict__ part, int64_t N, int64_t width,
+                                                       double* __restrict__ gacc, int64_t off) {
+  __shared__ double red[16][64];
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + c;
+  double v = 0.0;
+  if (q < width)
+    for (int64_t i = grp; i < N; i += 16) v += (double)part[i * width + q];
+  red[grp][c] = v;
+  __syncthreads();
+  if (grp == 0 && q < width) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k][c];
+    gacc[off + q] += t;
   }
 }
 
-__global__ void k_species_grad(const double* __restrict__ a_sig, const double* __restrict__ a_mu,
-                               const int32_t* __restrict__ species, int64_t N, int S, double* __restrict__ gacc,
-                               int64_t off_sig, int64_t off_mu) {
-  const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= S) return;
+// one block per species: threads sum atoms tid, tid + 256, ... of that
+// species, combined by a fixed-order tree
+__global__ void __launch_bounds__(256) k_species_grad(const double* __restrict__ a_sig,
+                                                      const double* __restrict__ a_mu,
+                                                      const int32_t* __restrict__ species, int64_t N, int S,
+                                                      double* __restrict__ gacc, int64_t off_sig, int64_t off_mu) {
+  __shared__ double r1[256], r2[256];
+  const int z = blockIdx.x;
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t i = 0; i < N; ++i)
+  for (int64_t i = threadIdx.x; i < N; i += 256)
     if (species[i] == z) { s1 += a_sig[i]; s2 += a_mu[i]; }
-  gacc[off_sig + z] += s1;
-  gacc[off_mu + z] += s2;
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    gacc[off_sig + z] += r1[0];
+    gacc[off_mu + z] += r2[0];
+  }
 }
 
 // dJ/dW_E1[h][f] = W_E2[h] q[f];  dJ/dW_E2[h] = sum_f W_E1[h][f] q[f]
@@ -797,11 +824,14 @@ template <class ALA, class ALB>
 static int wgrad(hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, ALB Bl, float* partial,
                  double* gacc, int64_t off, int env_c = 0, int env_l1 = 0) {
   const int rows = 2 * stack;
-  const int rps = ((rows + kSlices - 1) / kSlices + 15) / 16 * 16;
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)kSlices);
+  const int tiles = ((N + 63) / 64) * ((K + 63) / 64);
+  int slices = (1024 + tiles - 1) / tiles;
+  slices = slices < 1 ? 1 : (slices > kMaxSlices ? kMaxSlices : slices);
+  const int rps = ((rows + slices - 1) / slices + 15) / 16 * 16;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)slices);
   hipLaunchKernelGGL((k_wgrad<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
   hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for((int64_t)N * K, 256, 4096)), dim3(256), 0, st,
-                     (const float*)partial, kSlices, N, K, gacc, off, env_c, env_l1);
+                     (const float*)partial, slices, N, K, gacc, off, env_c, env_l1);
   AFM_LAUNCH_CHECK();
   return AFM_OK;
 }
@@ -1005,11 +1035,11 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   for (int layer = 1; layer < d.NL; ++layer) {
     snprintf(nm, sizeof nm, "layer%d.alpha", layer);
     const int64_t width = (int64_t)P.layer[layer - 1].n_paths * d.c;
-    hipLaunchKernelGGL(k_reduce_atoms, dim3(grid_for(width, 256, 4096)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_reduce_atoms, dim3((unsigned)((width + 63) / 64)), dim3(1024), 0, st,
                        (const float*)ws_ptr<float>(ws, L.so_galpha[layer - 1]), s.N, width, gacc,
                        block_offset(m, nm));
   }
-  hipLaunchKernelGGL(k_species_grad, dim3(grid_for(d.S, 128)), dim3(128), 0, st,
+  hipLaunchKernelGGL(k_species_grad, dim3((unsigned)d.S), dim3(256), 0, st,
                      (const double*)ws_ptr<double>(ws, L.so_asig), (const double*)ws_ptr<double>(ws, L.so_amu),
                      s.species, s.N, d.S, gacc, block_offset(m, "species.scale"), block_offset(m, "species.shift"));
   hipLaunchKernelGGL(k_edge_grad, dim3(grid_for((int64_t)d.h * d.w + d.h, 256, 4096)), dim3(256), 0, st,
