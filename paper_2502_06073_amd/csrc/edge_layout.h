@@ -29,6 +29,7 @@ struct TPArgs {
   const float* omega;    // omega^L  [t][lmax+1][C]
   const float* omega1;   // omega^1  (features V^0 = omega^1 (x) Y when L == 1)
   float* s;              // s^L      [t][n0e][C]
+  uint16_t* s16;         // s^L as bf16 bits (BF16 path: the MLP rounds s to bf16 anyway)
   float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
   const float* alpha;    // [n_paths][C]
   // layers before L: V^{L-1} is recomputed per edge from V^0 = omega^1 (x) Y

@@ -416,7 +416,8 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
     a.gamma_prev[l - 1] = ws_ptr<float>(ws, L.gamma[l - 1]);
     a.alpha_prev[l - 1] = m->W.alpha[l - 1];
   }
-  a.s = ws_ptr<float>(ws, L.s[layer - 1]);
+  if (m->prec == AFM_BF16_MFMA) a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
+  else a.s = ws_ptr<float>(ws, L.s[layer - 1]);
   a.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
   a.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;
   a.inv_sqrt_nbar = (float)(1.0 / sqrt(d.nbar));

@@ -215,6 +215,24 @@ __device__ __forceinline__ void stage_rows(uint4* __restrict__ act, const float*
   }
 }
 
+// The same from a bf16 matrix X[t][K] (K a multiple of 4): the fragment's
+// two runs of 4 features are copied as 8-byte words, no conversion.
+template <int K>
+__device__ __forceinline__ void stage_rows_bf16(uint4* __restrict__ act, const uint16_t* __restrict__ X,
+                                                int64_t tile, int64_t M, int tid) {
+  constexpr int NF = cdiv(K, 32) * NCB * 64;
+#pragma unroll 1
+  for (int idx = tid; idx < NF; idx += NTHR) {
+    const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB), g = l >> 4;
+    const int64_t t = tile * TILE + 16 * cb + (l & 15);
+    const int fa = 32 * kb + 4 * g, fb = fa + 16;
+    const bool valid = t < M;
+    const uint2 lo = (valid && fa + 4 <= K) ? *reinterpret_cast<const uint2*>(X + t * K + fa) : uint2{0u, 0u};
+    const uint2 hi = (valid && fb + 4 <= K) ? *reinterpret_cast<const uint2*>(X + t * K + fb) : uint2{0u, 0u};
+    act[idx] = uint4{lo.x, lo.y, hi.x, hi.y};
+  }
+}
+
 // acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
 //   W[2 pair + r][kb] x act[kb - kb0][cb]
 // W: packed weight fragments [RB][KBW][hi, lo][64]; act: LDS fragments.
@@ -328,7 +346,7 @@ struct ChainArgs {
   const uint4* latb[kMaxDepth];
   const float* xprev;     // x^{L-1}
   float* xnew;            // x^L (or x^0)
-  const float* s;         // s^L
+  const uint16_t* s16;   // s^L (bf16 bits)
   float* omega;           // omega^{L+1} (or omega^1)
   float* eps;             // edge energies (global edge index)
   uint2* pre[kMaxDepth];  // bf16 pre-activations per MLP layer
@@ -514,7 +532,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   f32x4 acc[2][NCBW];
   zero_acc(acc);
   stage_rows<W>(S.act[0], a.xprev, tile, M, tid);
-  stage_rows<KS>(S.act[1], a.s, tile, M, tid);
+  stage_rows_bf16<KS>(S.act[1], a.s16, tile, M, tid);
   __syncthreads();
   if (mine) {
     mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, half, lane);
@@ -883,7 +901,7 @@ int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   if (layer < d.NL) a.envf = frag_ptr(m, fo->envf[layer]);
   a.xprev = ws_ptr<float>(ws, L.x[layer - 1]);
   a.xnew = layer < d.NL ? ws_ptr<float>(ws, L.x[layer]) : nullptr;
-  a.s = ws_ptr<float>(ws, L.s[layer - 1]);
+  a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
   a.omega = layer < d.NL ? ws_ptr<float>(ws, L.omega[layer]) : nullptr;
   a.eps = ws_ptr<float>(ws, L.eps);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);

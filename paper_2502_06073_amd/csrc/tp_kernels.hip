@@ -31,6 +31,7 @@ int upload_cg_table(const float* host_table) {
 }
 
 
+__device__ __forceinline__ uint16_t to_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 // dst[q] += sum over the C channels (lanes n of one group) of v[q], q < NV
 template <int C, int NV>
 __device__ __forceinline__ void add_channel_sums(float (&v)[16], float* dst, int n) {
@@ -167,7 +168,8 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
         if constexpr (pt.s_idx >= 0) {
           float T[2 * pt.l3 + 1];
           path_fwd<LMAX, NL, L, k>(V, G, T);
-          a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
+          const int64_t si = (t * LP.n0e + pt.s_idx) * C + n;
+          if (a.s16) a.s16[si] = to_bf16_bits(T[0]); else a.s[si] = T[0];
         }
       });
     }
@@ -200,6 +202,13 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI], GV[NCI];
       recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
+      // dE/dV^L of this edge and channel, one storage-type branch per edge
+      float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
+      if constexpr (LP.n_out_comps > 0) {
+        const int64_t g0 = t * LP.n_out_comps * C + n;
+#pragma unroll
+        for (int q = 0; q < LP.n_out_comps; ++q) GVO[q] = a.gvout[g0 + q * C];
+      }
 #pragma unroll
       for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
       static_for<0, LP.n_paths>([&](auto K) {
@@ -214,8 +223,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         if constexpr (pt.out_off >= 0) {
           const float al = a.alpha[k * C + n];
 #pragma unroll
-          for (int m3 = 0; m3 < d3; ++m3)
-            GT[m3] += al * a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
+          for (int m3 = 0; m3 < d3; ++m3) GT[m3] += al * GVO[pt.out_off + m3];
         }
         static_for<0, nz.n>([&](auto Q) {
           constexpr int q = decltype(Q)::value;

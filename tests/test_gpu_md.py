@@ -85,3 +85,27 @@ def test_md_bf16_energy_drift_small():
     _say(f"[md bf16] 100 steps: max |E(t)-E(0)|/N = {drift * 1e3:.3f} meV/atom; KE/N {log[:, 0].mean() / s.n_atoms:.3f}")
     assert drift < 0.05
     assert md.calc.status() == 0
+
+
+def test_md_cutoff_compaction_matches_full_list():
+    """With a skin, the MD step evaluates forces on the list restricted to
+    |delta| < r_cut; at the same positions the full r_cut + skin list must
+    give the same forces and energies (skin edges contribute exactly zero),
+    up to the summation order of the environment sums."""
+    import torch
+    s = synth.cubic_lattice(6, 2.3, 0.25, 4, 98)
+    hp, w, s, masses, v0, md = _setup("fp32", s=s, cfg="E", rebuild=3)
+    md.run(5)
+    torch.cuda.synchronize()
+    F_md = md.forces.cpu().numpy().copy()
+    E_md = md.e_atom.cpu().numpy().copy()
+    nl_listed = int(md.calc.nl.n_edges.item())
+    md.calc.build_neighbors()
+    out = md.calc.energy_forces(virial=False)
+    F = out["forces"].cpu().numpy()
+    E = out["e_atom"].cpu().numpy()
+    rel_f = np.linalg.norm(F_md - F) / np.linalg.norm(F)
+    rel_e = np.linalg.norm(E_md - E) / np.linalg.norm(E)
+    _say(f"[md compaction] listed edges {nl_listed}; force rel {rel_f:.2e}, e_atom rel {rel_e:.2e}")
+    assert rel_f < 1e-5 and rel_e < 1e-5
+    assert md.calc.status() == 0
