@@ -411,9 +411,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   __shared__ ChainSmem<cmax(cmax(T0, T1), W)> S;
   constexpr int RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), RBW = W / 16;
   // first layer on the vector ALUs (one-hot columns are gathers), SiLU,
-  // straight into LDS fragments
+  // straight into LDS fragments; the radial columns of W_0 are staged in LDS
+  __shared__ float w0r[T0 * 16];
   {
     const int K0 = 2 * a.S + a.nb;
+    for (int q = tid; q < T0 * 16; q += NTHR) {
+      const int f = q / 16, nn = q % 16;
+      w0r[q] = nn < a.nb ? a.w0[(int64_t)f * K0 + 2 * a.S + nn] : 0.0f;
+    }
+    __syncthreads();
     constexpr int NF = cdiv(T0, 32) * NCB * 64;
     for (int idx = tid; idx < NF; idx += NTHR) {
       const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB), gl = l >> 4;
@@ -444,8 +450,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
             const float* w = a.w0 + (int64_t)f * K0;
             sacc = w[zi] + w[a.S + zj];
 #pragma unroll
-            for (int n = 0; n < 16; ++n)
-              if (n < a.nb) sacc += w[2 * a.S + n] * rho[n];
+            for (int n = 0; n < 16; ++n) sacc += w0r[f * 16 + n] * rho[n];
           }
           v[h][q] = sacc;
         }
@@ -768,6 +773,13 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     }
   }
   const int K0 = 2 * a.S + a.nb;
+  // radial columns of W_0
+  __shared__ float w0r[T0 * 16];
+  for (int q = tid; q < T0 * 16; q += NTHR) {
+    const int f = q / 16, nn = q % 16;
+    w0r[q] = nn < a.nb ? a.w0[(int64_t)f * K0 + 2 * a.S + nn] : 0.0f;
+  }
+  __syncthreads();
   for (int n = 0; n < a.nb; ++n) {
     float part[NCBW];
 #pragma unroll
@@ -779,7 +791,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int f = 16 * (2 * pslot + r) + 4 * g + q;
-            if (f < T0) p += a.w0[(int64_t)f * K0 + 2 * a.S + n] * acc[r][cb][q];
+            if (f < T0) p += w0r[f * 16 + n] * acc[r][cb][q];
           }
       }
       part[cb] = sum_groups(p);
