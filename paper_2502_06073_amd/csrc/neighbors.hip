@@ -198,85 +198,135 @@ __global__ void k_bin_fill(const AtomMeta* __restrict__ am, int64_t N, const int
   bin_atoms[bin_start[b] + slot] = (int32_t)i;
 }
 
-// One pass over the candidates of row i; WRITE = false counts, true fills.
+// One wavefront per row i: the candidates (every atom of the structure
+// times every image in the window, or the atoms of the 27 surrounding bins)
+// are spread over the 64 lanes.  WRITE = false counts, true fills; hits of a
+// 64-candidate batch are ranked by ballot, so rows of all-pairs structures
+// come out in canonical (j, n) order (candidates are enumerated in that
+// order) and rows of binned structures are sorted afterwards.
 template <bool WRITE>
-__global__ void k_rows(const double* __restrict__ pos, const double* __restrict__ cell,
-                       const uint8_t* __restrict__ pbc, const int64_t* __restrict__ seg, int64_t N,
-                       int64_t B, double r2, const StructMeta* __restrict__ meta,
-                       const AtomMeta* __restrict__ am, const int32_t* __restrict__ bin_start,
-                       const int32_t* __restrict__ bin_atoms,
-                       int64_t* __restrict__ counts, const int64_t* __restrict__ row_ptr,
-                       int64_t capacity, int32_t* __restrict__ col, int8_t* __restrict__ shift,
-                       int32_t* status, int max_row) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_rows(const double* __restrict__ pos, const double* __restrict__ cell,
+                                              const uint8_t* __restrict__ pbc, const int64_t* __restrict__ seg,
+                                              int64_t N, int64_t B, double r2, const StructMeta* __restrict__ meta,
+                                              const AtomMeta* __restrict__ am, const int32_t* __restrict__ bin_start,
+                                              const int32_t* __restrict__ bin_atoms, int64_t* __restrict__ counts,
+                                              const int64_t* __restrict__ row_ptr, int64_t capacity,
+                                              int32_t* __restrict__ col, int8_t* __restrict__ shift,
+                                              int32_t* status, int max_row) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i > N) return;
-  if (!WRITE && i == N) { counts[N] = 0; return; }
-  if (i == N) return;
+  if (i == N) {
+    if (!WRITE && lane == 0) counts[N] = 0;
+    return;
+  }
   if (WRITE && row_ptr[N] > capacity) return;
   const int s = find_struct(seg, B, i);
   const StructMeta& M = meta[s];
   const bool periodic = pbc[s] != 0;
-  const AtomMeta ai0 = am[i];
-  if (M.mode == 2 || (M.mode == 1 && ai0.bin < 0)) {
-    if (!WRITE) counts[i] = 0;
+  const AtomMeta ai = am[i];
+  if (M.mode == 2 || (M.mode == 1 && ai.bin < 0)) {
+    if (!WRITE && lane == 0) counts[i] = 0;
     return;
   }
   double h[9];
+#pragma unroll
   for (int q = 0; q < 9; ++q) h[q] = periodic ? cell[9 * s + q] : 0.0;
   const double ri[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-  const AtomMeta ai = am[i];
-  int64_t cnt = 0;
+  int64_t cnt = 0;   // uniform over the wavefront
   const int64_t base = WRITE ? row_ptr[i] : 0;
-  auto emit = [&](int64_t j, int n0, int n1, int n2) {
-    if (WRITE) {
-      const int64_t e = base + cnt;
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  auto batch = [&](bool hit, int64_t j, int n0, int n1, int n2) {
+    const uint64_t m = __ballot(hit);
+    if (WRITE && hit) {
+      const int64_t e = base + cnt + __popcll(m & lt);
       col[e] = (int32_t)j;
       if (n0 < -127 || n0 > 127 || n1 < -127 || n1 > 127 || n2 < -127 || n2 > 127)
         atomicOr(status, AFM_FLAG_IMAGES);
-      shift[3 * e] = (int8_t)n0; shift[3 * e + 1] = (int8_t)n1; shift[3 * e + 2] = (int8_t)n2;
+      shift[3 * e] = (int8_t)n0;
+      shift[3 * e + 1] = (int8_t)n1;
+      shift[3 * e + 2] = (int8_t)n2;
     }
-    ++cnt;
+    cnt += __popcll(m);
   };
   if (M.mode == 0) {
     const int64_t a0 = seg[s], a1 = seg[s + 1];
-    for (int64_t j = a0; j < a1; ++j) {
-      const double rj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
-      const AtomMeta aj = am[j];
-      const int o0 = ai.m[0] - aj.m[0], o1 = ai.m[1] - aj.m[1], o2 = ai.m[2] - aj.m[2];
-      for (int k0 = -M.R[0]; k0 <= M.R[0]; ++k0)
-        for (int k1 = -M.R[1]; k1 <= M.R[1]; ++k1)
-          for (int k2 = -M.R[2]; k2 <= M.R[2]; ++k2) {
-            const int n0 = periodic ? k0 + o0 : 0, n1 = periodic ? k1 + o1 : 0,
-                      n2 = periodic ? k2 + o2 : 0;
-            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            if (edge_d2(ri, rj, h, n0, n1, n2, periodic, nullptr) < r2) emit(j, n0, n1, n2);
-          }
+    const int d0 = 2 * M.R[0] + 1, d1 = 2 * M.R[1] + 1, d2 = 2 * M.R[2] + 1;
+    const int64_t nimg = (int64_t)d0 * d1 * d2;
+    const int64_t T = (a1 - a0) * nimg;
+    for (int64_t b0 = 0; b0 < T; b0 += 64) {
+      const int64_t idx = b0 + lane;
+      bool hit = false;
+      int64_t j = 0;
+      int n0 = 0, n1 = 0, n2 = 0;
+      if (idx < T) {
+        j = a0 + idx / nimg;
+        const int rem = (int)(idx % nimg);
+        const int k0 = rem / (d1 * d2) - M.R[0], k1 = (rem / d2) % d1 - M.R[1], k2 = rem % d2 - M.R[2];
+        const AtomMeta aj = am[j];
+        n0 = periodic ? k0 + ai.m[0] - aj.m[0] : 0;
+        n1 = periodic ? k1 + ai.m[1] - aj.m[1] : 0;
+        n2 = periodic ? k2 + ai.m[2] - aj.m[2] : 0;
+        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+          const double rj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+          hit = edge_d2(ri, rj, h, n0, n1, n2, periodic, nullptr) < r2;
+        }
+      }
+      batch(hit, j, n0, n1, n2);
     }
   } else {
-    const int lb = ai.bin - M.bin_off;
-    const int b2 = lb % M.nb[2], b1 = (lb / M.nb[2]) % M.nb[1], b0 = lb / (M.nb[2] * M.nb[1]);
-    for (int o0 = -1; o0 <= 1; ++o0)
-      for (int o1 = -1; o1 <= 1; ++o1)
-        for (int o2 = -1; o2 <= 1; ++o2) {
-          int p0 = b0 + o0, p1 = b1 + o1, p2 = b2 + o2;
-          int w0 = p0 < 0 ? -1 : (p0 >= M.nb[0] ? 1 : 0);
-          int w1 = p1 < 0 ? -1 : (p1 >= M.nb[1] ? 1 : 0);
-          int w2 = p2 < 0 ? -1 : (p2 >= M.nb[2] ? 1 : 0);
-          p0 -= w0 * M.nb[0]; p1 -= w1 * M.nb[1]; p2 -= w2 * M.nb[2];
-          const int gb = M.bin_off + (p0 * M.nb[1] + p1) * M.nb[2] + p2;
-          const int st = bin_start[gb], ct = bin_start[gb + 1] - st;
-          for (int q = 0; q < ct; ++q) {
-            const int64_t j = bin_atoms[st + q];
-            const AtomMeta aj = am[j];
-            const int n0 = w0 - aj.m[0] + ai.m[0], n1 = w1 - aj.m[1] + ai.m[1],
-                      n2 = w2 - aj.m[2] + ai.m[2];
-            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double rj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
-            if (edge_d2(ri, rj, h, n0, n1, n2, true, nullptr) < r2) emit(j, n0, n1, n2);
-          }
+    // lane b < 27: surrounding bin b (offsets -1..1 per axis), its atoms,
+    // the wrap of the bin index, and the exclusive prefix of the counts
+    int st = 0, ct = 0, w0 = 0, w1 = 0, w2 = 0;
+    if (lane < 27) {
+      const int lb = ai.bin - M.bin_off;
+      const int b2 = lb % M.nb[2], b1 = (lb / M.nb[2]) % M.nb[1], b0 = lb / (M.nb[2] * M.nb[1]);
+      int p0 = b0 + lane / 9 - 1, p1 = b1 + (lane / 3) % 3 - 1, p2 = b2 + lane % 3 - 1;
+      w0 = p0 < 0 ? -1 : (p0 >= M.nb[0] ? 1 : 0);
+      w1 = p1 < 0 ? -1 : (p1 >= M.nb[1] ? 1 : 0);
+      w2 = p2 < 0 ? -1 : (p2 >= M.nb[2] ? 1 : 0);
+      p0 -= w0 * M.nb[0]; p1 -= w1 * M.nb[1]; p2 -= w2 * M.nb[2];
+      const int gb = M.bin_off + (p0 * M.nb[1] + p1) * M.nb[2] + p2;
+      st = bin_start[gb];
+      ct = bin_start[gb + 1] - st;
+    }
+    int inc = ct;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    const int excl = inc - ct;
+    const int T = __shfl(inc, 26, 64);
+    for (int b0 = 0; b0 < T; b0 += 64) {
+      const int idx = b0 + lane;
+      // bin of candidate idx: the last b with excl_b <= idx
+      int lo = 0, hi = 27;
+#pragma unroll
+      for (int it = 0; it < 5; ++it) {
+        const int mid = (lo + hi) >> 1;
+        if (__shfl(excl, mid, 64) <= idx) lo = mid; else hi = mid;
+      }
+      const int sb = __shfl(st, lo, 64), eb = __shfl(excl, lo, 64);
+      const int x0 = __shfl(w0, lo, 64), x1 = __shfl(w1, lo, 64), x2 = __shfl(w2, lo, 64);
+      bool hit = false;
+      int64_t j = 0;
+      int n0 = 0, n1 = 0, n2 = 0;
+      if (idx < T) {
+        j = bin_atoms[sb + (idx - eb)];
+        const AtomMeta aj = am[j];
+        n0 = x0 - aj.m[0] + ai.m[0];
+        n1 = x1 - aj.m[1] + ai.m[1];
+        n2 = x2 - aj.m[2] + ai.m[2];
+        if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+          const double rj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+          hit = edge_d2(ri, rj, h, n0, n1, n2, true, nullptr) < r2;
         }
+      }
+      batch(hit, j, n0, n1, n2);
+    }
   }
-  if (!WRITE) {
+  if (!WRITE && lane == 0) {
     counts[i] = cnt;
     if (cnt > max_row) atomicOr(status, AFM_FLAG_CAPACITY);
   }
@@ -586,7 +636,7 @@ int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, cons
   hipLaunchKernelGGL(k_bin_fill, dim3(nblk(N, 256)), dim3(256), 0, st, (const AtomMeta*)am, N,
                      (const int32_t*)bstart, bcount, batoms);
   AFM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_rows<false>, dim3(nblk(N + 1, 128)), dim3(128), 0, st, s.pos, s.cell, s.pbc, s.seg,
+  hipLaunchKernelGGL(k_rows<false>, dim3(nblk(N + 1, 4)), dim3(256), 0, st, s.pos, s.cell, s.pbc, s.seg,
                      N, B, r2, (const StructMeta*)meta, (const AtomMeta*)am, (const int32_t*)bstart,
                      (const int32_t*)batoms, counts, (const int64_t*)nullptr,
                      nl.capacity, nl.col, nl.shift, nl.status, (int)ws->max_row);
@@ -596,7 +646,7 @@ int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, cons
   hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, st, (const int64_t*)nl.row_ptr, N, nl.n_edges);
   hipLaunchKernelGGL(k_capacity_flag, dim3(1), dim3(1), 0, st, (const int64_t*)nl.row_ptr, N, nl.capacity,
                      nl.status);
-  hipLaunchKernelGGL(k_rows<true>, dim3(nblk(N, 128)), dim3(128), 0, st, s.pos, s.cell, s.pbc, s.seg, N, B,
+  hipLaunchKernelGGL(k_rows<true>, dim3(nblk(N, 4)), dim3(256), 0, st, s.pos, s.cell, s.pbc, s.seg, N, B,
                      r2, (const StructMeta*)meta, (const AtomMeta*)am, (const int32_t*)bstart,
                      (const int32_t*)batoms, counts, (const int64_t*)nl.row_ptr,
                      nl.capacity, nl.col, nl.shift, nl.status, (int)ws->max_row);

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     float acc[NLM];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) acc[q] = 0.0f;
+#pragma unroll 2
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
@@ -155,6 +156,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
     float Gp[L > 1 ? L - 1 : 1][NLM];
     load_gamma_prev<LMAX, L, C>(a, i, n, Gp);
+#pragma unroll 2
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
