@@ -62,6 +62,35 @@ def test_neighbors_bit_exact(name):
     _check_nl(gpu_nlist(gpu["calc"]), _oracle_nl(s, hp["r_list"] if "r_list" in hp else hp["r_cut"]))
 
 
+@pytest.mark.parametrize("kind", ["cubic_12", "triclinic_binned"])
+def test_neighbors_bit_exact_binned(kind):
+    """Structures large enough for the binned candidate search (at least
+    3 bins per cell direction and 64 atoms): the list must still equal the
+    oracle's bit for bit, canonical order and reverse index included."""
+    import torch
+    import paper_2502_06073_amd as afm
+    if kind == "cubic_12":
+        s, r = synth.cubic_lattice(12, 2.2, 0.25, 4, 95), 5.5
+    else:
+        d = synth.config_d(40)
+        big = max((b for b in range(d.n_struct) if d.pbc[b]), key=lambda b: d.seg[b + 1] - d.seg[b])
+        s, r = d.structure(big), 4.0
+    # the binned search needs >= 3 bins of width >= r along every cell direction
+    h = s.cell[0]
+    vol = abs(np.linalg.det(h))
+    widths = [vol / np.linalg.norm(np.cross(h[(k + 1) % 3], h[(k + 2) % 3])) for k in range(3)]
+    assert min(widths) >= 3 * r and s.n_atoms >= 64, (widths, s.n_atoms)
+    sysd = afm.DeviceSystem.from_synth(s)
+    hp = small_l2(r_cut=r)
+    model = afm.Model(hp, weights_for(hp, 8), precision="fp32")
+    calc = afm.Calculator(model, sysd, r_list=r)
+    calc.build_neighbors()
+    torch.cuda.synchronize()
+    _say(f"[nl binned] {kind} N={s.n_atoms} edges {int(calc.nl.n_edges.item())}")
+    assert calc.status() == 0
+    _check_nl(gpu_nlist(calc), _oracle_nl(s, r))
+
+
 def test_neighbors_unwrapped_and_skin():
     s = synth.cubic_lattice(7, 2.3, 0.25, 4, 94)
     rng = np.random.default_rng(0)
