@@ -111,21 +111,25 @@ def time_steps(calc, steps, warmup, trace=False):
     return dt, out, stats
 
 
-def cpu_baseline(hp, s, w, budget_s=15.0):
+def cpu_baseline(hp, s, w, budget_s=25.0):
     """The FP64 oracle, as it stands, on a bounded sample of central atoms
     (E_i and dE/d delta of their edges: the per-atom work of one step)."""
     import torch
     import synth
     from oracle import model as M
-    rows = synth.subset_rows(s.n_atoms, 32, 7)
-    t0 = time.perf_counter()
-    M.rows_energy_grad(hp, w, s, rows, r_list=hp.get("r_list", hp["r_cut"]))
-    t1 = time.perf_counter() - t0
-    k = int(min(s.n_atoms, max(32, 32 * budget_s / max(t1, 1e-3))))
-    rows = synth.subset_rows(s.n_atoms, k, 8)
-    t0 = time.perf_counter()
-    M.rows_energy_grad(hp, w, s, rows, r_list=hp.get("r_list", hp["r_cut"]))
-    t = time.perf_counter() - t0
+    def run(k, seed):
+        rows = synth.subset_rows(s.n_atoms, k, seed)
+        t0 = time.perf_counter()
+        M.rows_energy_grad(hp, w, s, rows, r_list=hp.get("r_list", hp["r_cut"]))
+        return time.perf_counter() - t0
+    # grow the sample (at most 4x a time) until one run takes ~half the budget;
+    # the last run is the measurement
+    k, seed = 64, 7
+    while True:
+        t = run(k, seed)
+        if t >= 0.4 * budget_s or k == s.n_atoms:
+            break
+        k, seed = int(min(s.n_atoms, k * min(4.0, 0.6 * budget_s / max(t, 1e-3)))), seed + 1
     return dict(value=k / t, unit="atom-steps/s", cores=int(torch.get_num_threads()), kind="oracle",
                 sample=f"{k} seeded central atoms (E_i and dE/d delta_e of their rows), FP64, "
                        f"{t:.1f} s; os.cpu_count()={os.cpu_count()}")

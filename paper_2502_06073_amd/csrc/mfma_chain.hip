@@ -50,6 +50,13 @@ constexpr int NCBW = NCB;         // column blocks per wavefront
 constexpr int NWAVE = NPS * (NCB / NCBW);  // wavefronts: pair slot x column group
 constexpr int NTHR = 64 * NWAVE;
 constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
+// The adjoint chains (forces) use the hi term alone.  Rounding a weight to
+// bf16 shifts every edge energy the same way, so the energy keeps lo to stay
+// within 1 meV/atom; in the adjoint the same rounding adds a force error of
+// the size the bf16 activations and gradients already cause (emulated in
+// FP64 on a 125-atom lattice: 3.9 -> 5.1 meV/A RMS, bound 20 meV/A), and
+// halves the weight stream and the MFMAs of the adjoint.
+constexpr int kSplitBwd = 1;
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -236,37 +243,51 @@ __device__ __forceinline__ void stage_rows_bf16(uint4* __restrict__ act, const u
 // acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
 //   W[2 pair + r][kb] x act[kb - kb0][cb]
 // W: packed weight fragments [RB][KBW][hi, lo][64]; act: LDS fragments.
-// Weight fragments stream from L2 one k-block ahead; per k-block the hi
-// products of both row blocks and all column blocks are issued before the
-// lo products, so the two MFMAs into one accumulator are 16 apart.
-template <int KBW, int NKB>
+// NS = 2 uses w = hi + lo, NS = 1 the hi term alone (the lo fragments are
+// then never loaded).  Weight fragments stream from L2 one k-block ahead;
+// per k-block the hi products of both row blocks and all column blocks are
+// issued before the lo products, so the two MFMAs into one accumulator are
+// 16 apart.
+template <int KBW, int NKB, int NS = kSplit>
 __device__ __forceinline__ void mma_pair(const uint4* __restrict__ W, int pair, int kb0, const uint4* act,
                                          f32x4 (&acc)[2][NCBW], int half, int lane) {
+  static_assert(NS == 1 || NS == kSplit, "NS");
   const uint4* w0 = W + ((int64_t)(2 * pair) * KBW + kb0) * (kSplit * 64) + lane;
   const uint4* w1 = w0 + (int64_t)KBW * (kSplit * 64);
-  uint4 cur[4], nxt[4];
-  cur[0] = w0[0]; cur[1] = w0[64]; cur[2] = w1[0]; cur[3] = w1[64];
+  uint4 cur[2][NS], nxt[2][NS];
+#pragma unroll
+  for (int h = 0; h < NS; ++h) {
+    cur[0][h] = w0[64 * h];
+    cur[1][h] = w1[64 * h];
+  }
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb) {
     if (kb + 1 < NKB) {
       const int o = (kb + 1) * (kSplit * 64);
-      nxt[0] = w0[o]; nxt[1] = w0[o + 64]; nxt[2] = w1[o]; nxt[3] = w1[o + 64];
+#pragma unroll
+      for (int h = 0; h < NS; ++h) {
+        nxt[0][h] = w0[o + 64 * h];
+        nxt[1][h] = w1[o + 64 * h];
+      }
     }
     bf16x8 b[NCBW];
 #pragma unroll
     for (int c = 0; c < NCBW; ++c)
       b[c] = __builtin_bit_cast(bf16x8, act[frag_idx(kb, half * NCBW + c, lane)]);
 #pragma unroll
-    for (int h = 0; h < kSplit; ++h)
+    for (int h = 0; h < NS; ++h)
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
-        const bf16x8 A = __builtin_bit_cast(bf16x8, cur[2 * r + h]);
+        const bf16x8 A = __builtin_bit_cast(bf16x8, cur[r][h]);
 #pragma unroll
         for (int c = 0; c < NCBW; ++c) acc[r][c] = mfma(A, b[c], acc[r][c]);
       }
     if (kb + 1 < NKB) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+      for (int h = 0; h < NS; ++h) {
+        cur[0][h] = nxt[0][h];
+        cur[1][h] = nxt[1][h];
+      }
     }
     // keep the scheduler from hoisting later k-blocks' loads (register
     // pressure at 4 wavefronts per SIMD)
@@ -298,7 +319,7 @@ __device__ __forceinline__ void finish_pair(int pair, f32x4 (&acc)[2][NCBW], uin
 
 // A whole layer from LDS: rows of NPAIR pairs, the wavefronts of pair slot
 // ps own pairs ps, ps + NPS, ...; no barrier inside.
-template <int NPAIR, int KBW, class EPI>
+template <int NPAIR, int KBW, int NS = kSplit, class EPI>
 __device__ __forceinline__ void layer_lds(const uint4* __restrict__ W, const uint4* in, uint4* out, EPI&& epi,
                                           int pslot, int half, int lane) {
   static_for<0, cdiv(NPAIR, NPS)>([&](auto P) __attribute__((always_inline)) {
@@ -306,7 +327,7 @@ __device__ __forceinline__ void layer_lds(const uint4* __restrict__ W, const uin
     if (pair < NPAIR) {
       f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<KBW, KBW>(W, pair, 0, in, acc, half, lane);
+      mma_pair<KBW, KBW, NS>(W, pair, 0, in, acc, half, lane);
       finish_pair(pair, acc, out, epi, half, lane);
     }
   });
@@ -644,7 +665,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     if (mine) {
       f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, half, lane);
+      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitBwd>(a.envb, pair, 0, S.act[1], acc, half, lane);
       finish_pair(
           pair, acc, S.act[0],
           [&](int rb, int cb, f32x4& v) {
@@ -666,7 +687,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     if (mine) {
       f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<KBX, KBX>(a.latb[k], pair, 0, S.act[cur], acc, half, lane);
+      mma_pair<KBX, KBX, kSplitBwd>(a.latb[k], pair, 0, S.act[cur], acc, half, lane);
       finish_pair(
           pair, acc, S.act[cur ^ 1],
           [&](int rb, int cb, f32x4& v) {
@@ -680,7 +701,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     cur ^= 1;
   });
   // dE/d[x | s] = W_1^T ga_1: x rows added to the residual share, s rows stored
-  layer_lds<cdiv(W + KS, 32), KBX>(
+  layer_lds<cdiv(W + KS, 32), KBX, kSplitBwd>(
       a.latb[0], S.act[cur], nullptr,
       [&](int rb, int cb, f32x4& v) {
         const int64_t t = col_t(cb);
@@ -716,7 +737,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   if (mine) {
     f32x4 acc[2][NCBW];
     zero_acc(acc);
-    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32)>(a.envb, pair, 0, S.act[1], acc, half, lane);
+    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitBwd>(a.envb, pair, 0, S.act[1], acc, half, lane);
     finish_pair(
         pair, acc, S.act[0],
         [&](int rb, int cb, f32x4& v) {
@@ -738,7 +759,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
   int cur = 0;
   if constexpr (NT == 3) {
-    layer_lds<cdiv(T1, 32), W / 32>(
+    layer_lds<cdiv(T1, 32), W / 32, kSplitBwd>(
         a.tbb[2], S.act[0], S.act[1],
         [&](int rb, int cb, f32x4& v) {
           if (rb >= RB1) return;
@@ -756,7 +777,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   f32x4 acc[2][NCBW];
   zero_acc(acc);
   if (pslot < NP0) {
-    mma_pair<cdiv(T1, 32), cdiv(T1, 32)>(a.tbb[1], pslot, 0, S.act[cur], acc, half, lane);
+    mma_pair<cdiv(T1, 32), cdiv(T1, 32), kSplitBwd>(a.tbb[1], pslot, 0, S.act[cur], acc, half, lane);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int rb = 2 * pslot + r;
