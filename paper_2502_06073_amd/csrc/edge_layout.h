@@ -32,14 +32,16 @@ struct TPArgs {
   uint16_t* s16;         // s^L as bf16 bits (BF16 path: the MLP rounds s to bf16 anyway)
   float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
   const float* alpha;    // [n_paths][C]
-  // layers before L: V^{L-1} is recomputed per edge from V^0 = omega^1 (x) Y
-  // and these per-atom sums and mixing weights instead of being stored
-  const float* gamma_prev[kMaxTpLayers];   // Gamma^1 .. Gamma^{L-1}
-  const float* alpha_prev[kMaxTpLayers];   // alpha^1 .. alpha^{L-1}
+  // every layer's per-atom sums, mixing weights and scalar-output adjoints
+  // (index l: layer l + 1).  Neither V^{L-1} nor dE/dV^L is stored: the
+  // forward rebuilds V^{L-1} per edge from V^0 = omega^1 (x) Y and the
+  // Gammas of the earlier layers, the adjoint rebuilds dE/dV^L from the
+  // later layers' Gammas and dE/ds.
+  const float* gamma_l[kMaxTpLayers];
+  const float* alpha_l[kMaxTpLayers];
+  const float* gs_l[kMaxTpLayers];
   float inv_sqrt_nbar;
   const float* gs;       // dE/ds^L
-  const float* gvout;    // dE/dV^L (L < NL)
-  float* gvin;           // dE/dV^{L-1} (L > 1)
   float* gomega;         // dE/domega^L [t][lmax+1][C]
   float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
 };

@@ -412,9 +412,10 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   a.geo = ws_ptr<float>(ws, L.geo);
   a.omega = ws_ptr<float>(ws, L.omega[layer - 1]);
   a.omega1 = ws_ptr<float>(ws, L.omega[0]);
-  for (int l = 1; l < layer; ++l) {
-    a.gamma_prev[l - 1] = ws_ptr<float>(ws, L.gamma[l - 1]);
-    a.alpha_prev[l - 1] = m->W.alpha[l - 1];
+  for (int l = 0; l < d.NL; ++l) {
+    a.gamma_l[l] = ws_ptr<float>(ws, L.gamma[l]);
+    a.alpha_l[l] = l + 1 < d.NL ? m->W.alpha[l] : nullptr;
+    a.gs_l[l] = ws_ptr<float>(ws, L.gs[l]);
   }
   if (m->prec == AFM_BF16_MFMA) a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
   else a.s = ws_ptr<float>(ws, L.s[layer - 1]);
@@ -571,18 +572,13 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
           ga = gnext;
         }
         sgemm<false>(st, rr, E, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LoadPlain{ga, d.w},
-                     EpSplit{gx, d.w, ws_ptr<float>(ws, L.gs), ls});
+                     EpSplit{gx, d.w, ws_ptr<float>(ws, L.gs[layer - 1]), ls});
         AFM_LAUNCH_CHECK();
       }
     }
     TraceScope tr(st, "tp_bwd", layer);
     TPArgs ta = tp_args(m, ws, L, rr, layer);
-    ta.gs = ws_ptr<float>(ws, L.gs);
-    float* gva = ws_ptr<float>(ws, L.gv0);
-    float* gvb = ws_ptr<float>(ws, L.gv1);
-    // dE/dV^L lives in the buffer written by layer L+1's adjoint
-    ta.gvout = (layer < d.NL) ? (((d.NL - layer) % 2 == 1) ? gva : gvb) : nullptr;
-    ta.gvin = (layer > 1) ? (((d.NL - layer) % 2 == 0) ? gva : gvb) : nullptr;
+    ta.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
     rc = launch_tp(d.lmax, d.NL, layer, d.c, true, ta, s.N, st);
     if (rc) return rc;
   }

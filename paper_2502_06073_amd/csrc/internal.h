@@ -110,8 +110,7 @@ struct WsLayout {
   int64_t v[kMaxLayers] = {};                // float [CEX][ncomp c] (V^1..V^{NL-1})
   int64_t lat_pre[kMaxLayers][kMaxDepth] = {};  // float [CEX][w] (BF16 path: bf16)
   int64_t gx = 0, gt0 = 0, gt1 = 0;          // float [CEX][max(w, w+n0e c)]
-  int64_t gs = 0;                            // float [CEX][n0e c]
-  int64_t gv0 = 0, gv1 = 0;                  // float [CEX][kMaxComps c]
+  int64_t gs[kMaxLayers] = {};               // float [CEX][n0e c] dE/ds^L per layer
   int64_t gy = 0;                            // float [CEX][16] (GY[9], Gu at [9])
   int64_t gomega = 0;                        // float [CEX][(lmax+1)c]
   int64_t grho = 0;                          // float [CEX][16]

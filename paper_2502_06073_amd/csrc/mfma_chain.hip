@@ -875,7 +875,6 @@ static ChainArgs base_args(const afm_model* m, const afm_workspace* ws, const Ws
   a.gy = ws_ptr<float>(ws, L.gy);
   a.grho = ws_ptr<float>(ws, L.grho);
   a.gx = ws_ptr<float>(ws, L.gx);
-  a.gs = ws_ptr<float>(ws, L.gs);
   a.gomega = ws_ptr<float>(ws, L.gomega);
   return a;
 }
@@ -962,6 +961,7 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   a.seg = seg;
   a.B = B;
   a.ges = grad_e_struct;
+  a.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
   for (int k = 0; k < d.depth; ++k) a.latb[k] = frag_ptr(m, fo->latb[layer - 1][k]);
   if (layer < d.NL) a.envb = frag_ptr(m, fo->envb[layer]);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);

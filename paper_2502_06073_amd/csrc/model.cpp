@@ -282,9 +282,7 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   L.gx = take(E * gwide * 4);
   L.gt0 = take(E * gwide * 4);
   L.gt1 = take(E * gwide * 4);
-  L.gs = take(E * (int64_t)maxn0 * d.c * 4);
-  L.gv0 = take(E * (int64_t)maxcomp * d.c * 4);
-  L.gv1 = take(E * (int64_t)maxcomp * d.c * 4);
+  for (int l = 0; l < d.NL; ++l) L.gs[l] = take(E * (int64_t)P.layer[l].n0e * d.c * 4);
   L.gy = take(E * 64);
   L.gomega = take(E * (d.lmax + 1) * d.c * 4);
   L.grho = take(E * 64);
@@ -463,9 +461,11 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
     // sums, so layers after the first read omega^1 and L - 1 more Gammas
     const double prev = L == 1 ? 0.0 : ENV;
     const double gprev = (L - 1) * NLM * C;
-    const double dV = last ? 0.0 : lp.n_out_comps * C;       // dE/dV^L in (adjoint)
-    const double dVin = L == 1 ? 0.0 : lp.n_in_comps * C;    // dE/dV^{L-1} out (adjoint)
     const double s_out = lp.n0e * C;
+    // the adjoint rebuilds dE/dV^L from dE/ds and Gamma of the later layers
+    double gs_later = 0.0;
+    for (int l = L; l < d.NL; ++l) gs_later += P.layer[l].n0e * C;
+    const double gnext = (d.NL - L) * NLM * C;
     // environment sum (NLM C fma) + nonzero CG products (2 mul + add each);
     // the recomputation of earlier layers is not counted (algorithmic work)
     double nz0 = 0;
@@ -479,7 +479,7 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
     add("tp_fwd", L, 1, tpf, 4 * (ENV + NLM + prev + s_out), 4 * (NLM * C + gprev));
     // adjoint: twice the products (dV and dGamma), the mixing, the environment-sum adjoint
     const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + 2 * NLM * C;
-    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + prev + s_out + dV + dVin + ENV + NLM), 4 * (NLM * C + gprev));
+    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + prev + s_out + gs_later + ENV + NLM), 4 * (NLM * C + gprev + gnext));
     const double lat = (W + lp.n0e * C) * W + (d.depth - 1) * W * W;
     add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),
         4 * (W + s_out + (last ? 1 : W + ENV) + 1) + 2 * d.depth * W, 0);

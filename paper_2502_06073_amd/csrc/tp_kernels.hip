@@ -10,6 +10,10 @@
 //   backward: the adjoints of both lines; dE/dGamma_i is accumulated per
 //             thread over the row's edges (9 registers) and reduced over the
 //             edge slots in LDS.
+// Per-edge tensor features never go to memory: V^{L-1} is rebuilt from
+// V^0 = omega^1 (x) Y through the earlier layers' Gammas, and dE/dV^L from
+// the later layers' dE/ds and Gammas, a few hundred FLOP per channel in
+// place of 2-4 KB per edge written and read back.
 // The sums run over the nonzero CG entries only, unrolled with immediate
 // coefficients from the compile-time tables (cg_ct.h); Gamma_i of the
 // thread's channel stays in registers for the whole row.
@@ -52,15 +56,16 @@ struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
 };
 
-// Gamma^1 .. Gamma^{L-1} of atom i, channel n (registers)
-template <int LMAX, int L, int C>
-__device__ __forceinline__ void load_gamma_prev(const TPArgs& a, int64_t i, int n,
-                                                float (&Gp)[L > 1 ? L - 1 : 1][(LMAX + 1) * (LMAX + 1)]) {
+// Gamma of layers L0 + 1 .. L0 + NG of atom i, channel n (registers)
+template <int LMAX, int L0, int NG, int C, int ND>
+__device__ __forceinline__ void load_gammas(const TPArgs& a, int64_t i, int n,
+                                            float (&Gs)[ND][(LMAX + 1) * (LMAX + 1)]) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  static_assert(NG <= ND, "gamma registers");
 #pragma unroll
-  for (int l = 0; l + 1 < L; ++l)
+  for (int l = 0; l < NG; ++l)
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) Gp[l][q] = a.gamma_prev[l][(i * NLM + q) * C + n];
+    for (int q = 0; q < NLM; ++q) Gs[l][q] = a.gamma_l[L0 + l][(i * NLM + q) * C + n];
 }
 
 template <int LMAX, int NL, int L, int K>
@@ -91,7 +96,7 @@ __device__ __forceinline__ void recompute_V(const TPArgs& a, int64_t t, int n, c
       if constexpr (pt.out_off >= 0) {
         float T[2 * pt.l3 + 1];
         path_fwd<LMAX, NL, K, k>(Vin, Gp[K - 1], T);
-        const float al = a.alpha_prev[K - 1][k * C + n];
+        const float al = a.alpha_l[K - 1][k * C + n];
 #pragma unroll
         for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) V[pt.out_off + m3] += al * T[m3];
       }
@@ -109,6 +114,41 @@ __device__ __forceinline__ void path_fwd(const float* V, const float* G, float* 
   static_for<0, nz.n>([&](auto Q) {
     constexpr int q = decltype(Q)::value;
     T[nz.m3[q]] += nz.c[q] * V[pt.in_off + nz.m1[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+  });
+}
+
+// dE/dV^K (K < NL) of edge t, channel n: the adjoint of layer K + 1's
+// products, dE/dV^K[m1] = sum over paths and nonzeros of
+// C dE/dT^{K+1}[m3] Gamma^{K+1}[m2], where dE/dT^{K+1} = dE/ds^{K+1} on the
+// 0e paths plus alpha^{K+1} dE/dV^{K+1} (rebuilt the same way) on the
+// others.  Gn[j] holds Gamma^{L+1+j} (registers).
+template <int LMAX, int NL, int L, int K, int C, int NG>
+__device__ __forceinline__ void recompute_gV(const TPArgs& a, int64_t t, int n,
+                                             const float (&Gn)[NG][(LMAX + 1) * (LMAX + 1)], float* GV) {
+  constexpr LayerPlan LP = PlanCT<LMAX, NL>::plan.layer[K];  // layer K + 1
+  float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
+  if constexpr (K + 1 < NL) recompute_gV<LMAX, NL, L, K + 1, C, NG>(a, t, n, Gn, GVO);
+#pragma unroll
+  for (int q = 0; q < LP.n_in_comps; ++q) GV[q] = 0.0f;
+  const float* G = Gn[K - L];
+  static_for<0, LP.n_paths>([&](auto P) {
+    constexpr int k = decltype(P)::value;
+    constexpr PathT pt = LP.p[k];
+    constexpr int d3 = 2 * pt.l3 + 1;
+    constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+    float GT[d3];
+#pragma unroll
+    for (int m3 = 0; m3 < d3; ++m3) GT[m3] = 0.0f;
+    if constexpr (pt.s_idx >= 0) GT[0] = a.gs_l[K][(t * LP.n0e + pt.s_idx) * C + n];
+    if constexpr (pt.out_off >= 0) {
+      const float al = a.alpha_l[K][k * C + n];
+#pragma unroll
+      for (int m3 = 0; m3 < d3; ++m3) GT[m3] += al * GVO[pt.out_off + m3];
+    }
+    static_for<0, nz.n>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      GV[pt.in_off + nz.m1[q]] += nz.c[q] * GT[nz.m3[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+    });
   });
 }
 
@@ -155,7 +195,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
 #pragma unroll
     for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
     float Gp[L > 1 ? L - 1 : 1][NLM];
-    load_gamma_prev<LMAX, L, C>(a, i, n, Gp);
+    load_gammas<LMAX, 0, L - 1, C>(a, i, n, Gp);
 #pragma unroll 2
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
@@ -197,20 +237,17 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       G[q] = a.gamma[(i * NLM + q) * C + n];
       GG[q] = 0.0f;
     }
-    float Gp[L > 1 ? L - 1 : 1][NLM];
-    load_gamma_prev<LMAX, L, C>(a, i, n, Gp);
+    float Gp[L > 1 ? L - 1 : 1][NLM], Gn[L < NL ? NL - L : 1][NLM];
+    load_gammas<LMAX, 0, L - 1, C>(a, i, n, Gp);
+    load_gammas<LMAX, L, NL - L, C>(a, i, n, Gn);
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI], GV[NCI];
       recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
-      // dE/dV^L of this edge and channel, one storage-type branch per edge
+      // dE/dV^L of this edge and channel
       float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
-      if constexpr (LP.n_out_comps > 0) {
-        const int64_t g0 = t * LP.n_out_comps * C + n;
-#pragma unroll
-        for (int q = 0; q < LP.n_out_comps; ++q) GVO[q] = a.gvout[g0 + q * C];
-      }
+      if constexpr (L < NL) recompute_gV<LMAX, NL, L, L, C, NL - L>(a, t, n, Gn, GVO);
 #pragma unroll
       for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
       static_for<0, LP.n_paths>([&](auto K) {
@@ -234,10 +271,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
           GG[pt.l2 * pt.l2 + nz.m2[q]] += cg * V[pt.in_off + nz.m1[q]];
         });
       });
-      if constexpr (L > 1) {
-#pragma unroll
-        for (int q = 0; q < NCI; ++q) a.gvin[(t * NCI + q) * C + n] = GV[q];
-      } else {
+      if constexpr (L == 1) {
         // V^0 = omega^1 (x) Y
         float gyc[16];
 #pragma unroll
