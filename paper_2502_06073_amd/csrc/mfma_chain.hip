@@ -57,6 +57,11 @@ constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
 // FP64 on a 125-atom lattice: 3.9 -> 5.1 meV/A RMS, bound 20 meV/A), and
 // halves the weight stream and the MFMAs of the adjoint.
 constexpr int kSplitBwd = 1;
+// The environment embeddings omega = W_env x use the hi term alone in the
+// forward as well: omega enters the energy only through the per-atom sums
+// and tensor products, and rounding W_env to bf16 moved the emulated
+// energy by 0.04 meV/atom (the two-body and latent weights, 2.2 and 1.8).
+constexpr int kSplitEnv = 1;
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -505,7 +510,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     cur = 0;
   }
   // omega^1 = W_env^1 x^0
-  layer_lds<cdiv(ENV, 32), W / 32>(
+  layer_lds<cdiv(ENV, 32), W / 32, kSplitEnv>(
       a.envf, S.act[cur], nullptr,
       [&](int rb, int cb, f32x4& v) {
         const int64_t t = col_t(cb);
@@ -581,7 +586,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     cur ^= 1;
   });
   if constexpr (!LAST) {
-    layer_lds<cdiv(ENV, 32), KBX>(
+    layer_lds<cdiv(ENV, 32), KBX, kSplitEnv>(
         a.envf, S.act[cur], nullptr,
         [&](int rb, int cb, f32x4& v) {
           const int64_t t = col_t(cb);
