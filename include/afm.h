@@ -292,8 +292,9 @@ int afm_trace_read(afm_trace_stat* out /*host*/, int32_t max, int32_t* n /*host*
  * the kernels issue: flops = 2 x multiply-adds of the stage's products (for
  * the MLP stages once per weight, although the BF16 path issues every
  * product as a hi + lo pair of MFMAs); bytes = compulsory HBM traffic, each
- * input read once and each output written once (float32 features, bf16
- * stored pre-activations, per-atom tensors once per central atom).
+ * input read once and each output written once, in the BF16 path's storage
+ * types (bf16 pre-activations, omega, s and dE/domega; float32 x, dE/dx,
+ * dE/ds and geometry; per-atom tensors once per central atom).
  * kind: 0 = dense contraction (MFMA in the BF16 path), 1 = vector ALU /
  * memory stage.  out: host, `max` entries; *n receives the stage count.  */
 typedef struct {

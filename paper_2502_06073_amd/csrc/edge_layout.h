@@ -26,10 +26,11 @@ constexpr int kMaxTpLayers = 4;
 struct TPArgs {
   RowRange rr;
   const float* geo;
-  const float* omega;    // omega^L  [t][lmax+1][C]
-  const float* omega1;   // omega^1  (features V^0 = omega^1 (x) Y when L == 1)
-  float* s;              // s^L      [t][n0e][C]
-  uint16_t* s16;         // s^L as bf16 bits (BF16 path: the MLP rounds s to bf16 anyway)
+  // omega, s and dE/domega are float in the FP32 path and bf16 bits in the
+  // BF16 path (its MLP kernels round them to bf16 anyway)
+  const void* omega;     // omega^L  [t][lmax+1][C]
+  const void* omega1;    // omega^1  (features V^0 = omega^1 (x) Y when L == 1)
+  void* s;               // s^L      [t][n0e][C]
   float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
   const float* alpha;    // [n_paths][C]
   // every layer's per-atom sums, mixing weights and scalar-output adjoints
@@ -42,10 +43,11 @@ struct TPArgs {
   const float* gs_l[kMaxTpLayers];
   float inv_sqrt_nbar;
   const float* gs;       // dE/ds^L
-  float* gomega;         // dE/domega^L [t][lmax+1][C]
+  void* gomega;          // dE/domega^L [t][lmax+1][C]
   float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
 };
 
-int launch_tp(int lmax, int NL, int L, int C, bool bwd, const TPArgs& a, int64_t n_atoms_max, hipStream_t st);
+int launch_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const TPArgs& a, int64_t n_atoms_max,
+              hipStream_t st);
 
 }  // namespace afm

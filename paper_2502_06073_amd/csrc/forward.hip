@@ -417,8 +417,7 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
     a.alpha_l[l] = l + 1 < d.NL ? m->W.alpha[l] : nullptr;
     a.gs_l[l] = ws_ptr<float>(ws, L.gs[l]);
   }
-  if (m->prec == AFM_BF16_MFMA) a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
-  else a.s = ws_ptr<float>(ws, L.s[layer - 1]);
+  a.s = ws_ptr<float>(ws, L.s[layer - 1]);
   a.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
   a.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;
   a.inv_sqrt_nbar = (float)(1.0 / sqrt(d.nbar));
@@ -481,7 +480,7 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
     {
       TraceScope tr(st, "tp_fwd", layer);
       TPArgs ta = tp_args(m, ws, L, rr, layer);
-      int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, ta, s.N, st);
+      int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, m->prec == AFM_BF16_MFMA, ta, s.N, st);
       if (rc) return rc;
     }
     TraceScope tr(st, "latent_fwd", layer);
@@ -579,7 +578,7 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
     TraceScope tr(st, "tp_bwd", layer);
     TPArgs ta = tp_args(m, ws, L, rr, layer);
     ta.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
-    rc = launch_tp(d.lmax, d.NL, layer, d.c, true, ta, s.N, st);
+    rc = launch_tp(d.lmax, d.NL, layer, d.c, true, m->prec == AFM_BF16_MFMA, ta, s.N, st);
     if (rc) return rc;
   }
   // two-body: dE/dx^0 += dE/domega^1 W_env^1, then the MLP adjoint

@@ -245,6 +245,12 @@ __device__ __forceinline__ void stage_rows_bf16(uint4* __restrict__ act, const u
   }
 }
 
+// four consecutive bf16 values (8-byte store)
+__device__ __forceinline__ void st_bf16x4(uint16_t* p, f32x4 v) {
+  const uint4 w = __builtin_bit_cast(uint4, pack8(v, v));
+  *reinterpret_cast<uint2*>(p) = uint2{w.x, w.y};
+}
+
 // acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
 //   W[2 pair + r][kb] x act[kb - kb0][cb]
 // W: packed weight fragments [RB][KBW][hi, lo][64]; act: LDS fragments.
@@ -373,12 +379,12 @@ struct ChainArgs {
   const float* xprev;     // x^{L-1}
   float* xnew;            // x^L (or x^0)
   const uint16_t* s16;   // s^L (bf16 bits)
-  float* omega;           // omega^{L+1} (or omega^1)
+  uint16_t* omega;        // omega^{L+1} (or omega^1), bf16 bits
   float* eps;             // edge energies (global edge index)
   uint2* pre[kMaxDepth];  // bf16 pre-activations per MLP layer
   float* gx;              // dE/dx (in: of x^L / x^0; out: of x^{L-1})
   float* gs;              // dE/ds^L
-  const float* gomega;    // dE/domega^{L+1} (or of omega^1)
+  const uint16_t* gomega; // dE/domega^{L+1} (or of omega^1), bf16 bits
   float* gy;              // [t][16], dE/du at [9]
   float* grho;            // [t][16]
 };
@@ -514,7 +520,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
       a.envf, S.act[cur], nullptr,
       [&](int rb, int cb, f32x4& v) {
         const int64_t t = col_t(cb);
-        if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
+        if (rb < ENV / 16 && t < M) st_bf16x4(a.omega + t * ENV + 16 * rb + 4 * g, v);
       },
       pslot, half, lane);
 }
@@ -590,7 +596,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
         a.envf, S.act[cur], nullptr,
         [&](int rb, int cb, f32x4& v) {
           const int64_t t = col_t(cb);
-          if (rb < ENV / 16 && t < M) st4(a.omega + t * ENV + 16 * rb + 4 * g, v);
+          if (rb < ENV / 16 && t < M) st_bf16x4(a.omega + t * ENV + 16 * rb + 4 * g, v);
         },
         pslot, half, lane);
   } else {
@@ -665,7 +671,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     }
   } else {
     // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
-    stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
+    stage_rows_bf16<ENV>(S.act[1], a.gomega, tile, M, tid);
     __syncthreads();
     if (mine) {
       f32x4 acc[2][NCBW];
@@ -737,7 +743,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
   // head: x^0 = u silu(a_last); dE/dx^0 = stored + W_env^1T dE/domega^1
-  stage_rows<ENV>(S.act[1], a.gomega, tile, M, tid);
+  stage_rows_bf16<ENV>(S.act[1], a.gomega, tile, M, tid);
   __syncthreads();
   if (mine) {
     f32x4 acc[2][NCBW];
@@ -880,7 +886,7 @@ static ChainArgs base_args(const afm_model* m, const afm_workspace* ws, const Ws
   a.gy = ws_ptr<float>(ws, L.gy);
   a.grho = ws_ptr<float>(ws, L.grho);
   a.gx = ws_ptr<float>(ws, L.gx);
-  a.gomega = ws_ptr<float>(ws, L.gomega);
+  a.gomega = ws_ptr<uint16_t>(ws, L.gomega);
   return a;
 }
 
@@ -898,7 +904,7 @@ int mfma_twobody_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   a.col = col;
   a.envf = frag_ptr(m, fo->envf[0]);
   a.xnew = ws_ptr<float>(ws, L.x[0]);
-  a.omega = ws_ptr<float>(ws, L.omega[0]);
+  a.omega = ws_ptr<uint16_t>(ws, L.omega[0]);
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                             \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                  \
@@ -939,7 +945,7 @@ int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   a.xprev = ws_ptr<float>(ws, L.x[layer - 1]);
   a.xnew = layer < d.NL ? ws_ptr<float>(ws, L.x[layer]) : nullptr;
   a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
-  a.omega = layer < d.NL ? ws_ptr<float>(ws, L.omega[layer]) : nullptr;
+  a.omega = layer < d.NL ? ws_ptr<uint16_t>(ws, L.omega[layer]) : nullptr;
   a.eps = ws_ptr<float>(ws, L.eps);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
   const bool last = layer == d.NL;

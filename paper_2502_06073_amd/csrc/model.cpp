@@ -443,9 +443,10 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
   };
   // col + shift + two positions in, geometry record + row index out
   add("geometry", 0, 1, 60.0, 4 + 3 + 48 + 4.0 * (GEO_Y + 9) + 4, 0);
-  // x^0, omega^1 and the stored pre-activations out
-  add("twobody_fwd", 0, 0, 2.0 * (tbm + W * ENV), 8 + 4 * (W + ENV) + 2 * tbpre, 0);
-  add("twobody_bwd", 0, 0, 2.0 * (tbm + W * ENV), 4 * (ENV + W) + 2 * tbpre + 4 * (d.nb + 1), 0);
+  // species pair in; x^0, omega^1 (bf16) and the stored pre-activations out
+  add("twobody_fwd", 0, 0, 2.0 * (tbm + W * ENV), 8 + 4 * W + 2 * ENV + 2 * tbpre, 0);
+  // dE/domega^1 (bf16), dE/dx^0, pre-activations in; dE/drho, dE/du out
+  add("twobody_bwd", 0, 0, 2.0 * (tbm + W * ENV), 2 * ENV + 4 * W + 2 * tbpre + 4 * (d.nb + 1), 0);
   for (int L = 1; L <= d.NL; ++L) {
     const LayerPlan& lp = P.layer[L - 1];
     const bool last = L == d.NL;
@@ -476,15 +477,21 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
       for (int q = 0; q < (2 * t.l1 + 1) * (2 * t.l2 + 1) * (2 * t.l3 + 1); ++q) nz0 += std::fabs(buf[q]) > 1e-12;
     }
     const double tpf = 2 * NLM * C + 3 * (last ? nz0 : nz) * C + (last ? 0 : 2 * outc * C) + NLM * C;
-    add("tp_fwd", L, 1, tpf, 4 * (ENV + NLM + prev + s_out), 4 * (NLM * C + gprev));
+    // omega^L, omega^1 (bf16), Y in; s^L (bf16) out
+    add("tp_fwd", L, 1, tpf, 2 * ENV + 4 * NLM + 2 * prev + 2 * s_out, 4 * (NLM * C + gprev));
     // adjoint: twice the products (dV and dGamma), the mixing, the environment-sum adjoint
     const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + 2 * NLM * C;
-    add("tp_bwd", L, 1, tpb, 4 * (ENV + NLM + prev + s_out + gs_later + ENV + NLM), 4 * (NLM * C + gprev + gnext));
+    // omega^L, omega^1, Y, dE/ds of this and the later layers in; dE/domega^L
+    // (bf16) and dE/dY out
+    add("tp_bwd", L, 1, tpb, 2 * ENV + 4 * NLM + 2 * prev + 4 * (s_out + gs_later) + 2 * ENV + 4 * NLM,
+        4 * (NLM * C + gprev + gnext));
     const double lat = (W + lp.n0e * C) * W + (d.depth - 1) * W * W;
+    // x^{L-1}, s^L (bf16), u in; x^L + omega^{L+1} (bf16) or eps out; pre-activations out
     add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),
-        4 * (W + s_out + (last ? 1 : W + ENV) + 1) + 2 * d.depth * W, 0);
+        4 * W + 2 * s_out + 4 + (last ? 4 : 4 * W + 2 * ENV) + 2 * d.depth * W, 0);
+    // dE/domega^{L+1} (bf16), dE/dx^L, pre-activations in; dE/dx^{L-1}, dE/ds^L, dE/du out
     add("latent_bwd", L, 0, 2.0 * (lat + (last ? 0 : W * ENV)),
-        4 * ((last ? 0 : ENV) + W + W + s_out + 1) + 2 * d.depth * W + 4, 0);
+        (last ? 0 : 2 * ENV) + 4 * W + 2 * d.depth * W + 4 * W + 4 * s_out + 4, 0);
   }
   // rho and u adjoints in, dE/d delta out
   add("geometry_bwd", 0, 1, 40.0 + 4.0 * d.nb, 4.0 * (GEO_Y + 9) + 4 * (16 + 16) + 12, 0);

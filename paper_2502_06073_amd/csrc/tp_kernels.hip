@@ -36,6 +36,17 @@ int upload_cg_table(const float* host_table) {
 
 
 __device__ __forceinline__ uint16_t to_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+// element i of a float (B16 false) or bf16 (B16 true) array
+template <bool B16>
+__device__ __forceinline__ float ld_w(const void* p, int64_t i) {
+  if constexpr (B16) return __builtin_bit_cast(float, (uint32_t)static_cast<const uint16_t*>(p)[i] << 16);
+  else return static_cast<const float*>(p)[i];
+}
+template <bool B16>
+__device__ __forceinline__ void st_w(void* p, int64_t i, float v) {
+  if constexpr (B16) static_cast<uint16_t*>(p)[i] = to_bf16_bits(v);
+  else static_cast<float*>(p)[i] = v;
+}
 // dst[q] += sum over the C channels (lanes n of one group) of v[q], q < NV
 template <int C, int NV>
 __device__ __forceinline__ void add_channel_sums(float (&v)[16], float* dst, int n) {
@@ -74,20 +85,20 @@ __device__ __forceinline__ void path_fwd(const float* V, const float* G, float* 
 // Output features of layer K (V^K, the input of layer K + 1) for edge t,
 // channel n, recomputed from V^0 = omega^1 (x) Y through layers 1..K with
 // Gamma^l = Gp[l - 1] and the mixing weights alpha^l.
-template <int LMAX, int NL, int K, int C, int NG>
+template <int LMAX, int NL, int K, int C, bool B16, int NG>
 __device__ __forceinline__ void recompute_V(const TPArgs& a, int64_t t, int n, const float* Y,
                                             const float (&Gp)[NG][(LMAX + 1) * (LMAX + 1)], float* V) {
   if constexpr (K == 0) {
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
-      const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+      const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * C + n);
 #pragma unroll
       for (int m = 0; m < 2 * l + 1; ++m) V[l * l + m] = w * Y[l * l + m];
     }
   } else {
     constexpr LayerPlan LP = PlanCT<LMAX, NL>::plan.layer[K - 1];
     float Vin[LP.n_in_comps];
-    recompute_V<LMAX, NL, K - 1, C, NG>(a, t, n, Y, Gp, Vin);
+    recompute_V<LMAX, NL, K - 1, C, B16, NG>(a, t, n, Y, Gp, Vin);
 #pragma unroll
     for (int q = 0; q < LP.n_out_comps; ++q) V[q] = 0.0f;
     static_for<0, LP.n_paths>([&](auto P) {
@@ -152,8 +163,11 @@ __device__ __forceinline__ void recompute_gV(const TPArgs& a, int64_t t, int n,
   });
 }
 
-template <int LMAX, int NL, int L, int C>
-__global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
+// Layers up to 2 fit 5 wavefronts per SIMD; the deeper rebuild of V^{L-1}
+// needs 4 and an edge loop that is not unrolled.
+template <int LMAX, int NL, int L, int C, bool B16>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L >= 3 ? 4 : 5))) k_tp_fwd(TPArgs a) {
+  constexpr int UNR = L >= 3 ? 1 : 2;
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NS = 256 / C;
@@ -168,13 +182,13 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     float acc[NLM];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) acc[q] = 0.0f;
-#pragma unroll 2
+#pragma unroll UNR
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) acc[l * l + m] += w * Y[l * l + m];
       }
@@ -196,12 +210,12 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
     float Gp[L > 1 ? L - 1 : 1][NLM];
     load_gammas<LMAX, 0, L - 1, C>(a, i, n, Gp);
-#pragma unroll 2
+#pragma unroll UNR
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI];
-      recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
+      recompute_V<LMAX, NL, L - 1, C, B16>(a, t, n, Y, Gp, V);
       // only the scalar (0e) paths leave the kernel; V^L is recomputed by
       // the layers that read it
       static_for<0, LP.n_paths>([&](auto K) {
@@ -211,7 +225,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
           float T[2 * pt.l3 + 1];
           path_fwd<LMAX, NL, L, k>(V, G, T);
           const int64_t si = (t * LP.n0e + pt.s_idx) * C + n;
-          if (a.s16) a.s16[si] = to_bf16_bits(T[0]); else a.s[si] = T[0];
+          st_w<B16>(a.s, si, T[0]);
         }
       });
     }
@@ -219,7 +233,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
   }
 }
 
-template <int LMAX, int NL, int L, int C>
+template <int LMAX, int NL, int L, int C, bool B16>
 __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
@@ -244,7 +258,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       float V[NCI], GV[NCI];
-      recompute_V<LMAX, NL, L - 1, C>(a, t, n, Y, Gp, V);
+      recompute_V<LMAX, NL, L - 1, C, B16>(a, t, n, Y, Gp, V);
       // dE/dV^L of this edge and channel
       float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
       if constexpr (L < NL) recompute_gV<LMAX, NL, L, L, C, NL - L>(a, t, n, Gn, GVO);
@@ -278,14 +292,14 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
         for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
-          const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+          const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * C + n);
           float go = 0.0f;
 #pragma unroll
           for (int m = 0; m < 2 * l + 1; ++m) {
             go += GV[l * l + m] * Y[l * l + m];
             gyc[l * l + m] = GV[l * l + m] * w;
           }
-          a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
+          st_w<B16>(a.gomega, (t * (LMAX + 1) + l) * C + n, go);
         }
         add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
       }
@@ -309,7 +323,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
         float go = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
@@ -317,8 +331,9 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
           go += gg * Y[l * l + m];
           gyc[l * l + m] = gg * w;
         }
-        float* dst = a.gomega + (t * (LMAX + 1) + l) * C + n;
-        if constexpr (L == 1) *dst += go; else *dst = go;
+        const int64_t gi = (t * (LMAX + 1) + l) * C + n;
+        if constexpr (L == 1) go += ld_w<B16>(a.gomega, gi);
+        st_w<B16>(a.gomega, gi, go);
       }
       add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
     }
@@ -328,43 +343,48 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
 
 typedef void (*tp_kernel_t)(TPArgs);
 
-template <int LMAX, int NL, int C>
+template <int LMAX, int NL, int C, bool B16>
 static tp_kernel_t pick(int L, bool bwd) {
-  if (L == 1) return bwd ? k_tp_bwd<LMAX, NL, 1, C> : k_tp_fwd<LMAX, NL, 1, C>;
-  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp_bwd<LMAX, NL, 2, C> : k_tp_fwd<LMAX, NL, 2, C>;
-  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp_bwd<LMAX, NL, 3, C> : k_tp_fwd<LMAX, NL, 3, C>;
+  if (L == 1) return bwd ? k_tp_bwd<LMAX, NL, 1, C, B16> : k_tp_fwd<LMAX, NL, 1, C, B16>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp_bwd<LMAX, NL, 2, C, B16> : k_tp_fwd<LMAX, NL, 2, C, B16>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp_bwd<LMAX, NL, 3, C, B16> : k_tp_fwd<LMAX, NL, 3, C, B16>;
   return nullptr;
 }
 
-template <int LMAX, int C>
+template <int LMAX, int C, bool B16>
 static tp_kernel_t pick_nl(int NL, int L, bool bwd) {
   switch (NL) {
-    case 1: return pick<LMAX, 1, C>(L, bwd);
-    case 2: return pick<LMAX, 2, C>(L, bwd);
-    case 3: return pick<LMAX, 3, C>(L, bwd);
+    case 1: return pick<LMAX, 1, C, B16>(L, bwd);
+    case 2: return pick<LMAX, 2, C, B16>(L, bwd);
+    case 3: return pick<LMAX, 3, C, B16>(L, bwd);
   }
   return nullptr;
 }
 
-template <int LMAX>
+template <int LMAX, bool B16>
 static tp_kernel_t pick_c(int C, int NL, int L, bool bwd) {
   switch (C) {
-    case 8: return pick_nl<LMAX, 8>(NL, L, bwd);
-    case 16: return pick_nl<LMAX, 16>(NL, L, bwd);
-    case 32: return pick_nl<LMAX, 32>(NL, L, bwd);
-    case 64: return pick_nl<LMAX, 64>(NL, L, bwd);
+    case 8: return pick_nl<LMAX, 8, B16>(NL, L, bwd);
+    case 16: return pick_nl<LMAX, 16, B16>(NL, L, bwd);
+    case 32: return pick_nl<LMAX, 32, B16>(NL, L, bwd);
+    case 64: return pick_nl<LMAX, 64, B16>(NL, L, bwd);
   }
   return nullptr;
 }
 
-int launch_tp(int lmax, int NL, int L, int C, bool bwd, const TPArgs& a, int64_t n_atoms_max,
-              hipStream_t st) {
-  tp_kernel_t k = nullptr;
+template <bool B16>
+static tp_kernel_t pick_l(int lmax, int C, int NL, int L, bool bwd) {
   switch (lmax) {
-    case 0: k = pick_c<0>(C, NL, L, bwd); break;
-    case 1: k = pick_c<1>(C, NL, L, bwd); break;
-    case 2: k = pick_c<2>(C, NL, L, bwd); break;
+    case 0: return pick_c<0, B16>(C, NL, L, bwd);
+    case 1: return pick_c<1, B16>(C, NL, L, bwd);
+    case 2: return pick_c<2, B16>(C, NL, L, bwd);
   }
+  return nullptr;
+}
+
+int launch_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const TPArgs& a, int64_t n_atoms_max,
+              hipStream_t st) {
+  tp_kernel_t k = bf16 ? pick_l<true>(lmax, C, NL, L, bwd) : pick_l<false>(lmax, C, NL, L, bwd);
   if (!k) { set_error("tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
   const unsigned grid = grid_for(n_atoms_max, 1, 65536);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, a);
