@@ -251,7 +251,23 @@ int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
  * skin/2 since the last rebuild sets AFM_FLAG_SKIN.  With use_graph != 0 and
  * a non-null stream, the n-step sequence is captured into a hipGraph on the
  * first call for a given phase (step % rebuild_every) and replayed after
- * that (the first call instantiates the graph: host-side setup). */
+ * that (the first call instantiates the graph: host-side setup).
+ *
+ * Canonical ensemble (the paper's NVT runs at 300 K, Results): with
+ * t_target_K > 0 a single Nose-Hoover thermostat couples to all atoms, with
+ * mass Q = g kB T tau_fs^2 (g = n_dof, or 3 n_atoms when n_dof <= 0),
+ * integrated by the symmetric Trotter splitting (thermostat half step,
+ * velocity Verlet step, thermostat half step; a half step advances xi by
+ * dt/4 with G = (2 KE - g kB T)/Q, scales the velocities by
+ * exp(-xi dt/2), advances eta by xi dt/2 and xi by dt/4 again).  The
+ * thermostat state lives in `nh` (device, caller-owned, 4 doubles: xi
+ * (fs^-1), eta, and two scratch words; zeros for a fresh start) so that
+ * captured graphs carry it from replay to replay.  If thermostat_log is
+ * non-null, each step writes Q xi^2/2 + g kB T eta (eV) to thermostat_log[t]
+ * (KE + PE + this is conserved).  The energy_log KE is taken after the
+ * thermostat scaling.  t_target_K > 0 needs tau_fs > 0 and nh != NULL
+ * (else AFM_E_INVALID); t_target_K <= 0 is NVE and ignores the other
+ * fields.  Changing t_target_K or tau_fs captures a new graph. */
 typedef struct {
   double* pos;                   /* [n_atoms, 3] device, updated */
   double* vel;                   /* [n_atoms, 3] device, updated */
@@ -265,6 +281,11 @@ typedef struct {
   double* energy_log;            /* [n_steps, 2] device */
   double* e_atom;                /* [n_atoms] device scratch */
   double* e_struct;              /* [n_struct] device scratch */
+  double t_target_K;             /* NVT target temperature; <= 0: NVE */
+  double tau_fs;                 /* NVT thermostat period */
+  int64_t n_dof;                 /* NVT degrees of freedom; <= 0: 3 n_atoms */
+  double* nh;                    /* [4] device: xi, eta, scratch (NVT) */
+  double* thermostat_log;        /* [n_steps] device or NULL (NVT) */
 } afm_md_state;
 
 int afm_md_step(const afm_model* model, const afm_system* sys, afm_nlist* nl,

@@ -383,13 +383,16 @@ def energy_and_forces(calc: Calculator, pos: torch.Tensor) -> torch.Tensor:
 
 
 class MD:
-    """NVE velocity-Verlet driver over afm_md_step.  Positions are updated in
-    place in calc.sysd.pos; calc must have been built with r_list = r_cut +
-    skin.  With use_graph the steps run on a private stream and are replayed
-    from a captured hipGraph after the first call of each phase."""
+    """Velocity-Verlet driver over afm_md_step: NVE, or NVT with a Nose-Hoover
+    thermostat when t_target_K > 0 (period tau_fs, n_dof degrees of freedom,
+    3 N by default).  Positions are updated in place in calc.sysd.pos; calc
+    must have been built with r_list = r_cut + skin.  With use_graph the steps
+    run on a private stream and are replayed from a captured hipGraph after
+    the first call of each phase."""
 
     def __init__(self, calc: Calculator, masses_by_species, v0, dt_fs: float = 0.5, skin: float = 0.5,
-                 rebuild_every: int = 10, use_graph: bool = False):
+                 rebuild_every: int = 10, use_graph: bool = False, t_target_K: float = 0.0,
+                 tau_fs: float = 100.0, n_dof: int = 0, xi0: float = 0.0, eta0: float = 0.0):
         dev = calc.model.device
         self.calc = calc
         self.stream = torch.cuda.Stream(dev) if use_graph else None
@@ -413,17 +416,33 @@ class MD:
         st.step = 0
         st.e_atom = _ptr(self.e_atom)
         st.e_struct = _ptr(self.e_struct)
+        # thermostat state (xi, eta, two scratch words), carried across calls
+        self.nh = torch.tensor([xi0, eta0, 1.0, 0.0], dtype=torch.float64, device=dev)
+        st.t_target_K = float(t_target_K)
+        st.tau_fs = float(tau_fs)
+        st.n_dof = int(n_dof)
+        st.nh = _ptr(self.nh)
+        st.thermostat_log = None
         self.state = st
         self._logs = {}
+        self._tlogs = {}
+        self.thermostat_log = None
 
     def run(self, n_steps: int) -> torch.Tensor:
-        """Advance n_steps; returns the [n_steps, 2] (kinetic, potential) log."""
+        """Advance n_steps; returns the [n_steps, 2] (kinetic, potential) log
+        (NVT: the thermostat energies of the steps go to self.thermostat_log)."""
         dev = self.calc.model.device
         log = self._logs.get(n_steps)
         if log is None:
             log = torch.zeros(n_steps, 2, dtype=torch.float64, device=dev)
             self._logs[n_steps] = log
         self.state.energy_log = _ptr(log)
+        if self.state.t_target_K > 0:
+            tlog = self._tlogs.get(n_steps)
+            if tlog is None:
+                tlog = torch.zeros(n_steps, dtype=torch.float64, device=dev)
+                self._tlogs[n_steps] = tlog
+            self.state.thermostat_log = _ptr(tlog)
         if self.stream is not None:
             self.stream.wait_stream(torch.cuda.current_stream(dev))
             with torch.cuda.stream(self.stream):
@@ -436,4 +455,7 @@ class MD:
                 check("afm_md_step", load().afm_md_step(
                     self.calc.model.handle, C.byref(self.calc.sysd.struct()), C.byref(self.calc.nl.struct()),
                     C.byref(self.state), n_steps, C.byref(self.calc.ws.ws), _stream_ptr(dev)))
+        if self.state.t_target_K > 0:
+            # thermostat energy Q xi^2/2 + g kB T eta per step (eV)
+            self.thermostat_log = self._tlogs[n_steps].clone()
         return log.clone()

@@ -61,7 +61,9 @@ class MdState(C.Structure):
                 ("mass_by_species", C.c_void_p), ("dt_fs", C.c_double), ("skin", C.c_double),
                 ("rebuild_every", C.c_int32), ("use_graph", C.c_int32), ("step", C.c_int64),
                 ("energy_log", C.c_void_p),
-                ("e_atom", C.c_void_p), ("e_struct", C.c_void_p)]
+                ("e_atom", C.c_void_p), ("e_struct", C.c_void_p),
+                ("t_target_K", C.c_double), ("tau_fs", C.c_double), ("n_dof", C.c_int64),
+                ("nh", C.c_void_p), ("thermostat_log", C.c_void_p)]
 
 
 EXPORTS = {

@@ -1,4 +1,5 @@
 // C ABI entry points: argument checks and the chunk schedule.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -155,6 +156,10 @@ int afm_md_step(const afm_model* m, const afm_system* sys, afm_nlist* nl, afm_md
   }
   if (n_steps < 0 || !(state->dt_fs > 0) || !(state->skin >= 0) || state->rebuild_every < 0 || state->step < 0) {
     set_error("bad MD parameters");
+    return AFM_E_INVALID;
+  }
+  if (state->t_target_K > 0 && (!(state->tau_fs > 0) || !std::isfinite(state->t_target_K) || !state->nh)) {
+    set_error("NVT needs tau_fs > 0, a finite target temperature and the thermostat state array");
     return AFM_E_INVALID;
   }
   s.pos = state->pos;

@@ -10,6 +10,13 @@
 // kinetic energy is reduced in a fixed order (per-block partials, then one
 // block), so trajectories are bitwise reproducible.  Optionally the n-step
 // sequence is captured once into a hipGraph and replayed.
+//
+// NVT (the paper's canonical-ensemble runs): one Nose-Hoover thermostat over
+// all atoms, symmetric Trotter splitting around the Verlet step.  Each
+// thermostat half step is one single-block kernel that reduces the kinetic
+// energy partials, advances (xi, eta) in the device array nh and leaves the
+// velocity scale exp(-xi dt/2) there; the scaling itself is folded into the
+// next per-atom kernel.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -24,19 +31,25 @@
 namespace afm {
 
 constexpr double kAcc = 9.648533212e-3;
+constexpr double kKB = 8.617333262e-5;  // eV / K
 constexpr int kMdBlock = 256;
+// nh[]: thermostat state carried across steps and calls
+constexpr int kNhXi = 0, kNhEta = 1, kNhScale = 2, kNhKe = 3;
 
+// v = scale v + dt/2 F/m; r += dt v  (scale = nh[kNhScale] in NVT, else 1)
 __global__ void k_md_kick_drift(double* __restrict__ pos, double* __restrict__ vel,
                                 const double* __restrict__ F, const int32_t* __restrict__ species,
                                 const double* __restrict__ mass, int S, int64_t N, double dt,
-                                const double* __restrict__ ref, double half_skin2, int32_t* status) {
+                                const double* __restrict__ ref, double half_skin2, int32_t* status,
+                                const double* __restrict__ nh) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
   const double inv_m = kAcc / mass[min(max(species[i], 0), S - 1)];
+  const double sc = nh ? nh[kNhScale] : 1.0;
   double d2 = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const double v = vel[3 * i + q] + 0.5 * dt * F[3 * i + q] * inv_m;
+    const double v = sc * vel[3 * i + q] + 0.5 * dt * F[3 * i + q] * inv_m;
     vel[3 * i + q] = v;
     const double r = pos[3 * i + q] + dt * v;
     pos[3 * i + q] = r;
@@ -72,9 +85,69 @@ __global__ void __launch_bounds__(kMdBlock) k_md_kick(double* __restrict__ vel, 
   if (threadIdx.x == 0) ke_part[blockIdx.x] = part[0];
 }
 
+// per-block kinetic energy partials of the current velocities
+__global__ void __launch_bounds__(kMdBlock) k_md_ke(const double* __restrict__ vel,
+                                                     const int32_t* __restrict__ species,
+                                                     const double* __restrict__ mass, int S, int64_t N,
+                                                     double* __restrict__ ke_part) {
+  __shared__ double part[kMdBlock];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double ke = 0.0;
+  if (i < N) {
+    const double m = mass[min(max(species[i], 0), S - 1)];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ke += 0.5 * m * vel[3 * i + q] * vel[3 * i + q] / kAcc;
+  }
+  part[threadIdx.x] = ke;
+  __syncthreads();
+  for (int off = kMdBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ke_part[blockIdx.x] = part[0];
+}
+
+// One Nose-Hoover half step (time dt/2) from the kinetic energy partials:
+// xi += dt/4 G(KE); s = exp(-xi dt/2); KE *= s^2; eta += xi dt/2;
+// xi += dt/4 G(KE), G = (2 KE - gkT)/Q.  Leaves s and the scaled KE in nh;
+// with tlog, writes Q xi^2/2 + gkT eta there.
+__global__ void __launch_bounds__(256) k_nh_half(const double* __restrict__ ke_part, int64_t nb, double dt,
+                                                  double Q, double gkT, double* __restrict__ nh,
+                                                  double* __restrict__ tlog) {
+  __shared__ double pa[256];
+  double a = 0.0;
+  for (int64_t k = threadIdx.x; k < nb; k += 256) a += ke_part[k];
+  pa[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) pa[threadIdx.x] += pa[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double ke = pa[0], xi = nh[kNhXi], eta = nh[kNhEta];
+    xi += 0.25 * dt * (2.0 * ke - gkT) / Q;
+    const double s = exp(-0.5 * dt * xi);
+    ke *= s * s;
+    eta += 0.5 * dt * xi;
+    xi += 0.25 * dt * (2.0 * ke - gkT) / Q;
+    nh[kNhXi] = xi;
+    nh[kNhEta] = eta;
+    nh[kNhScale] = s;
+    nh[kNhKe] = ke;
+    if (tlog) *tlog = 0.5 * Q * xi * xi + gkT * eta;
+  }
+}
+
+__global__ void k_md_scale(double* __restrict__ vel, int64_t n, const double* __restrict__ nh) {
+  const double s = nh[kNhScale];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    vel[q] *= s;
+}
+
+// (KE, PE) of the step; in NVT the KE after the thermostat scaling (nh)
 __global__ void __launch_bounds__(256) k_md_log(const double* __restrict__ ke_part, int64_t nb,
                                                  const double* __restrict__ e_struct, int64_t B,
-                                                 double* __restrict__ log2) {
+                                                 double* __restrict__ log2, const double* __restrict__ nh) {
   __shared__ double pa[256], pb[256];
   double a = 0.0, b = 0.0;
   for (int64_t k = threadIdx.x; k < nb; k += 256) a += ke_part[k];
@@ -90,7 +163,7 @@ __global__ void __launch_bounds__(256) k_md_log(const double* __restrict__ ke_pa
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    log2[0] = pa[0];
+    log2[0] = nh ? nh[kNhKe] : pa[0];
     log2[1] = pb[0];
   }
 }
@@ -143,15 +216,25 @@ static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, cons
   double* ke_part = ws_ptr<double>(ws, L.md_ke);
   const double r_list = m->dims.r_cut + state->skin;
   const double hs2 = 0.25 * state->skin * state->skin;
+  const bool nvt = state->t_target_K > 0;
+  double* nh = nvt ? state->nh : nullptr;
+  const double gkT = (state->n_dof > 0 ? (double)state->n_dof : 3.0 * (double)N) * kKB * state->t_target_K;
+  const double Q = gkT * state->tau_fs * state->tau_fs;
   if (state->step == 0) {
     hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(3 * N, 256, 4096)), dim3(256), 0, st, (const double*)state->pos,
                        ref, 3 * N);
   }
   for (int32_t t = 0; t < n_steps; ++t) {
     const int64_t k = state->step + t + 1;
+    if (nvt) {
+      hipLaunchKernelGGL(k_md_ke, dim3(gb), dim3(kMdBlock), 0, st, (const double*)state->vel, s.species,
+                         state->mass_by_species, m->dims.S, N, ke_part);
+      hipLaunchKernelGGL(k_nh_half, dim3(1), dim3(256), 0, st, (const double*)ke_part, (int64_t)gb, state->dt_fs, Q,
+                         gkT, nh, (double*)nullptr);
+    }
     hipLaunchKernelGGL(k_md_kick_drift, dim3(gb), dim3(kMdBlock), 0, st, state->pos, state->vel,
                        (const double*)state->forces, s.species, state->mass_by_species, m->dims.S, N, state->dt_fs,
-                       (const double*)ref, hs2, n.status);
+                       (const double*)ref, hs2, n.status, (const double*)nh);
     AFM_LAUNCH_CHECK();
     if (state->rebuild_every > 0 && k % state->rebuild_every == 0) {
       hipLaunchKernelGGL(k_md_wrap, dim3(gb), dim3(256), 0, st, state->pos, s.cell, s.pbc, s.seg, s.B, N);
@@ -171,8 +254,14 @@ static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, cons
     if (rc) return rc;
     hipLaunchKernelGGL(k_md_kick, dim3(gb), dim3(kMdBlock), 0, st, state->vel, (const double*)state->forces,
                        s.species, state->mass_by_species, m->dims.S, N, state->dt_fs, ke_part);
+    if (nvt) {
+      hipLaunchKernelGGL(k_nh_half, dim3(1), dim3(256), 0, st, (const double*)ke_part, (int64_t)gb, state->dt_fs, Q,
+                         gkT, nh, state->thermostat_log ? state->thermostat_log + t : (double*)nullptr);
+      hipLaunchKernelGGL(k_md_scale, dim3(grid_for(3 * N, 256, 4096)), dim3(256), 0, st, state->vel, 3 * N,
+                         (const double*)nh);
+    }
     hipLaunchKernelGGL(k_md_log, dim3(1), dim3(256), 0, st, (const double*)ke_part, (int64_t)gb,
-                       (const double*)state->e_struct, s.B, state->energy_log + 2 * (int64_t)t);
+                       (const double*)state->e_struct, s.B, state->energy_log + 2 * (int64_t)t, (const double*)nh);
     AFM_LAUNCH_CHECK();
   }
   return AFM_OK;
@@ -180,7 +269,7 @@ static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, cons
 
 // cached graphs keyed by every pointer and size the captured sequence uses
 typedef std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*,
-                   int64_t, int32_t, int64_t, hipStream_t>
+                   int64_t, int32_t, int64_t, hipStream_t, const void*, const void*, double, double, int64_t>
     GraphKey;
 static std::mutex g_graph_mu;
 static std::map<GraphKey, hipGraphExec_t> g_graphs;
@@ -200,8 +289,10 @@ int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* s
     return rc;
   }
   const int64_t phase = state->rebuild_every > 0 ? state->step % state->rebuild_every : 0;
+  const bool nvt = state->t_target_K > 0;
   GraphKey key{m, ws->ptr, state->pos, state->vel, state->forces, state->energy_log, n.row_ptr, phase, n_steps,
-               (int64_t)s.N, st};
+               (int64_t)s.N, st, nvt ? state->nh : nullptr, nvt ? state->thermostat_log : nullptr,
+               nvt ? state->t_target_K : 0.0, nvt ? state->tau_fs : 0.0, nvt ? state->n_dof : 0};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
