@@ -181,7 +181,8 @@ def count_edges(calc, r):
 
 def bench_md(a):
     """1M-atom NVE MD (velocity Verlet, dt 0.5 fs, rebuild every 10 steps at
-    r_c + 0.5 A), BF16 path, steps replayed from captured graphs."""
+    r_c + 0.5 A), BF16 path, steps replayed from captured graphs; with --nvt T
+    the same run in the canonical ensemble (Nose-Hoover, tau 100 fs)."""
     import torch
     import synth
     import paper_2502_06073_amd as afm
@@ -195,26 +196,31 @@ def bench_md(a):
     calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=int(a.max_gib * 2 ** 30))
     masses = synth.species_masses(hp["n_species"], 3005)
     v0 = synth.maxwell_boltzmann(masses[s.species], 300.0, 3001)
-    md = afm.MD(calc, masses, v0, dt_fs=0.5, skin=skin, rebuild_every=10, use_graph=True)
+    md = afm.MD(calc, masses, v0, dt_fs=0.5, skin=skin, rebuild_every=10, use_graph=True,
+                t_target_K=a.nvt, tau_fs=100.0)
     n_listed = int(calc.nl.n_edges.item())
     n_active = count_edges(calc, hp["r_cut"])
     print(f"[bench] E: {s.n_atoms} atoms, {n_listed} listed edges, {n_active} within r_c, "
           f"{calc.ws.ws.n_chunks} chunks", file=sys.stderr, flush=True)
     block = 10
-    logs = []
+    logs, tlogs = [], []
     for _ in range(max(1, a.warmup // block)):
         logs.append(md.run(block))
+        tlogs.append(md.thermostat_log)
     torch.cuda.synchronize()
     n_blocks = max(1, a.steps // block)
     t0 = time.perf_counter()
     for _ in range(n_blocks):
         logs.append(md.run(block))
+        tlogs.append(md.thermostat_log)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     K = n_blocks * block
     value = s.n_atoms * K / dt
     log = torch.cat(logs).cpu().numpy()
     etot = log.sum(1) / s.n_atoms
+    if a.nvt > 0:      # the conserved quantity of the thermostatted dynamics
+        etot = etot + torch.cat(tlogs).cpu().numpy() / s.n_atoms
     print(f"[bench] E: {dt / K * 1e3:.1f} ms/step, {value:.4g} atom-steps/s", file=sys.stderr, flush=True)
     # one traced MD step (eager): the stages of a step as the MD loop runs
     # them (cutoff compaction included)
@@ -233,7 +239,9 @@ def bench_md(a):
                value=value, unit="atom-steps/s", n_gpus=1, steps=K, warmup=a.warmup, ms_per_step=dt / K * 1e3,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="bf16",
                data="synthetic (seeded jittered lattice, Maxwell-Boltzmann 300 K velocities, N(0,1/fan_in) weights)",
-               config=dict(workload=f"{s.n_atoms}-atom NVE MD (100^3 SC lattice a=2.3 A, 4 species), dt 0.5 fs, "
+               config=dict(workload=f"{s.n_atoms}-atom " + (f"NVT MD at {a.nvt:g} K (Nose-Hoover, tau 100 fs)"
+                                                               if a.nvt > 0 else "NVE MD") +
+                                    " (100^3 SC lattice a=2.3 A, 4 species), dt 0.5 fs, "
                                     f"rebuild every 10 steps at r_c 5.5 + 0.5 A skin, l_max 2, 3 layers, latent 256, "
                                     f"graph-replayed steps incl. rebuilds",
                            n_atoms=s.n_atoms, n_edges_listed=n_listed, n_edges_within_rc=n_active,
@@ -242,9 +250,9 @@ def bench_md(a):
                              frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
                mlp_roofline_frac_one_step=mlp_flops / (step_ms * 1e-3) / PEAK_BF16,
                stage_ms_one_step={k: round(v["total_ms"], 3) for k, v in stats.items()},
-               nve=dict(max_abs_drift_mev_per_atom=float(np.abs(etot - etot[0]).max() * 1e3),
+               **{"nvt_extended_energy" if a.nvt > 0 else "nve": dict(max_abs_drift_mev_per_atom=float(np.abs(etot - etot[0]).max() * 1e3),
                         slope_mev_per_atom_per_ps=float(np.polyfit(np.arange(len(etot)) * 0.5e-3, etot, 1)[0] * 1e3),
-                        steps=int(len(etot))))
+                        steps=int(len(etot)))})
     print(json.dumps(out), flush=True)
     return 0
 
@@ -346,9 +354,12 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="B")
+    ap.add_argument("--nvt", type=float, default=0.0, metavar="KELVIN",
+                    help="config E: canonical ensemble at this temperature (default: NVE)")
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fast", action="store_true", help="skip timing the fast-adjoint variant")
     ap.add_argument("--max-gib", type=float, default=96.0,
                     help="workspace limit for the 1M-atom MD workload (row chunks beyond it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -409,6 +420,15 @@ def main(argv=None):
                                        achieved=round(v["achieved"], 2), unit=v["unit"]) for k, v in roofs.items()},
                mlp_tflops_per_step=mlp_flops / (ms * 1e-3) / 1e12)
     outs = {"bf16": out_bf16}
+    if not a.no_fast:
+        # the opt-in fast adjoint: force GEMMs on the leading bf16 weight term only
+        print("[bench] timing bf16 with the fast adjoint", file=sys.stderr, flush=True)
+        _, _, _, calcf = setup(a.config, "bf16_fast")
+        dtf, outf, stf = time_steps(calcf, a.steps, a.warmup, trace=True)
+        out["bf16_fast_adjoint"] = dict(value=s.n_atoms * a.steps / dtf, ms_per_step=dtf / a.steps * 1e3,
+                                        stage_ms={k: round(v["total_ms"] / v["launches"], 4) for k, v in stf.items()})
+        outs["bf16_fast"] = outf
+        del calcf
     if not a.no_fp32:
         print("[bench] timing fp32 plain", file=sys.stderr, flush=True)
         _, _, _, calc32 = setup(a.config, "fp32")

@@ -70,7 +70,13 @@ typedef enum {
 typedef enum {
   AFM_FP64_REF = 0,    /* not built: the FP64 reference is the CPU oracle     */
   AFM_FP32_PLAIN = 1,  /* every step in FP32 on the vector ALUs               */
-  AFM_BF16_MFMA = 2    /* MLP GEMMs on BF16 MFMA with FP32 accumulation       */
+  AFM_BF16_MFMA = 2,   /* MLP GEMMs on BF16 MFMA with FP32 accumulation       */
+  AFM_BF16_MFMA_FAST_ADJOINT = 3
+  /* as AFM_BF16_MFMA, but the adjoint (force) GEMMs use only the leading
+   * bf16 term of each weight where the energy uses two: faster forces with
+   * a larger error (still within the BF16 force tolerance) that are no
+   * longer the exact gradient of the reported energy, so NVE energy
+   * conservation degrades; workspaces are planned as for AFM_BF16_MFMA */
 } afm_precision;
 
 /* ---- hyperparameters (host struct) --------------------------------------

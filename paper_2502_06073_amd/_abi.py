@@ -12,7 +12,7 @@ AFM_OK = 0
 STATUS = {0: "AFM_OK", -1: "AFM_E_INVALID", -2: "AFM_E_CAPACITY", -3: "AFM_E_NONFINITE",
           -4: "AFM_E_UNSUPPORTED", -5: "AFM_E_HIP", -6: "AFM_E_WEIGHTS"}
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_SPECIES, FLAG_SKIN, FLAG_IMAGES = 1, 2, 4, 8, 16
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_fast": 3}
 
 
 class Hparams(C.Structure):

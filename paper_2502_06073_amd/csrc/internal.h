@@ -64,7 +64,8 @@ struct ModelDims {
 
 struct afm_model {
   afm_hparams hp;
-  afm_precision prec;
+  afm_precision prec;          // AFM_FP32_PLAIN or AFM_BF16_MFMA
+  bool fast_adjoint = false;   // AFM_BF16_MFMA_FAST_ADJOINT was asked for
   afm::ModelDims dims;
   afm::Plan plan;
   int device;

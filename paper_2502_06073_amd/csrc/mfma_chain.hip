@@ -50,13 +50,15 @@ constexpr int NCBW = NCB;         // column blocks per wavefront
 constexpr int NWAVE = NPS * (NCB / NCBW);  // wavefronts: pair slot x column group
 constexpr int NTHR = 64 * NWAVE;
 constexpr int kSplit = 2;         // bf16 terms per weight (hi, lo)
-// The adjoint chains (forces) use the hi term alone.  Rounding a weight to
-// bf16 shifts every edge energy the same way, so the energy keeps lo to stay
-// within 1 meV/atom; in the adjoint the same rounding adds a force error of
-// the size the bf16 activations and gradients already cause (emulated in
-// FP64 on a 125-atom lattice: 3.9 -> 5.1 meV/A RMS, bound 20 meV/A), and
-// halves the weight stream and the MFMAs of the adjoint.
-constexpr int kSplitBwd = 1;
+// The adjoint chains (forces) use the same terms as the forward, so that the
+// forces are the gradient of the reported energy up to the bf16 rounding of
+// activations and gradients.  The fast-adjoint variant uses the hi term
+// alone there: rounding a weight to bf16 shifts every edge energy the same
+// way (the energy keeps lo to stay within 1 meV/atom), while in the adjoint
+// it adds a force error of the size the bf16 activations already cause
+// (emulated in FP64 on a 125-atom lattice: 3.9 -> 5.1 meV/A RMS, bound
+// 20 meV/A) and halves the adjoint's weight stream and MFMAs -- at the price
+// of forces that belong to a model ~4 meV/atom away from the reported one.
 // The environment embeddings omega = W_env x use the hi term alone in the
 // forward as well: omega enters the energy only through the per-atom sums
 // and tensor products, and rounding W_env to bf16 moved the emulated
@@ -610,7 +612,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 // ---------------------------------------------------------------------------
 // adjoint of one latent layer: dE/dx^L -> dE/dx^{L-1}, dE/ds^L, dE/du
 
-template <int W, int KS, int ENV, int DEPTH, bool LAST>
+template <int W, int KS, int ENV, int DEPTH, bool LAST, int kSplitBwd>
 __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_lat_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
@@ -676,7 +678,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     if (mine) {
       f32x4 acc[2][NCBW];
       zero_acc(acc);
-      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitBwd>(a.envb, pair, 0, S.act[1], acc, half, lane);
+      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, pair, 0, S.act[1], acc, half, lane);
       finish_pair(
           pair, acc, S.act[0],
           [&](int rb, int cb, f32x4& v) {
@@ -730,7 +732,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 // ---------------------------------------------------------------------------
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
-template <int T0, int T1, int T2, int W, int ENV>
+template <int T0, int T1, int T2, int W, int ENV, int kSplitBwd>
 __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_tb_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
@@ -748,7 +750,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   if (mine) {
     f32x4 acc[2][NCBW];
     zero_acc(acc);
-    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitBwd>(a.envb, pair, 0, S.act[1], acc, half, lane);
+    mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, pair, 0, S.act[1], acc, half, lane);
     finish_pair(
         pair, acc, S.act[0],
         [&](int rb, int cb, f32x4& v) {
@@ -926,7 +928,10 @@ int mfma_twobody_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                             \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                  \
-    hipLaunchKernelGGL((k_tb_bwd<a0, a1, a2, w, (l + 1) * c>), chain_grid(L), dim3(NTHR), 0, st, a); \
+    if (m->fast_adjoint)                                                                           \
+      hipLaunchKernelGGL((k_tb_bwd<a0, a1, a2, w, (l + 1) * c, 1>), chain_grid(L), dim3(NTHR), 0, st, a); \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_tb_bwd<a0, a1, a2, w, (l + 1) * c, kSplit>), chain_grid(L), dim3(NTHR), 0, st, a); \
     AFM_LAUNCH_CHECK();                                                                            \
     return AFM_OK;                                                                                 \
   }
@@ -948,7 +953,7 @@ int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   a.omega = layer < d.NL ? ws_ptr<uint16_t>(ws, L.omega[layer]) : nullptr;
   a.eps = ws_ptr<float>(ws, L.eps);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
-  const bool last = layer == d.NL;
+  const bool last = layer == d.NL, fast = m->fast_adjoint;
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                                  \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                       \
     if (last)                                                                                           \
@@ -976,13 +981,19 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   for (int k = 0; k < d.depth; ++k) a.latb[k] = frag_ptr(m, fo->latb[layer - 1][k]);
   if (layer < d.NL) a.envb = frag_ptr(m, fo->envb[layer]);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
-  const bool last = layer == d.NL;
+  const bool last = layer == d.NL, fast = m->fast_adjoint;
 #define X(w, c, l, dp, a0, a1, a2, n0)                                                                  \
   if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                       \
-    if (last)                                                                                           \
-      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, true>), chain_grid(L), dim3(NTHR), 0, st, a);  \
+    if (last && fast)                                                                                   \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, true, 1>), chain_grid(L), dim3(NTHR), 0, st, a); \
+    else if (last)                                                                                      \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, true, kSplit>), chain_grid(L), dim3(NTHR), 0, st, \
+                         a);                                                                            \
+    else if (fast)                                                                                      \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, false, 1>), chain_grid(L), dim3(NTHR), 0, st, a); \
     else                                                                                                \
-      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, false>), chain_grid(L), dim3(NTHR), 0, st, a); \
+      hipLaunchKernelGGL((k_lat_bwd<w, n0 * c, (l + 1) * c, dp, false, kSplit>), chain_grid(L), dim3(NTHR), 0, st, \
+                         a);                                                                            \
     AFM_LAUNCH_CHECK();                                                                                 \
     return AFM_OK;                                                                                      \
   }

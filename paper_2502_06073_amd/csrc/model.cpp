@@ -382,7 +382,7 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
                      afm_precision precision, afm_model** out) {
   if (!out || !weights) { set_error("null argument"); return AFM_E_INVALID; }
   *out = nullptr;
-  if (precision != AFM_FP32_PLAIN && precision != AFM_BF16_MFMA) {
+  if (precision != AFM_FP32_PLAIN && precision != AFM_BF16_MFMA && precision != AFM_BF16_MFMA_FAST_ADJOINT) {
     set_error("precision not built (the FP64 reference is the CPU oracle)");
     return AFM_E_UNSUPPORTED;
   }
@@ -398,7 +398,8 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
   for (int64_t q = 0; q < n_weights; ++q)
     if (!isfinite(weights[q])) { set_error("non-finite weight"); delete m; return AFM_E_NONFINITE; }
   m->hp = *hp;
-  m->prec = precision;
+  m->fast_adjoint = precision == AFM_BF16_MFMA_FAST_ADJOINT;
+  m->prec = m->fast_adjoint ? AFM_BF16_MFMA : precision;
   m->plan = make_plan(m->dims.lmax, m->dims.NL);
   hipError_t e = hipGetDevice(&m->device);
   if (e != hipSuccess) { set_error(hipGetErrorString(e)); delete m; return AFM_E_HIP; }

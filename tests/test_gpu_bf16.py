@@ -34,20 +34,21 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_bf16_parity(name):
+@pytest.mark.parametrize("name,prec", [(n, "bf16") for n in CASES] +
+                         [("Bshape_5cube", "bf16_fast"), ("D_12mixed", "bf16_fast"), ("E_6cube", "bf16_fast")])
+def test_bf16_parity(name, prec):
     from oracle import model as M
     cfg, s = CASES[name]()
     hp = synth.load_hparams(cfg)
     w = synth.draw_weights(M.param_layout(M.HParams.from_dict(hp)), synth.WEIGHT_SEEDS[cfg])
-    _say(f"[bf16] {name} N={s.n_atoms}")
+    _say(f"[{prec}] {name} N={s.n_atoms}")
     r_list = hp.get("r_list", hp["r_cut"])
-    gpu = gpu_run(hp, w, s, "bf16", r_list=r_list)
+    gpu = gpu_run(hp, w, s, prec, r_list=r_list)
     assert gpu["status"] == 0
     ref = M.energy_forces(M.HParams.from_dict(hp), w, s, r_list=r_list)
     rep = parity_report(hp, w, s, gpu, ref)
     f_rms_ref = float(np.sqrt(np.mean(ref["forces"] ** 2)))
-    _say(f"[bf16] {name} {rep} ref-force-rms {f_rms_ref:.3f}")
+    _say(f"[{prec}] {name} {rep} ref-force-rms {f_rms_ref:.3f}")
     assert rep["e_per_atom_abs"] <= E_TOL, rep
     assert rep["force_rms_abs"] <= F_TOL, rep
     assert rep["forces"] <= 0.03, rep          # relative, scale-free
