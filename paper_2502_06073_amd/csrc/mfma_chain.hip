@@ -624,7 +624,27 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   float gu[NCBW];
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
-  // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2; v = dE/dx^L on entry
+  // sigma_Z(i) escale gE_s of the edge in column block cb (last layer)
+  auto edge_coef = [&](int cb) {
+    const int64_t t = col_t(cb);
+    float ce = 0.0f;
+    if (t < M) {
+      const int64_t i = a.eidx[t];
+      ce = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
+      if (a.ges) {
+        int64_t lo = 0, hi = a.B;
+        while (hi - lo > 1) {
+          int64_t mid = (lo + hi) >> 1;
+          if (a.seg[mid] <= i) lo = mid; else hi = mid;
+        }
+        ce *= (float)a.ges[lo];
+      }
+    }
+    return ce;
+  };
+  // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2; v = dE/dx^L on entry.  The
+  // residual share r2 v of dE/dx^{L-1} is parked in gx, except in the last
+  // layer, where it is rebuilt from w_eff at the end
   auto head = [&](int rb, int cb, f32x4& v) {
     const int64_t t = col_t(cb);
     const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, cbA(cb), lane);
@@ -637,29 +657,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
       gu[cb] += gs_ * pa[q] * sg;
       v[q] = gs_ * u[cb] * sg * (1.0f + pa[q] * (1.0f - sg));
     }
-    if (t < M) st4(a.gx + t * W + 16 * rb + 4 * g, res);
+    if constexpr (!LAST)
+      if (t < M) st4(a.gx + t * W + 16 * rb + 4 * g, res);
   };
   if constexpr (LAST) {
     // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
     if (mine) {
       float ce[NCBW];
 #pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb) {
-        const int64_t t = col_t(cb);
-        ce[cb] = 0.0f;
-        if (t < M) {
-          const int64_t i = a.eidx[t];
-          ce[cb] = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
-          if (a.ges) {
-            int64_t lo = 0, hi = a.B;
-            while (hi - lo > 1) {
-              int64_t mid = (lo + hi) >> 1;
-              if (a.seg[mid] <= i) lo = mid; else hi = mid;
-            }
-            ce[cb] *= (float)a.ges[lo];
-          }
-        }
-      }
+      for (int cb = 0; cb < NCBW; ++cb) ce[cb] = edge_coef(cb);
       f32x4 acc[2][NCBW];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
@@ -721,7 +727,16 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
         if (t >= M) return;
         if (rb < RBW) {
           float* p = a.gx + t * W + 16 * rb + 4 * g;
-          st4(p, ld4(p) + v);
+          f32x4 res;
+          if constexpr (LAST) {
+            const float ce = edge_coef(cb);
+            const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) res[q] = (ce * we[q]) * r2;
+          } else {
+            res = ld4(p);
+          }
+          st4(p, res + v);
         } else if (16 * (rb - RBW) < KS) {
           st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
         }
