@@ -436,11 +436,13 @@ def rows_energy_grad(hp, weights: np.ndarray, sys, rows: np.ndarray,
 def vjp_weights(hp, weights: np.ndarray, sys, grad_e_struct: np.ndarray,
                 grad_forces: np.ndarray, nl: Optional[Dict] = None,
                 r_list: Optional[float] = None,
-                want_pos: bool = False) -> Dict[str, np.ndarray]:
-    """d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i] by double backward
-    (float64 autograd with create_graph), one structure at a time (exact:
-    structures do not interact).  Optionally the same derivative with
-    respect to the positions."""
+                want_pos: bool = False,
+                grad_virial: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i + sum_s gW_s : W_s] by
+    double backward (float64 autograd with create_graph), one structure at a
+    time (exact: structures do not interact), with the virial
+    W_s = -sum_e g_e delta_e^T built inside the graph.  Optionally the same
+    derivative with respect to the positions."""
     hp = _as_hp(hp)
     if nl is None:
         nl = nbr.build(sys, hp.r_cut if r_list is None else r_list)
@@ -469,14 +471,18 @@ def vjp_weights(hp, weights: np.ndarray, sys, grad_e_struct: np.ndarray,
         zs = species[a:b]
         Ei = rows_energy(hp, P, delta, zs[Il], zs[Jl], Il, zs)
         Es = Ei.sum()
+        Wv = torch.zeros(3, 3, dtype=DT)
         if e1 > e0:
             (g,) = torch.autograd.grad(Es, delta, create_graph=True)
             F = torch.zeros(b - a, 3, dtype=DT).index_add(0, Il, g)
             F = F.index_add(0, Jl, -g)
+            Wv = -(g[:, :, None] * delta[:, None, :]).sum(0)
         else:
             F = torch.zeros(b - a, 3, dtype=DT)
         obj = (float(grad_e_struct[s]) * Es
                + (torch.tensor(grad_forces[a:b], dtype=DT) * F).sum())
+        if grad_virial is not None:
+            obj = obj + (torch.tensor(grad_virial[s], dtype=DT) * Wv).sum()
         ins = [Wt] + ([pos] if want_pos else [])
         gr = torch.autograd.grad(obj, ins, allow_unused=True)
         if gr[0] is not None:
@@ -489,22 +495,45 @@ def vjp_weights(hp, weights: np.ndarray, sys, grad_e_struct: np.ndarray,
     return out
 
 
+def cell_volume(cell: np.ndarray) -> float:
+    """|a . (b x c)| of a cell whose rows are the lattice vectors."""
+    return float(abs(np.dot(cell[0], np.cross(cell[1], cell[2]))))
+
+
 def loss_and_grad(hp, weights: np.ndarray, sys, e_hat: np.ndarray,
                   f_hat: np.ndarray, nl: Optional[Dict] = None,
-                  r_list: Optional[float] = None) -> Dict[str, np.ndarray]:
-    """L = mean_s((E_s - E^_s) / N_s)^2 + (1 / 3N) sum_i |F_i - F^_i|^2 and
-    dL/dtheta (energy:force weights 1:1)."""
+                  r_list: Optional[float] = None,
+                  s_hat: Optional[np.ndarray] = None,
+                  weights_efs=(1.0, 1.0, 1.0)) -> Dict[str, np.ndarray]:
+    """L = wE mean_s((E_s - E^_s) / N_s)^2 + wF (1 / 3N) sum_i |F_i - F^_i|^2
+    [+ wS (1 / 9 P) sum over the P periodic structures of |sigma_s - s^_s|^2]
+    and dL/dtheta.  The paper's loss weighs per-atom energy, force and
+    stress errors 8:1:1 (Model Training); the stress reading is
+    sigma_s = W_s / V_s with the virial W_s = -dE/d(strain) and V_s the cell
+    volume (open structures carry no stress term)."""
     hp = _as_hp(hp)
+    wE, wF, wS = weights_efs
     res = energy_forces(hp, weights, sys, nl=nl, r_list=r_list)
     n_s = np.diff(sys.seg).astype(np.float64)
     B = sys.n_struct
     N = sys.n_atoms
     de = (res["e_struct"] - e_hat) / n_s
     df = res["forces"] - f_hat
-    loss = float(np.mean(de * de) + np.sum(df * df) / (3.0 * N))
-    g_e = 2.0 * de / n_s / B
-    g_f = 2.0 * df / (3.0 * N)
-    gw = vjp_weights(hp, weights, sys, g_e, g_f, nl=res["nl"])["grad_weights"]
+    loss = float(wE * np.mean(de * de) + wF * np.sum(df * df) / (3.0 * N))
+    g_e = wE * 2.0 * de / n_s / B
+    g_f = wF * 2.0 * df / (3.0 * N)
+    g_w = None
+    sigma = None
+    if s_hat is not None:
+        per = np.asarray(sys.pbc, dtype=bool)
+        n_p = int(per.sum())
+        vol = np.array([cell_volume(sys.cell[s]) if per[s] else 1.0 for s in range(B)])
+        sigma = res["virial"] / vol[:, None, None]
+        ds = np.where(per[:, None, None], sigma - s_hat, 0.0)
+        if n_p > 0:
+            loss += float(wS * np.sum(ds * ds) / (9.0 * n_p))
+            g_w = wS * 2.0 * ds / (9.0 * n_p) / vol[:, None, None]
+    gw = vjp_weights(hp, weights, sys, g_e, g_f, nl=res["nl"], grad_virial=g_w)["grad_weights"]
     return dict(loss=loss, grad_weights=gw, grad_e_struct=g_e,
-                grad_forces=g_f, e_struct=res["e_struct"],
-                forces=res["forces"])
+                grad_forces=g_f, grad_virial=g_w, e_struct=res["e_struct"],
+                forces=res["forces"], stress=sigma)

@@ -223,6 +223,30 @@ def config_d(n_struct: int = 512) -> System:
     return _pack(parts, 89)
 
 
+def mixed_batch(n_struct: int, n_lo: int, n_hi: int, density: float, n_species: int,
+                seed: int) -> System:
+    """Small stand-in for a training batch with stress: even-indexed
+    structures periodic triclinic, odd-indexed open clusters, N ~ U{n_lo..n_hi}
+    (draw: all sizes first, then each structure in turn), d_min 0.9 A."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = rng.integers(n_lo, n_hi + 1, size=n_struct)
+    parts = []
+    for s in range(n_struct):
+        if s % 2 == 0:
+            parts.append(_triclinic(rng, int(sizes[s]), density, 0.9, n_species))
+        else:
+            parts.append(_cluster(rng, int(sizes[s]), density, 0.9, n_species))
+    return _pack(parts, n_species)
+
+
+def stress_targets(sys: System, seed: int, scale: float = 0.01) -> np.ndarray:
+    """Target stresses N(0, scale^2) eV/A^3 per component for the periodic
+    structures, zeros for the open ones ([n_struct, 3, 3])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = scale * rng.standard_normal(size=(sys.n_struct, 3, 3))
+    return np.where(np.asarray(sys.pbc, dtype=bool)[:, None, None], t, 0.0)
+
+
 def config_e(n_side: int = 100) -> System:
     return cubic_lattice(n_side, 2.3, 0.25, 4, STRUCT_SEEDS["E"])
 

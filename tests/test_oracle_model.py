@@ -362,3 +362,43 @@ def test_subset_forces_match_full():
     sub = M.forces_subset(hp, w, s, atoms)
     np.testing.assert_allclose(sub["forces"], full["forces"][atoms], atol=1e-12)
     np.testing.assert_allclose(sub["e_atom"], full["e_atom"][atoms], rtol=1e-13)
+
+
+def test_stress_loss_gradient_finite_differences():
+    """Energy/force/stress loss (weights 8:1:1) on a batch with periodic and
+    open structures: the double backward through the virial matches central
+    differences of the loss in random weight directions."""
+    hp = small_hp()
+    s = synth.mixed_batch(3, 8, 12, 0.1, 3, 41)
+    w = weights(hp, 10)
+    e_hat, f_hat = synth.training_targets(s, 6)
+    s_hat = synth.stress_targets(s, 7)
+    res = M.loss_and_grad(hp, w, s, e_hat, f_hat, s_hat=s_hat, weights_efs=(8.0, 1.0, 1.0))
+    assert res["grad_virial"] is not None and np.abs(res["grad_virial"][1]).max() == 0.0
+    g = res["grad_weights"]
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.standard_normal(w.shape[0])
+        h = 1e-6
+        lp = M.loss_and_grad(hp, w + h * v, s, e_hat, f_hat, s_hat=s_hat, weights_efs=(8.0, 1.0, 1.0))["loss"]
+        lm = M.loss_and_grad(hp, w - h * v, s, e_hat, f_hat, s_hat=s_hat, weights_efs=(8.0, 1.0, 1.0))["loss"]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_virial_term_of_the_double_backward_alone():
+    """d/dtheta (gW : W) from the double backward equals central differences
+    of gW : W, with W from the first-order oracle (pinned by strain FD)."""
+    hp = small_hp()
+    s = synth.mixed_batch(2, 9, 9, 0.1, 3, 43)
+    w = weights(hp, 11)
+    rng = np.random.default_rng(4)
+    gW = rng.standard_normal((s.n_struct, 3, 3))
+    out = M.vjp_weights(hp, w, s, np.zeros(s.n_struct), np.zeros((s.n_atoms, 3)), grad_virial=gW)
+    v = rng.standard_normal(w.shape[0])
+    h = 1e-6
+
+    def obj(wv):
+        return float(np.sum(gW * M.energy_forces(hp, wv, s)["virial"]))
+    fd = (obj(w + h * v) - obj(w - h * v)) / (2 * h)
+    assert abs(fd - out["grad_weights"] @ v) <= 1e-6 * max(abs(fd), 1e-3)
