@@ -148,6 +148,23 @@ int afm_model_create(const afm_hparams* hp /*host*/, const double* weights /*hos
                      int64_t n_weights, afm_precision precision, afm_model** out /*host*/);
 int afm_model_destroy(afm_model* model);
 
+/* Replace the model's weight values (host, float64, the same layout and
+ * count as at creation) — a training step's update.  Repacks into the
+ * existing device allocation after a device-wide synchronisation, so no
+ * work that reads the model may be in flight or captured in a graph being
+ * replayed; blocking; allocates nothing. */
+int afm_model_set_weights(afm_model* model, const double* weights /*host*/, int64_t n_weights);
+
+/* One Adam update (Model Training: parameters optimised with Adam; Kingma &
+ * Ba's algorithm with bias correction): for q < n,
+ *   m1 = b1 m1 + (1 - b1) g;  m2 = b2 m2 + (1 - b2) g^2;
+ *   theta -= lr (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps)
+ * with g = grad[q] (float32, e.g. afm_backward_forces_backward's output)
+ * and step count t >= 1.  theta, m1, m2: device float64 [n], updated in
+ * place (m1 = m2 = 0 before the first step).  Asynchronous on `stream`. */
+int afm_adam_step(double* theta, const float* grad, double* m1, double* m2, int64_t n, double lr,
+                  double beta1, double beta2, double eps, int64_t t, void* stream);
+
 /* ---- systems, neighbour lists, workspaces --------------------------------- */
 typedef struct {
   int64_t n_atoms;
@@ -229,19 +246,24 @@ int afm_energy_forces(const afm_model* model, const afm_system* sys, const afm_n
                       double* e_atom, double* e_struct, double* forces, double* virial,
                       const afm_workspace* ws, void* stream);
 
-/* Weight gradients for force matching (Model Training: the loss combines
- * energy and force errors): given upstream grad_e_struct[n_struct] and
- * grad_forces[n_atoms,3] (device, float64), writes
- *   grad_weights[n_params] = d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i]
- * (device, float32, in the flat weight layout, overwritten).  A NULL
- * grad_e_struct or grad_forces stands for zeros.  Needs a workspace planned
+/* Weight gradients for force and stress matching (Model Training: the loss
+ * combines per-atom energy, force and stress errors): given upstream
+ * grad_e_struct[n_struct], grad_forces[n_atoms,3] and
+ * grad_virial[n_struct,3,3] (device, float64), writes
+ *   grad_weights[n_params] = d/dtheta [sum_s gE_s E_s + sum_i gF_i . F_i
+ *                                      + sum_s gW_s : W_s]
+ * with W_s the virial of afm_backward_forces (device, float32, in the flat
+ * weight layout, overwritten).  A NULL grad_e_struct, grad_forces or
+ * grad_virial stands for zeros.  (A stress sigma_s = W_s / V_s enters as
+ * gW_s = g_sigma_s / V_s.)  Needs a workspace planned
  * with with_second_order = 1; runs in FP32 on the vector ALUs with FP64
  * accumulation of the weight gradients (deterministic).  grad_pos must be
  * NULL (position gradients are not built). */
 int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
                                  const afm_nlist* nl, const double* grad_e_struct,
-                                 const double* grad_forces, float* grad_weights,
-                                 double* grad_pos, const afm_workspace* ws, void* stream);
+                                 const double* grad_forces, const double* grad_virial,
+                                 float* grad_weights, double* grad_pos, const afm_workspace* ws,
+                                 void* stream);
 
 /* ---- molecular dynamics ---------------------------------------------------
  * Methodology (MD simulations, 0.5 fs time step): velocity Verlet in

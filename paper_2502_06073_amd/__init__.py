@@ -25,7 +25,7 @@ from . import _abi
 from ._abi import AfmError, check, load
 
 __all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
-           "param_layout", "cg_real", "hparams_struct", "stage_costs", "energy_and_forces", "AfmError",
+           "param_layout", "cg_real", "hparams_struct", "stage_costs", "energy_and_forces", "AfmError", "Adam",
            "trace_enable", "trace_read", "energy_forces_for_training", "MD"]
 
 
@@ -119,7 +119,8 @@ def cg_real(l1: int, l2: int, l3: int) -> np.ndarray:
 
 
 class Model:
-    """Device copy of a weight vector for one precision ("fp32" or "bf16")."""
+    """Device copy of a weight vector for one precision ("fp32", "bf16" or
+    "bf16_fast", the BF16 path with the fast adjoint)."""
 
     def __init__(self, hp: Dict, weights: np.ndarray, precision: str = "bf16", device: int = 0):
         lib = load()
@@ -134,6 +135,13 @@ class Model:
                   lib.afm_model_create(C.byref(h), w.ctypes.data_as(C.POINTER(C.c_double)), w.shape[0],
                                        _abi.PRECISION[precision], C.byref(handle)))
         self.handle = handle
+
+    def set_weights(self, weights: np.ndarray):
+        """New weight values (same layout); synchronises the device."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        with torch.cuda.device(self.device):
+            check("afm_model_set_weights",
+                  load().afm_model_set_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_double)), w.shape[0]))
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -275,9 +283,9 @@ class Calculator:
     def model_n_params(self) -> int:
         return int(sum(b["size"] for b in param_layout(self.model.hp)))
 
-    def forces_backward(self, grad_e_struct=None, grad_forces=None) -> torch.Tensor:
-        """Weight gradient of sum gE E + sum gF . F (needs second_order=True)."""
-        return _forces_backward(self, grad_e_struct, grad_forces)
+    def forces_backward(self, grad_e_struct=None, grad_forces=None, grad_virial=None) -> torch.Tensor:
+        """Weight gradient of sum gE E + sum gF . F + sum gW : W (needs second_order=True)."""
+        return _forces_backward(self, grad_e_struct, grad_forces, grad_virial=grad_virial)
 
     def _outs(self, forces: bool):
         dev = self.model.device
@@ -321,43 +329,74 @@ class Calculator:
 
 
 def _forces_backward(calc: "Calculator", grad_e_struct: Optional[torch.Tensor],
-                     grad_forces: Optional[torch.Tensor], pos: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """d/dtheta [sum gE E + sum gF . F] (float32, flat weight layout)."""
+                     grad_forces: Optional[torch.Tensor], pos: Optional[torch.Tensor] = None,
+                     grad_virial: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """d/dtheta [sum gE E + sum gF . F + sum gW : W] (float32, flat weight layout)."""
     dev = calc.model.device
     g = torch.empty(calc.model_n_params(), dtype=torch.float32, device=dev)
     gE = None if grad_e_struct is None else grad_e_struct.to(torch.float64).contiguous()
     gF = None if grad_forces is None else grad_forces.to(torch.float64).contiguous()
+    gW = None if grad_virial is None else grad_virial.to(torch.float64).contiguous()
     with torch.cuda.device(dev):
         check("afm_backward_forces_backward",
               calc.lib.afm_backward_forces_backward(calc.model.handle, C.byref(calc.sysd.struct(pos)),
-                                                    C.byref(calc.nl.struct()), _ptr(gE), _ptr(gF), _ptr(g), None,
-                                                    C.byref(calc.ws.ws), _stream_ptr(dev)))
+                                                    C.byref(calc.nl.struct()), _ptr(gE), _ptr(gF), _ptr(gW),
+                                                    _ptr(g), None, C.byref(calc.ws.ws), _stream_ptr(dev)))
     return g
 
 
 class _ForceMatchFn(torch.autograd.Function):
-    """(E_s, F) as functions of a proxy weight tensor: the backward returns
-    the weight gradient of sum gE E + sum gF . F from the library's
-    second-order entry point (the weights themselves live in the model)."""
+    """(E_s, F, W_s) as functions of a proxy weight tensor: the backward
+    returns the weight gradient of sum gE E + sum gF . F + sum gW : W from the
+    library's second-order entry point (the weights themselves live in the
+    model)."""
 
     @staticmethod
     def forward(ctx, theta, calc):
-        out = calc.energy_forces(virial=False)
+        out = calc.energy_forces(virial=True)
         ctx.calc = calc
         ctx.theta_meta = (theta.device, theta.dtype)
-        return out["e_struct"], out["forces"]
+        ctx.set_materialize_grads(False)     # unused outputs arrive as None
+        return out["e_struct"], out["forces"], out["virial"]
 
     @staticmethod
-    def backward(ctx, gE, gF):
-        g = _forces_backward(ctx.calc, gE, gF)
+    def backward(ctx, gE, gF, gW):
+        g = _forces_backward(ctx.calc, gE, gF, grad_virial=gW)
         dev, dt = ctx.theta_meta
         return g.to(device=dev, dtype=dt), None
 
 
-def energy_forces_for_training(calc: "Calculator", theta: torch.Tensor):
-    """E_s and F whose gradients flow to `theta` (a float64 tensor standing
-    for the model's weights; requires a calculator with second_order=True)."""
-    return _ForceMatchFn.apply(theta, calc)
+def energy_forces_for_training(calc: "Calculator", theta: torch.Tensor, virial: bool = False):
+    """E_s and F (and the virials W_s if `virial`) whose gradients flow to
+    `theta` (a float64 tensor standing for the model's weights; requires a
+    calculator with second_order=True)."""
+    E, F, W = _ForceMatchFn.apply(theta, calc)
+    return (E, F, W) if virial else (E, F)
+
+
+class Adam:
+    """Adam on the model's flat weight vector: step(grad) applies
+    afm_adam_step to a device float64 copy of the weights and repacks the
+    model with afm_model_set_weights."""
+
+    def __init__(self, model: Model, weights: np.ndarray, lr: float = 1e-3, betas=(0.9, 0.999),
+                 eps: float = 1e-8):
+        dev = model.device
+        self.model = model
+        self.theta = torch.as_tensor(np.ascontiguousarray(weights, np.float64), device=dev).clone()
+        self.m1 = torch.zeros_like(self.theta)
+        self.m2 = torch.zeros_like(self.theta)
+        self.lr, self.betas, self.eps, self.t = float(lr), betas, float(eps), 0
+
+    def step(self, grad: torch.Tensor):
+        g = grad.to(device=self.theta.device, dtype=torch.float32).contiguous()
+        self.t += 1
+        dev = self.model.device
+        with torch.cuda.device(dev):
+            check("afm_adam_step", load().afm_adam_step(
+                _ptr(self.theta), _ptr(g), _ptr(self.m1), _ptr(self.m2), self.theta.numel(), self.lr,
+                float(self.betas[0]), float(self.betas[1]), self.eps, self.t, _stream_ptr(dev)))
+        self.model.set_weights(self.theta.cpu().numpy())
 
 
 class _EnergyFn(torch.autograd.Function):

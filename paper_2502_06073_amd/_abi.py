@@ -73,6 +73,9 @@ EXPORTS = {
     "afm_model_create": [C.POINTER(Hparams), C.POINTER(C.c_double), C.c_int64, C.c_int,
                          C.POINTER(C.c_void_p)],
     "afm_model_destroy": [C.c_void_p],
+    "afm_model_set_weights": [C.c_void_p, C.POINTER(C.c_double), C.c_int64],
+    "afm_adam_step": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                      C.c_double, C.c_double, C.c_int64, C.c_void_p],
     "afm_workspace_plan": [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                            C.POINTER(Workspace)],
     "afm_build_neighbors": [C.POINTER(System), C.c_double, C.POINTER(Nlist), C.POINTER(Workspace),
@@ -84,7 +87,7 @@ EXPORTS = {
     "afm_energy_forces": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.POINTER(Workspace), C.c_void_p],
     "afm_backward_forces_backward": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Workspace),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Workspace),
                                      C.c_void_p],
     "afm_md_step": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(MdState), C.c_int32,
                     C.POINTER(Workspace), C.c_void_p],

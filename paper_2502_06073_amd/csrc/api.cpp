@@ -125,8 +125,9 @@ int afm_energy_forces(const afm_model* m, const afm_system* sys, const afm_nlist
 }
 
 int afm_backward_forces_backward(const afm_model* m, const afm_system* sys, const afm_nlist* nl,
-                                 const double* grad_e_struct, const double* grad_forces, float* grad_weights,
-                                 double* grad_pos, const afm_workspace* ws, void* stream) {
+                                 const double* grad_e_struct, const double* grad_forces,
+                                 const double* grad_virial, float* grad_weights, double* grad_pos,
+                                 const afm_workspace* ws, void* stream) {
   SysDev s{};
   NlDev n{};
   WsLayout L{};
@@ -137,7 +138,8 @@ int afm_backward_forces_backward(const afm_model* m, const afm_system* sys, cons
   if (!grad_weights) { set_error("grad_weights is required"); return AFM_E_INVALID; }
   if (grad_pos) { set_error("grad_pos is not built (must be NULL)"); return AFM_E_UNSUPPORTED; }
   if (!ws->with_second_order) { set_error("workspace was planned without the second-order buffers"); return AFM_E_INVALID; }
-  return run_second_order(m, s, n, ws, L, grad_e_struct, grad_forces, grad_weights, (hipStream_t)stream);
+  return run_second_order(m, s, n, ws, L, grad_e_struct, grad_forces, grad_virial, grad_weights,
+                          (hipStream_t)stream);
 }
 
 int afm_md_step(const afm_model* m, const afm_system* sys, afm_nlist* nl, afm_md_state* state, int32_t n_steps,

@@ -72,6 +72,7 @@ struct afm_model {
   int64_t n_params;
   std::vector<afm_param_block> blocks;
   void* dev_mem = nullptr;
+  int64_t dev_bytes = 0;
   afm::DevWeights W;
 };
 
@@ -196,8 +197,8 @@ int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, cons
                  hipStream_t st);                                          // neighbors.hip
 
 int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
-                     const WsLayout& L, const double* gE, const double* gF, float* grad_out,
-                     hipStream_t st);                                      // second_order.hip
+                     const WsLayout& L, const double* gE, const double* gF, const double* gW,
+                     float* grad_out, hipStream_t st);                                      // second_order.hip
 
 int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl,
                       const afm_workspace* ws, const WsLayout& L, double* forces,

@@ -504,6 +504,25 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
   return AFM_OK;
 }
 
+int afm_model_set_weights(afm_model* m, const double* weights, int64_t n_weights) {
+  if (!m || !weights) { set_error("null argument"); return AFM_E_INVALID; }
+  if (n_weights != m->n_params) {
+    set_error("expected " + std::to_string(m->n_params) + " weights, got " + std::to_string(n_weights));
+    return AFM_E_WEIGHTS;
+  }
+  for (int64_t q = 0; q < n_weights; ++q)
+    if (!isfinite(weights[q])) { set_error("non-finite weight"); return AFM_E_NONFINITE; }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess && dev != m->device) e = hipSetDevice(m->device);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return AFM_E_HIP; }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return AFM_E_HIP; }
+  const int rc = afm::pack_weights(m, weights);
+  if (dev != m->device) (void)hipSetDevice(dev);
+  return rc;
+}
+
 int afm_model_destroy(afm_model* m) {
   if (!m) return AFM_OK;
   if (m->dev_mem) {

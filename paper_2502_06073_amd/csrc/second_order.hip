@@ -2,10 +2,12 @@
 // (Methodology / Model Training: the loss combines energy and force errors,
 // so training needs d/dtheta of the forces).
 //
-// Objective J(theta) = sum_s gE_s E_s + sum_i gF_i . F_i.  With
-// F_i = -dE/dr_i this is J = sum_s gE_s E_s - Edot, where Edot is the
-// derivative of E along positions moving with velocity gF, i.e. along edge
-// tangents delta_dot_e = gF_j - gF_i.  The schedule is forward-over-reverse:
+// Objective J(theta) = sum_s gE_s E_s + sum_i gF_i . F_i + sum_s gW_s : W_s.
+// With F_i = -dE/dr_i and W_s = -sum_e g_e delta_e^T (g_e = dE/d delta_e)
+// this is J = sum_s gE_s E_s - Edot, where Edot is the derivative of E along
+// the edge tangents delta_dot_e = (gF_j - gF_i) + gW_s delta_e: positions
+// moving with velocity gF plus a homogeneous deformation gW of each
+// structure (the stress term).  The schedule is forward-over-reverse:
 // every network quantity z gets a tangent z_dot (stacked as extra rows under
 // the primal rows, so each GEMM serves both), then J is reversed with
 // respect to the weights through primal and tangent together.  Basis and
@@ -70,15 +72,29 @@ __device__ __forceinline__ void sh9_jvp(float x, float y, float z, const float* 
 
 // tangent geometry: geo2[t] = (delta_dot[3], d_dot, u_dot, Y_dot[9], -, -)
 __global__ void k_geom2(RowRange rr, const float* __restrict__ geo, const int32_t* __restrict__ eidx,
-                        const int32_t* __restrict__ col, const double* __restrict__ gF, float r_cut, int p,
-                        float* __restrict__ geo2) {
+                        const int32_t* __restrict__ col, const double* __restrict__ gF,
+                        const double* __restrict__ gW, const int64_t* __restrict__ seg, int64_t B, float r_cut,
+                        int p, float* __restrict__ geo2) {
   int64_t e0, e1;
   rr.get(e0, e1);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < e1 - e0; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = eidx[t], j = col[e0 + t];
-    float dd[3];
-    for (int q = 0; q < 3; ++q) dd[q] = gF ? (float)(gF[3 * j + q] - gF[3 * i + q]) : 0.0f;
     const float* G = geo + t * GEO_STRIDE;
+    double dd64[3] = {0.0, 0.0, 0.0};
+    if (gF)
+      for (int q = 0; q < 3; ++q) dd64[q] = gF[3 * j + q] - gF[3 * i + q];
+    if (gW) {
+      int64_t lo = 0, hi = B;
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (seg[mid] <= i) lo = mid; else hi = mid;
+      }
+      const double* w = gW + 9 * lo;
+      for (int q = 0; q < 3; ++q)
+        dd64[q] += w[3 * q] * (double)G[0] + w[3 * q + 1] * (double)G[1] + w[3 * q + 2] * (double)G[2];
+    }
+    float dd[3];
+    for (int q = 0; q < 3; ++q) dd[q] = (float)dd64[q];
     const float r = G[GEO_D];
     float* o = geo2 + t * GEO_STRIDE;
     if (r > 0.0f) {
@@ -840,7 +856,8 @@ int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const 
                     RowRange rr, hipStream_t st);   // forward.hip
 
 int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
-                     const WsLayout& L, const double* gE, const double* gF, float* grad_out, hipStream_t st) {
+                     const WsLayout& L, const double* gE, const double* gF, const double* gW, float* grad_out,
+                     hipStream_t st) {
   TraceScope tr(st, "second_order");
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
@@ -873,7 +890,8 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
     rc = launch_geometry(m, s, nl, ws, L, rr, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_geom2, dim3(grid_for(stack, 256, 65536)), dim3(256), 0, st, rr, (const float*)geo,
-                       (const int32_t*)eidx, (const int32_t*)nl.col, gF, (float)d.r_cut, d.p, geo2);
+                       (const int32_t*)eidx, (const int32_t*)nl.col, gF, gW, s.seg, s.B, (float)d.r_cut, d.p,
+                       geo2);
     float* tbp0 = ws_ptr<float>(ws, L.so_tb_pre[0]);
     hipLaunchKernelGGL(k_tb2_first, dim3(grid_for((int64_t)stack * d.tb[0], 256, 65536)), dim3(256), 0, st, rr, stack,
                        (const float*)geo, (const float*)geo2, (const int32_t*)eidx, (const int32_t*)nl.col, s.species,

@@ -96,10 +96,17 @@ int pack_weights(afm_model* m, const double* w) {
     frag_off = reserve((int64_t)frags.size());
     memcpy(host.data() + frag_off, frags.data(), frags.size());
   }
-  void* dev = nullptr;
-  hipError_t e = hipMalloc(&dev, host.size());
-  if (e != hipSuccess) { set_error(std::string("hipMalloc weights: ") + hipGetErrorString(e)); return AFM_E_HIP; }
-  m->dev_mem = dev;
+  // a repack (new weight values, same model) reuses the allocation: the
+  // layout depends only on the shapes
+  void* dev = m->dev_mem;
+  hipError_t e = hipSuccess;
+  if (dev && m->dev_bytes != (int64_t)host.size()) { set_error("internal: weight layout changed"); return AFM_E_INVALID; }
+  if (!dev) {
+    e = hipMalloc(&dev, host.size());
+    if (e != hipSuccess) { set_error(std::string("hipMalloc weights: ") + hipGetErrorString(e)); return AFM_E_HIP; }
+    m->dev_mem = dev;
+    m->dev_bytes = (int64_t)host.size();
+  }
   e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) { set_error(std::string("hipMemcpy weights: ") + hipGetErrorString(e)); return AFM_E_HIP; }
   for (auto& f : fix) *f.dst = static_cast<char*>(dev) + f.off;

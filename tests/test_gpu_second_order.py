@@ -101,3 +101,62 @@ def test_training_loss_gradient_through_autograd():
     _say(f"[train] loss gpu {loss.item():.6f} oracle {ref['loss']:.6f}; grad rel {err:.2e}")
     assert abs(loss.item() - ref["loss"]) < 1e-5 * abs(ref["loss"])
     assert err < TOL
+
+
+def _mixed():
+    return synth.load_hparams("C"), synth.mixed_batch(4, 20, 60, 0.1, 10, 113)
+
+
+def test_second_order_virial_term_matches_oracle():
+    import torch
+    from oracle import model as M
+    hp, s = _mixed()
+    w = weights_for(hp, 34)
+    rng = np.random.default_rng(6)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    gW = rng.standard_normal((s.n_struct, 3, 3))
+    calc = _calc(hp, w, s)
+    dev = "cuda"
+    g_all = calc.forces_backward(torch.tensor(gE, device=dev), torch.tensor(gF, device=dev),
+                                 torch.tensor(gW, device=dev)).cpu().numpy().astype(np.float64)
+    g_w = calc.forces_backward(None, None, torch.tensor(gW, device=dev)).cpu().numpy().astype(np.float64)
+    ref_all = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, gF, grad_virial=gW)["grad_weights"]
+    ref_w = M.vjp_weights(M.HParams.from_dict(hp), w, s, np.zeros(s.n_struct), np.zeros_like(gF),
+                          grad_virial=gW)["grad_weights"]
+    e_all = np.linalg.norm(g_all - ref_all) / np.linalg.norm(ref_all)
+    e_w = np.linalg.norm(g_w - ref_w) / np.linalg.norm(ref_w)
+    _say(f"[d2 virial] mixed batch {s.n_struct} structures / {s.n_atoms} atoms: all terms rel {e_all:.2e}, "
+         f"virial term alone rel {e_w:.2e}")
+    assert e_all < TOL and e_w < TOL
+
+
+def test_training_loss_with_stress_through_autograd():
+    """The 8:1:1 per-atom energy / force / stress loss (stress on the periodic
+    structures) and its weight gradient, against the oracle."""
+    import torch
+    import paper_2502_06073_amd as afm
+    from oracle import model as M
+    hp, s = _mixed()
+    w = weights_for(hp, 35)
+    e_hat, f_hat = synth.training_targets(s, 8)
+    s_hat = synth.stress_targets(s, 9)
+    calc = _calc(hp, w, s)
+    theta = torch.zeros(w.shape[0], dtype=torch.float64, requires_grad=True)
+    E, F, W = afm.energy_forces_for_training(calc, theta, virial=True)
+    dev = "cuda"
+    n_s = torch.tensor(np.diff(s.seg), dtype=torch.float64, device=dev)
+    per = np.asarray(s.pbc, dtype=bool)
+    vol = torch.tensor([M.cell_volume(s.cell[k]) if per[k] else 1.0 for k in range(s.n_struct)], device=dev)
+    mask = torch.tensor(per, device=dev, dtype=torch.float64)[:, None, None]
+    de = (E - torch.tensor(e_hat, device=dev)) / n_s
+    df = F - torch.tensor(f_hat, device=dev)
+    ds = (W / vol[:, None, None] - torch.tensor(s_hat, device=dev)) * mask
+    loss = 8.0 * (de * de).mean() + (df * df).sum() / (3.0 * s.n_atoms) + (ds * ds).sum() / (9.0 * per.sum())
+    loss.backward()
+    ref = M.loss_and_grad(M.HParams.from_dict(hp), w, s, e_hat, f_hat, s_hat=s_hat, weights_efs=(8.0, 1.0, 1.0))
+    g = theta.grad.cpu().numpy()
+    err = np.linalg.norm(g - ref["grad_weights"]) / np.linalg.norm(ref["grad_weights"])
+    _say(f"[train stress] loss gpu {loss.item():.6f} oracle {ref['loss']:.6f}; grad rel {err:.2e}")
+    assert abs(loss.item() - ref["loss"]) < 1e-5 * abs(ref["loss"])
+    assert err < TOL
