@@ -11,6 +11,11 @@
 // k_wgrad:  P[slice][n][k] = sum_{m in slice} A(m, n) * B(m, k): weight
 // gradients reduced over edges; slices are summed afterwards in a fixed
 // order (deterministic, no atomics).
+//
+// The _mfma variants (second-order path) stage the same LDS tiles and
+// multiply them on the matrix cores in FP32 (v_mfma_f32_16x16x4f32, FP32
+// products and accumulation): each of the 4 wavefronts owns a 32 x 32
+// quarter of the tile as 2 x 2 blocks of 16 x 16.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -84,12 +89,102 @@ __global__ void __launch_bounds__(256) k_sgemm(RowRange rr, int K, int N, const 
   }
 }
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// A (16 x 4) and B (4 x 16) operands: lane l holds row / column l % 16 at
+// k = l / 16; the 16 x 16 result: lane l holds column l % 16, rows
+// 4 (l / 16) .. 4 (l / 16) + 3.
+__device__ __forceinline__ f32x4_t mfma_f32(float a, float b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <bool NT, class AL, class EP>
+__global__ void __launch_bounds__(256) k_sgemm_mfma(RowRange rr, int K, int N, const float* __restrict__ W, int ldw,
+                                                    AL al, EP ep, int stack) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int rows = stack ? 2 * stack : M;
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= rows) return;
+  if (stack && (m0 % stack) >= M) return;
+  const int n0 = blockIdx.y * 64;
+  constexpr int KS = 32;  // k per stage
+  __shared__ float As[KS][68];
+  __shared__ float Bs[KS][68];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  // the next stage is fetched into registers while the current one is
+  // multiplied
+  float ra[KS / 4], rb[KS / 4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < KS / 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / KS, kk = idx % KS;
+      const int m = m0 + r, k = k0 + kk;
+      ra[q] = (m < rows && row_live(m, M, stack) && k < K) ? al(m, k) : 0.0f;
+      int kb, c;
+      if (NT) { c = idx / KS; kb = idx % KS; } else { kb = idx >> 6; c = idx & 63; }
+      const int k2 = k0 + kb, n = n0 + c;
+      float v = 0.0f;
+      if (k2 < K && n < N) v = NT ? W[(int64_t)n * ldw + k2] : W[(int64_t)k2 * ldw + n];
+      rb[q] = v;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+#pragma unroll
+    for (int q = 0; q < KS / 4; ++q) {
+      const int idx = tid + 256 * q;
+      As[idx % KS][idx / KS] = ra[q];
+      if (NT) Bs[idx % KS][idx / KS] = rb[q]; else Bs[idx >> 6][idx & 63] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KS < K) fetch(k0 + KS);
+#pragma unroll
+    for (int s4 = 0; s4 < KS / 4; ++s4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[4 * s4 + lk][32 * wr + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[4 * s4 + lk][32 * wc + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + 32 * wr + 16 * i + 4 * lk + q;
+      if (m >= rows || !row_live(m, M, stack)) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 32 * wc + 16 * j + lr;
+        if (n < N) ep(m, n, acc[i][j][q]);
+      }
+    }
+}
+
+template <bool NT, bool MF = false, class AL, class EP>
 inline void sgemm(hipStream_t st, RowRange rr, int64_t max_rows, int K, int N, const float* W, int ldw, AL al,
                   EP ep, int stack = 0) {
   const int64_t rows = stack ? 2 * (int64_t)stack : max_rows;
   dim3 grid((unsigned)((rows + 63) / 64 > 0 ? (rows + 63) / 64 : 1), (unsigned)((N + 63) / 64));
-  hipLaunchKernelGGL((k_sgemm<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
+  if constexpr (MF)
+    hipLaunchKernelGGL((k_sgemm_mfma<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
+  else
+    hipLaunchKernelGGL((k_sgemm<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
 }
 
 template <class ALA, class ALB>
@@ -144,6 +239,79 @@ __global__ void __launch_bounds__(256) k_wgrad(RowRange rr, int stack, int N, in
       if (k < K) P[(int64_t)n * K + k] = acc[i][j];
     }
   }
+}
+
+template <class ALA, class ALB>
+__global__ void __launch_bounds__(256) k_wgrad_mfma(RowRange rr, int stack, int N, int K, int rows_per_slice,
+                                                    ALA A, ALB Bl, float* __restrict__ partial) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int rows = stack ? 2 * stack : M;
+  const int n0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+  const int slice = blockIdx.z;
+  const int r0 = slice * rows_per_slice;
+  const int r1 = min(rows, r0 + rows_per_slice);
+  constexpr int MS = 32;  // rows (the reduction index) per stage
+  __shared__ float As[MS][68];
+  __shared__ float Bs[MS][68];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  float ra[MS / 4], rb[MS / 4];
+  auto fetch = [&](int m0) {
+#pragma unroll
+    for (int q = 0; q < MS / 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int mm = idx >> 6, c = idx & 63;
+      const int m = m0 + mm;
+      const bool live = m < r1 && row_live(m, M, stack);
+      ra[q] = (live && n0 + c < N) ? A(m, n0 + c) : 0.0f;
+      rb[q] = (live && k0 + c < K) ? Bl(m, k0 + c) : 0.0f;
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int m0 = r0; m0 < r1; m0 += MS) {
+#pragma unroll
+    for (int q = 0; q < MS / 4; ++q) {
+      const int idx = tid + 256 * q;
+      As[idx >> 6][idx & 63] = ra[q];
+      Bs[idx >> 6][idx & 63] = rb[q];
+    }
+    __syncthreads();
+    if (m0 + MS < r1) fetch(m0 + MS);
+#pragma unroll
+    for (int s4 = 0; s4 < MS / 4; ++s4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[4 * s4 + lk][32 * wr + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[4 * s4 + lk][32 * wc + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  float* P = partial + (int64_t)slice * N * K;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * wr + 16 * i + 4 * lk + q;
+      if (n >= N) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + 32 * wc + 16 * j + lr;
+        if (k < K) P[(int64_t)n * K + k] = acc[i][j][q];
+      }
+    }
 }
 
 }  // namespace afm

@@ -845,7 +845,7 @@ static int wgrad(hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, AL
   slices = slices < 1 ? 1 : (slices > kMaxSlices ? kMaxSlices : slices);
   const int rps = ((rows + slices - 1) / slices + 15) / 16 * 16;
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)slices);
-  hipLaunchKernelGGL((k_wgrad<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
+  hipLaunchKernelGGL((k_wgrad_mfma<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
   hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for((int64_t)N * K, 256, 4096)), dim3(256), 0, st,
                      (const float*)partial, slices, N, K, gacc, off, env_c, env_l1);
   AFM_LAUNCH_CHECK();
@@ -898,14 +898,14 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                        m->W.tb[0], d.S, d.nb, d.tb[0], (float)d.r_cut, d.p, tbp0);
     AFM_LAUNCH_CHECK();
     for (int k = 1; k < d.ntb; ++k)
-      sgemm<true>(st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
+      sgemm<true, true>(st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
                   LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack},
                   EpSt{ws_ptr<float>(ws, L.so_tb_pre[k]), d.tb[k]}, stack);
     float* x0 = ws_ptr<float>(ws, L.so_x[0]);
     hipLaunchKernelGGL(k_tb2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack, d.w,
                        (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), (const float*)geo,
                        (const float*)geo2, x0);
-    sgemm<true>(st, rr, E2, d.w, env, m->W.env[0], d.w, LdPlain{x0, d.w}, EpSt{ws_ptr<float>(ws, L.so_omega[0]), env},
+    sgemm<true, true>(st, rr, E2, d.w, env, m->W.env[0], d.w, LdPlain{x0, d.w}, EpSt{ws_ptr<float>(ws, L.so_omega[0]), env},
                 stack);
     AFM_LAUNCH_CHECK();
     for (int layer = 1; layer <= d.NL; ++layer) {
@@ -930,10 +930,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       for (int k = 0; k < d.depth; ++k) {
         float* pre = ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k]);
         if (k == 0)
-          sgemm<true>(st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
+          sgemm<true, true>(st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
                       EpSt{pre, d.w}, stack);
         else
-          sgemm<true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
+          sgemm<true, true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
                       LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, EpSt{pre, d.w}, stack);
       }
       float* xn = ws_ptr<float>(ws, L.so_x[layer]);
@@ -941,7 +941,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                          d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), xp,
                          (const float*)geo, (const float*)geo2, xn);
       if (layer < d.NL)
-        sgemm<true>(st, rr, E2, d.w, env, m->W.env[layer], d.w, LdPlain{xn, d.w},
+        sgemm<true, true>(st, rr, E2, d.w, env, m->W.env[layer], d.w, LdPlain{xn, d.w},
                     EpSt{ws_ptr<float>(ws, L.so_omega[layer]), env}, stack);
       AFM_LAUNCH_CHECK();
     }
@@ -963,7 +963,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       const int ls = lp.n0e * d.c;
       const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
       if (layer < d.NL) {
-        sgemm<false>(st, rr, E2, env, d.w, m->W.env[layer], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+        sgemm<false, true>(st, rr, E2, env, d.w, m->W.env[layer], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
         snprintf(nm, sizeof nm, "layer%d.env", layer + 1);
         rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{ws_ptr<float>(ws, L.so_x[layer]), d.w},
                    partial, gacc, block_offset(m, nm), d.c, d.lmax + 1);
@@ -980,7 +980,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
           rc = wgrad(st, rr, stack, d.w, d.w, LdPlain{ga, d.w},
                      LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
+          sgemm<false, true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
           hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr,
                              stack, d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), gh, ga,
                              (const float*)geo, (const float*)geo2, 0, 1.0f, 0.0f);
@@ -989,7 +989,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
           rc = wgrad(st, rr, stack, d.w, d.w + ls, LdPlain{ga, d.w},
                      LdCat{xp, d.w, ws_ptr<float>(ws, L.so_s[layer - 1]), ls}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false>(st, rr, E2, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LdPlain{ga, d.w},
+          sgemm<false, true>(st, rr, E2, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LdPlain{ga, d.w},
                        EpSplit2{gx, d.w, gs2, ls}, stack);
           AFM_LAUNCH_CHECK();
         }
@@ -1017,7 +1017,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       // alpha shares are per atom (chunks do not overlap): reduced after the last chunk
     }
     // two-body reverse
-    sgemm<false>(st, rr, E2, env, d.w, m->W.env[0], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+    sgemm<false, true>(st, rr, E2, env, d.w, m->W.env[0], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
     rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{x0, d.w}, partial, gacc,
                block_offset(m, "layer1.env"), d.c, d.lmax + 1);
     if (rc) return rc;
@@ -1034,7 +1034,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
           rc = wgrad(st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
                      LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false>(st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+          sgemm<false, true>(st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
                        EpSt{gh, d.tb[k - 1]}, stack);
           hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.tb[k - 1], 256, 65536)), dim3(256), 0, st,
                              rr, stack, d.tb[k - 1], (const float*)ws_ptr<float>(ws, L.so_tb_pre[k - 1]), gh, ga,
