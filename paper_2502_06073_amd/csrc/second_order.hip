@@ -22,6 +22,7 @@
 
 #include <vector>
 
+#include "cg_ct.h"
 #include "device_util.h"
 #include "edge_layout.h"
 #include "gemm_f32.h"
@@ -319,25 +320,21 @@ struct LayerCT2 {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
 };
 
-template <int LMAX, int NL, int L, int C>
-__device__ __forceinline__ void build_M2(float* Ms, const float* gam, int n, int slot) {
-  constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
-  constexpr int NS = 256 / C;
-  static_for<0, LP.n_paths>([&](auto K) {
-    constexpr PathT pt = LP.p[decltype(K)::value];
-    constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
-    constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
-    if (decltype(K)::value % NS == slot) {
+// the products of one path over the CG nonzeros (compile-time tables):
+// T[m3] = sum C V[m1] G[m2] and its tangent Td = sum C (Vd G + V Gd)
+template <int LMAX, int NL, int L, int K>
+__device__ __forceinline__ void path2(const float* V, const float* Vd, const float* G, const float* Gd, float* T,
+                                      float* Td) {
+  constexpr PathT pt = LayerCT2<LMAX, NL, L>::lp.p[K];
+  constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
 #pragma unroll
-      for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-        for (int m3 = 0; m3 < d3; ++m3) {
-          float acc = 0.0f;
-#pragma unroll
-          for (int m2 = 0; m2 < d2; ++m2) acc += c_cg[off + (m1 * d2 + m2) * d3 + m3] * gam[(pt.l2 * pt.l2 + m2) * C + n];
-          Ms[(pt.m_off + m1 * d3 + m3) * C + n] = acc;
-        }
-    }
+  for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) { T[m3] = 0.0f; Td[m3] = 0.0f; }
+  static_for<0, nz.n>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    const float v = V[pt.in_off + nz.m1[q]], vd = Vd[pt.in_off + nz.m1[q]];
+    const float g = G[pt.l2 * pt.l2 + nz.m2[q]], gd = Gd[pt.l2 * pt.l2 + nz.m2[q]];
+    T[nz.m3[q]] += nz.c[q] * v * g;
+    Td[nz.m3[q]] += nz.c[q] * (vd * g + v * gd);
   });
 }
 
@@ -372,8 +369,6 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NS = 256 / C;
   constexpr int NCI = LP.n_in_comps, NCO = LP.n_out_comps > 0 ? LP.n_out_comps : 1;
-  __shared__ float Ms[LP.m_size * C];
-  __shared__ float Mds[LP.m_size * C];
   __shared__ float red[2 * NS * NLM * C];
   __shared__ float gam[NLM * C];
   __shared__ float gamd[NLM * C];
@@ -421,9 +416,9 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       a.gammad[(i * NLM + q) * C + n] = gd;
     }
     __syncthreads();
-    build_M2<LMAX, NL, L, C>(Ms, gam, n, slot);
-    build_M2<LMAX, NL, L, C>(Mds, gamd, n, slot);
-    __syncthreads();
+    float G[NLM], Gd[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) { G[q] = gam[q * C + n]; Gd[q] = gamd[q * C + n]; }
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0, ts = a.stack + t;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
@@ -436,21 +431,9 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       static_for<0, LP.n_paths>([&](auto K) {
         constexpr int k = decltype(K)::value;
         constexpr PathT pt = LP.p[k];
-        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        constexpr int d3 = 2 * pt.l3 + 1;
         float T[d3], Td[d3];
-#pragma unroll
-        for (int m3 = 0; m3 < d3; ++m3) {
-          float v = 0.0f, vd = 0.0f;
-#pragma unroll
-          for (int m1 = 0; m1 < d1; ++m1) {
-            const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
-            const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
-            v += V[pt.in_off + m1] * mm;
-            vd += Vd[pt.in_off + m1] * mm + V[pt.in_off + m1] * mmd;
-          }
-          T[m3] = v;
-          Td[m3] = vd;
-        }
+        path2<LMAX, NL, L, k>(V, Vd, G, Gd, T, Td);
         if constexpr (pt.s_idx >= 0) {
           a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
           a.s[(ts * LP.n0e + pt.s_idx) * C + n] = Td[0];
@@ -482,29 +465,22 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NS = 256 / C;
   constexpr int NCI = LP.n_in_comps;
-  constexpr int MS = LP.m_size;
   constexpr int NP = LP.n_paths;
-  constexpr int MAXB = 25;
-  __shared__ float Ms[MS * C];
-  __shared__ float Mds[MS * C];
-  __shared__ float red[NS * MAXB * C];
-  __shared__ float gg[2 * NLM * C];   // Gamma, then dJ/dGamma and dJ/dGamma_dot
+  __shared__ float red[NS * 2 * NLM * C];
+  __shared__ float gg[2 * NLM * C];   // dJ/dGamma and dJ/dGamma_dot
   const int n = threadIdx.x % C, slot = threadIdx.x / C;
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
   for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
     const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
-    for (int q = slot; q < NLM; q += NS) {
-      gg[q * C + n] = a.gamma[(i * NLM + q) * C + n];
-      gg[(NLM + q) * C + n] = a.gammad[(i * NLM + q) * C + n];
-    }
-    __syncthreads();
-    build_M2<LMAX, NL, L, C>(Ms, gg, n, slot);
-    build_M2<LMAX, NL, L, C>(Mds, gg + NLM * C, n, slot);
-    __syncthreads();
-    float GM[MS], GMd[MS], ga[NP];
+    float G[NLM], Gd[NLM], GG[NLM], GGd[NLM], ga[NP];
 #pragma unroll
-    for (int q = 0; q < MS; ++q) { GM[q] = 0.0f; GMd[q] = 0.0f; }
+    for (int q = 0; q < NLM; ++q) {
+      G[q] = a.gamma[(i * NLM + q) * C + n];
+      Gd[q] = a.gammad[(i * NLM + q) * C + n];
+      GG[q] = 0.0f;
+      GGd[q] = 0.0f;
+    }
 #pragma unroll
     for (int q = 0; q < NP; ++q) ga[q] = 0.0f;
     for (int64_t e = eb + slot; e < ee; e += NS) {
@@ -518,7 +494,8 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
       static_for<0, NP>([&](auto K) {
         constexpr int k = decltype(K)::value;
         constexpr PathT pt = LP.p[k];
-        constexpr int d1 = 2 * pt.l1 + 1, d3 = 2 * pt.l3 + 1;
+        constexpr int d3 = 2 * pt.l3 + 1;
+        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
         float GT[d3], GTd[d3];
 #pragma unroll
         for (int m3 = 0; m3 < d3; ++m3) { GT[m3] = 0.0f; GTd[m3] = 0.0f; }
@@ -528,36 +505,29 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
         }
         if constexpr (pt.out_off >= 0) {
           const float al = a.alpha[k * C + n];
+          float T[d3], Td[d3];
+          path2<LMAX, NL, L, k>(V, Vd, G, Gd, T, Td);
           float gal = 0.0f;
 #pragma unroll
           for (int m3 = 0; m3 < d3; ++m3) {
             const float gvo = a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
             const float gvod = a.gvout[(ts * LP.n_out_comps + pt.out_off + m3) * C + n];
-            float T = 0.0f, Td = 0.0f;
-#pragma unroll
-            for (int m1 = 0; m1 < d1; ++m1) {
-              const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
-              const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
-              T += V[pt.in_off + m1] * mm;
-              Td += Vd[pt.in_off + m1] * mm + V[pt.in_off + m1] * mmd;
-            }
-            gal += gvo * T + gvod * Td;
+            gal += gvo * T[m3] + gvod * Td[m3];
             GT[m3] += al * gvo;
             GTd[m3] += al * gvod;
           }
           ga[k] += gal;
         }
-#pragma unroll
-        for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-          for (int m3 = 0; m3 < d3; ++m3) {
-            const float mm = Ms[(pt.m_off + m1 * d3 + m3) * C + n];
-            const float mmd = Mds[(pt.m_off + m1 * d3 + m3) * C + n];
-            GV[pt.in_off + m1] += mm * GT[m3] + mmd * GTd[m3];
-            GVd[pt.in_off + m1] += mm * GTd[m3];
-            GM[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GT[m3] + Vd[pt.in_off + m1] * GTd[m3];
-            GMd[pt.m_off + m1 * d3 + m3] += V[pt.in_off + m1] * GTd[m3];
-          }
+        // adjoints of T = C (V x G) and Td = C (Vd x G + V x Gd)
+        static_for<0, nz.n>([&](auto Q) {
+          constexpr int q = decltype(Q)::value;
+          constexpr int i1 = pt.in_off + nz.m1[q], i2 = pt.l2 * pt.l2 + nz.m2[q], i3 = nz.m3[q];
+          const float cgt = nz.c[q] * GT[i3], cgd = nz.c[q] * GTd[i3];
+          GV[i1] += cgt * G[i2] + cgd * Gd[i2];
+          GVd[i1] += cgd * G[i2];
+          GG[i2] += cgt * V[i1] + cgd * Vd[i1];
+          GGd[i2] += cgd * V[i1];
+        });
       });
       if constexpr (L > 1) {
 #pragma unroll
@@ -580,25 +550,20 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
         }
       }
     }
-    // reduce dJ/dM and dJ/dM_dot over slots, path by path, into Ms / Mds
+    // dJ/dGamma and dJ/dGamma_dot summed over the slots, scaled by nbar^-1/2
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      red[(slot * 2 * NLM + q) * C + n] = GG[q];
+      red[(slot * 2 * NLM + NLM + q) * C + n] = GGd[q];
+    }
     __syncthreads();
-    static_for<0, NP>([&](auto K) {
-      constexpr PathT pt = LP.p[decltype(K)::value];
-      constexpr int blk = (2 * pt.l1 + 1) * (2 * pt.l3 + 1);
+    for (int q = slot; q < 2 * NLM; q += NS) {
+      float v = 0.0f;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int q = 0; q < blk; ++q) red[(slot * MAXB + q) * C + n] = h ? GMd[pt.m_off + q] : GM[pt.m_off + q];
-        __syncthreads();
-        for (int q = slot; q < blk; q += NS) {
-          float v = 0.0f;
-#pragma unroll
-          for (int s = 0; s < NS; ++s) v += red[(s * MAXB + q) * C + n];
-          (h ? Mds : Ms)[(pt.m_off + q) * C + n] = v;
-        }
-        __syncthreads();
-      }
-    });
+      for (int s2 = 0; s2 < NS; ++s2) v += red[(s2 * 2 * NLM + q) * C + n];
+      gg[q * C + n] = v * a.inv_sqrt_nbar;
+    }
+    __syncthreads();
     // alpha-gradient shares of this atom
     if constexpr (L < NL) {
       static_for<0, NP>([&](auto K) {
@@ -614,29 +579,6 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
         __syncthreads();
       });
     }
-    // dJ/dGamma = C^T dJ/dM, dJ/dGamma_dot = C^T dJ/dM_dot (scaled)
-    for (int q = slot; q < NLM; q += NS) {
-      float g = 0.0f, gd = 0.0f;
-      static_for<0, NP>([&](auto K) {
-        constexpr PathT pt = LP.p[decltype(K)::value];
-        constexpr int d1 = 2 * pt.l1 + 1, d2 = 2 * pt.l2 + 1, d3 = 2 * pt.l3 + 1;
-        constexpr int off = cg_offset(pt.l1, pt.l2, pt.l3);
-        const int m2 = q - pt.l2 * pt.l2;
-        if (m2 >= 0 && m2 < d2) {
-#pragma unroll
-          for (int m1 = 0; m1 < d1; ++m1)
-#pragma unroll
-            for (int m3 = 0; m3 < d3; ++m3) {
-              const float cgv = c_cg[off + (m1 * d2 + m2) * d3 + m3];
-              g += cgv * Ms[(pt.m_off + m1 * d3 + m3) * C + n];
-              gd += cgv * Mds[(pt.m_off + m1 * d3 + m3) * C + n];
-            }
-        }
-      });
-      gg[q * C + n] = g * a.inv_sqrt_nbar;
-      gg[(NLM + q) * C + n] = gd * a.inv_sqrt_nbar;
-    }
-    __syncthreads();
     // Gamma = sum omega (x) Y;  Gamma_dot = sum omega_dot (x) Y + omega (x) Y_dot
     for (int64_t e = eb + slot; e < ee; e += NS) {
       const int64_t t = e - e0, ts = a.stack + t;
