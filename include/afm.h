@@ -256,7 +256,7 @@ int afm_energy_forces(const afm_model* model, const afm_system* sys, const afm_n
  * weight layout, overwritten).  A NULL grad_e_struct, grad_forces or
  * grad_virial stands for zeros.  (A stress sigma_s = W_s / V_s enters as
  * gW_s = g_sigma_s / V_s.)  Needs a workspace planned
- * with with_second_order = 1; runs in FP32 on the vector ALUs with FP64
+ * with with_second_order = 1; runs in FP32 (GEMMs on FP32 MFMA) with FP64
  * accumulation of the weight gradients (deterministic).  grad_pos must be
  * NULL (position gradients are not built). */
 int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,

@@ -12,8 +12,10 @@
 // the primal rows, so each GEMM serves both), then J is reversed with
 // respect to the weights through primal and tangent together.  Basis and
 // spherical harmonics (and their tangents) do not depend on the weights, so
-// no second derivatives of the geometry are needed.  Everything runs in FP32
-// on the vector ALUs; weight gradients are reduced in fixed-order slices and
+// no second derivatives of the geometry are needed.  Everything runs in FP32:
+// the GEMMs and weight-gradient reductions on the matrix cores
+// (v_mfma_f32_16x16x4f32), the tensor products on the vector ALUs over the
+// CG nonzeros; weight gradients are reduced in fixed-order slices and
 // accumulated in FP64 (deterministic).  Chunks of rows are exact (E_i and
 // Edot_i depend only on row i).
 #include <hip/hip_runtime.h>
