@@ -542,6 +542,10 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   float ep[NCBW];
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) ep[cb] = 0.0f;
+  // x^{L-1} of the pair's rows, loaded after the last layer's MFMAs and
+  // before its epilogue stores (a load behind a store the compiler cannot
+  // prove disjoint waits for its own round trip: 8 serialised per pair)
+  f32x4 xpf[2][NCBW];
   // epilogue of latent layer k: SiLU, or the residual update after the last
   auto epi = [&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -553,7 +557,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
       } else {
         const int64_t t = col_t(cb);
         const bool valid = t < M;
-        const f32x4 xp = valid ? ld4(a.xprev + t * W + 16 * rb + 4 * g) : zero4();
+        const f32x4 xp = xpf[rb & 1][cb];
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = (xp[q] + u[cb] * v[q] * sigm(v[q])) * r2;
         if constexpr (!LAST) {
@@ -578,6 +582,17 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[1], acc, half, lane);
   }
   __syncthreads();
+  if constexpr (DEPTH == 1) {
+    if (mine) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NCBW; ++cb) {
+          const int64_t t = col_t(cb);
+          xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
+        }
+    }
+  }
   if (mine)
     finish_pair(pair, acc, (LAST && DEPTH == 1) ? nullptr : S.act[0], epi(std::integral_constant<int, 0>{}),
                 half, lane);
@@ -588,6 +603,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     if (mine) {
       zero_acc(acc);
       mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, half, lane);
+      if constexpr (k == DEPTH - 1) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int cb = 0; cb < NCBW; ++cb) {
+            const int64_t t = col_t(cb);
+            xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
+          }
+      }
       finish_pair(pair, acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(K), half, lane);
     }
     __syncthreads();
