@@ -147,8 +147,6 @@ inline T* ws_ptr(const afm_workspace* ws, int64_t off) {
 int pack_weights(afm_model* m, const double* w);   // weights.cpp
 
 // ---- kernel launchers (defined in the .hip files) ----
-int upload_cg_table(const float* host_table);                // tp_kernels.hip
-int upload_cg_table_second_order(const float* host_table);   // second_order.hip
 
 struct SysDev {
   int64_t N, B;

@@ -204,21 +204,6 @@ static bool cg_tables_agree() {
   return true;
 }
 
-static std::vector<float> cg_table_f32() {
-  std::vector<float> t(cg_table_size(), 0.f);
-  double buf[125];
-  for (int a = 0; a <= kMaxLmax; ++a)
-    for (int b = 0; b <= kMaxLmax; ++b)
-      for (int c = abs(a - b); c <= a + b && c <= kMaxLmax + kMaxLmax; ++c) {
-        int off = cg_offset(a, b, c);
-        if (off < 0) continue;
-        real_cg(a, b, c, buf);
-        int n = (2 * a + 1) * (2 * b + 1) * (2 * c + 1);
-        for (int q = 0; q < n; ++q) t[off + q] = (float)buf[q];
-      }
-  return t;
-}
-
 // ----------------------------------------------------------------------------
 // workspace layout
 
@@ -411,10 +396,6 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
     delete m;
     return AFM_E_INVALID;
   }
-  std::vector<float> cg = cg_table_f32();
-  rc = upload_cg_table(cg.data());
-  if (!rc) rc = upload_cg_table_second_order(cg.data());
-  if (rc) { (void)hipFree(m->dev_mem); delete m; return rc; }
   *out = m;
   return AFM_OK;
 }

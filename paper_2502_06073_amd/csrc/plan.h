@@ -32,8 +32,6 @@ struct PathT {
   int in_off = 0;    // component offset of (l1,p1) in the input features
   int out_off = -1;  // component offset of (l3,p3) in the output features (-1: none)
   int s_idx = -1;    // index among the layer's (0,+) paths (-1: not a scalar path)
-  int m_off = 0;     // offset of this path's [2l1+1][2l3+1] block in the
-                     // per-atom precontracted environment
 };
 
 struct LayerPlan {
@@ -48,7 +46,6 @@ struct LayerPlan {
   int out_off[kMaxIrreps] = {};
   int n_out_comps = 0;
   int n0e = 0;       // number of (0,+) paths = scalars per channel fed to the MLP
-  int m_size = 0;    // sum over paths of (2l1+1)(2l3+1)
 };
 
 struct Plan {
@@ -147,7 +144,7 @@ constexpr Plan make_plan(int lmax, int n_layers) {
     lp.n_out_comps = 0;
     for (int k = 0; k < lp.n_out; ++k) lp.n_out_comps += 2 * lp.out[k].l + 1;
     lp.n_paths = nfull[L];
-    int s = 0, moff = 0;
+    int s = 0;
     for (int k = 0; k < nfull[L]; ++k) {
       PathT t = full[L][k];
       for (int q = 0; q < lp.n_in; ++q)
@@ -156,38 +153,13 @@ constexpr Plan make_plan(int lmax, int n_layers) {
       for (int q = 0; q < lp.n_out; ++q)
         if (lp.out[q].l == t.l3 && lp.out[q].p == t.p3) t.out_off = lp.out_off[q];
       t.s_idx = (t.l3 == 0 && t.p3 == 1) ? s++ : -1;
-      t.m_off = moff;
-      moff += (2 * t.l1 + 1) * (2 * t.l3 + 1);
       lp.p[k] = t;
     }
     lp.n0e = s;
-    lp.m_size = moff;
     in_mask = out_mask;
   }
   P.ok = true;
   return P;
-}
-
-// Offsets of the dense real Clebsch-Gordan tensors C^{l1 l2 l3}[m1][m2][m3]
-// (l <= 2) inside one flat table, in (l1, l2, l3) lexicographic order.
-constexpr int cg_offset(int l1, int l2, int l3) {
-  int off = 0;
-  for (int a = 0; a <= kMaxLmax; ++a)
-    for (int b = 0; b <= kMaxLmax; ++b)
-      for (int c = 0; c <= kMaxLmax; ++c) {
-        if (c < iabs(a - b) || c > a + b) continue;
-        if (a == l1 && b == l2 && c == l3) return off;
-        off += (2 * a + 1) * (2 * b + 1) * (2 * c + 1);
-      }
-  return -1;
-}
-constexpr int cg_table_size() {
-  int off = 0;
-  for (int a = 0; a <= kMaxLmax; ++a)
-    for (int b = 0; b <= kMaxLmax; ++b)
-      for (int c = 0; c <= kMaxLmax; ++c)
-        if (c >= iabs(a - b) && c <= a + b) off += (2 * a + 1) * (2 * b + 1) * (2 * c + 1);
-  return off;
 }
 
 template <int LMAX, int NL>

@@ -308,15 +308,6 @@ struct TP2Args {
   float* galpha;         // [N][n_paths][C] per-atom alpha-gradient shares
 };
 
-// this translation unit's copy of the CG table (device symbols are per unit)
-__constant__ float c_cg[cg_table_size()];
-
-int upload_cg_table_second_order(const float* host_table) {
-  AFM_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_cg), host_table, sizeof(float) * cg_table_size(), 0,
-                                  hipMemcpyHostToDevice));
-  return AFM_OK;
-}
-
 template <int LMAX, int NL, int L>
 struct LayerCT2 {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];

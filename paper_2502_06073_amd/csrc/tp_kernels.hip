@@ -26,14 +26,6 @@
 
 namespace afm {
 
-__constant__ float c_cg[cg_table_size()];
-
-int upload_cg_table(const float* host_table) {
-  AFM_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_cg), host_table, sizeof(float) * cg_table_size(), 0,
-                                  hipMemcpyHostToDevice));
-  return AFM_OK;
-}
-
 
 __device__ __forceinline__ uint16_t to_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 // element i of a float (B16 false) or bf16 (B16 true) array
