@@ -109,7 +109,6 @@ struct WsLayout {
   int64_t x[kMaxLayers + 1] = {};            // float [CEX][w]  x^0..x^{NL-1}
   int64_t omega[kMaxLayers] = {};            // float [CEX][(lmax+1)c]
   int64_t s[kMaxLayers] = {};                // float [CEX][n0e c]
-  int64_t v[kMaxLayers] = {};                // float [CEX][ncomp c] (V^1..V^{NL-1})
   int64_t lat_pre[kMaxLayers][kMaxDepth] = {};  // float [CEX][w] (BF16 path: bf16)
   int64_t gx = 0, gt0 = 0, gt1 = 0;          // float [CEX][max(w, w+n0e c)]
   int64_t gs[kMaxLayers] = {};               // float [CEX][n0e c] dE/ds^L per layer
