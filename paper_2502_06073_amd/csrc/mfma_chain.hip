@@ -4,14 +4,14 @@
 // two-body latent MLP, "embedding MLP ... linear projection", latent MLP,
 // SiLU), forward and adjoint.
 //
-// Mapping.  A workgroup of 8 wavefronts owns a tile of 128 edges (8 column
+// Mapping.  A workgroup of 8 wavefronts owns a tile of 64 edges (4 column
 // blocks of 16).  Each layer is computed transposed, Y^T = W X^T: the
 // weights are the MFMA A operand (16 output features x 32 input features
 // per fragment), the edges the B/C columns.  The tile's activations live in
 // LDS as bf16 B fragments (two ping-pong buffers), written once by the
 // wavefront that computed them and read by all eight; each wavefront owns
 // pairs of 16-row output blocks and streams its own weight fragments from
-// L2 into registers, so a weight byte is fetched once per 128 edges and an
+// L2 into registers, so a weight byte is fetched once per 64 edges and an
 // LDS fragment feeds 2 x (rows per wavefront) MFMAs.  One barrier per layer.
 // A C block's lane group g holds output features 4g..4g+3, so the pair of
 // blocks (2p, 2p+1) packs into the B fragment of k-block p of the next layer
