@@ -154,45 +154,74 @@ __global__ void __launch_bounds__(256) k_edge_energy(RowRange rr, const float* _
   }
 }
 
+// Per-atom row reductions run on groups of kRowLanes consecutive lanes, one
+// group per atom: the lanes of a group read consecutive edges of the row
+// (coalesced), and a row of ~70 edges takes ~5 steps instead of ~70, so
+// even a 10^4-atom system fills the chip.
+constexpr int kRowLanes = 16;
+constexpr int kRowBlock = 256;
+
+// Sum over a lane group (butterfly: every lane of the group ends with the
+// same bits, and the order is fixed, so the result repeats run to run)
+__device__ __forceinline__ double row_group_sum(double v) {
+#pragma unroll
+  for (int o = kRowLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // E_i = sigma_Z energy_scale sum_{row i} eps_e + mu_Z (float64)
-__global__ void k_atom_energy(const int64_t* __restrict__ row_ptr, int64_t N, int64_t capacity,
-                              const float* __restrict__ eps, const int32_t* __restrict__ species, int n_species,
-                              const double* __restrict__ sc, const double* __restrict__ sh, double escale,
-                              double* __restrict__ e_atom, int32_t* status) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__global__ void __launch_bounds__(kRowBlock) k_atom_energy(const int64_t* __restrict__ row_ptr, int64_t N,
+                                                           int64_t capacity, const float* __restrict__ eps,
+                                                           const int32_t* __restrict__ species, int n_species,
+                                                           const double* __restrict__ sc,
+                                                           const double* __restrict__ sh, double escale,
+                                                           double* __restrict__ e_atom, int32_t* status) {
+  const int64_t i = (blockIdx.x * (int64_t)kRowBlock + threadIdx.x) / kRowLanes;
+  const int sub = threadIdx.x % kRowLanes;
+  if (i >= N) return;   // uniform over the lane group
   const int zi = species[i];
   if (row_ptr[N] > capacity || zi < 0 || zi >= n_species) {
-    if (zi < 0 || zi >= n_species) atomicOr(status, AFM_FLAG_SPECIES);
-    e_atom[i] = __longlong_as_double(0x7ff8000000000000LL);
+    if (sub == 0) {
+      if (zi < 0 || zi >= n_species) atomicOr(status, AFM_FLAG_SPECIES);
+      e_atom[i] = __longlong_as_double(0x7ff8000000000000LL);
+    }
     return;
   }
   double acc = 0.0;
-  for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += (double)eps[e];
-  const int z = species[i];
-  e_atom[i] = sc[z] * escale * acc + sh[z];
+  for (int64_t e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += kRowLanes) acc += (double)eps[e];
+  acc = row_group_sum(acc);
+  if (sub == 0) e_atom[i] = sc[zi] * escale * acc + sh[zi];
 }
 
-// per-structure sums of per-atom values (fixed-order tree per block)
+// per-structure sums of per-atom values: strided per-thread sums, a
+// butterfly per wavefront, then the wavefront partials in order (fixed
+// order throughout)
+constexpr int kSumBlock = 1024;
 template <int W>
-__global__ void __launch_bounds__(256) k_struct_sum(const int64_t* __restrict__ seg, const double* __restrict__ v,
-                                                    double* __restrict__ out) {
-  __shared__ double part[256 * W];
+__global__ void __launch_bounds__(kSumBlock) k_struct_sum(const int64_t* __restrict__ seg,
+                                                          const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double part[kSumBlock / 64][W];
   const int64_t s = blockIdx.x;
   const int64_t a = seg[s], b = seg[s + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double acc[W];
+#pragma unroll
   for (int q = 0; q < W; ++q) acc[q] = 0.0;
-  for (int64_t i = a + threadIdx.x; i < b; i += 256)
+  for (int64_t i = a + threadIdx.x; i < b; i += kSumBlock)
+#pragma unroll
     for (int q = 0; q < W; ++q) acc[q] += v[i * W + q];
-  for (int q = 0; q < W; ++q) part[threadIdx.x * W + q] = acc[q];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off)
-      for (int q = 0; q < W; ++q) part[threadIdx.x * W + q] += part[(threadIdx.x + off) * W + q];
-    __syncthreads();
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+    if (lane == 0) part[wave][q] = acc[q];
   }
-  if (threadIdx.x == 0)
-    for (int q = 0; q < W; ++q) out[s * W + q] = part[q];
+  __syncthreads();
+  if (threadIdx.x < W) {
+    double t = 0.0;
+    for (int w = 0; w < kSumBlock / 64; ++w) t += part[w][threadIdx.x];
+    out[s * W + threadIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,18 +319,22 @@ __global__ void k_geometry_bwd(RowRange rr, const float* __restrict__ geo, const
 }
 
 // F_i = sum_{e in row i} (g_e - g_rev(e));  W_i = -sum_{e in row i} g_e delta_e^T
-__global__ void k_force_scatter(const double* __restrict__ pos, const double* __restrict__ cell,
+// (one lane group per atom)
+__global__ void __launch_bounds__(kRowBlock) k_force_scatter(const double* __restrict__ pos, const double* __restrict__ cell,
                                 const uint8_t* __restrict__ pbc, const int64_t* __restrict__ seg, int64_t B,
                                 const int64_t* __restrict__ row_ptr, int64_t N, const int32_t* __restrict__ col,
                                 const int8_t* __restrict__ shift, const int32_t* __restrict__ rev,
                                 const float* __restrict__ g, int64_t capacity, double* __restrict__ forces,
                                 double* __restrict__ wat) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int64_t i = (blockIdx.x * (int64_t)kRowBlock + threadIdx.x) / kRowLanes;
+  const int sub = threadIdx.x % kRowLanes;
+  if (i >= N) return;   // uniform over the lane group
   if (row_ptr[N] > capacity) {
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    if (forces) for (int q = 0; q < 3; ++q) forces[3 * i + q] = nan;
-    if (wat) for (int q = 0; q < 9; ++q) wat[9 * i + q] = nan;
+    if (sub == 0) {
+      if (forces) for (int q = 0; q < 3; ++q) forces[3 * i + q] = nan;
+      if (wat) for (int q = 0; q < 9; ++q) wat[9 * i + q] = nan;
+    }
     return;
   }
   int64_t sl = 0, sh = B;
@@ -312,7 +345,7 @@ __global__ void k_force_scatter(const double* __restrict__ pos, const double* __
   const bool per = pbc[sl] != 0;
   const double* h = cell + 9 * sl;
   double F[3] = {0, 0, 0}, Wv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+  for (int64_t e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += kRowLanes) {
     const int64_t j = col[e], r = rev[e];
     float ge[3] = {g[3 * e], g[3 * e + 1], g[3 * e + 2]};
     double d[3];
@@ -331,6 +364,12 @@ __global__ void k_force_scatter(const double* __restrict__ pos, const double* __
       for (int p = 0; p < 3; ++p) Wv[q * 3 + p] -= (double)ge[q] * d[p];
     }
   }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) F[q] = row_group_sum(F[q]);
+  if (wat)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Wv[q] = row_group_sum(Wv[q]);
+  if (sub != 0) return;
   if (forces)
     for (int q = 0; q < 3; ++q) forces[3 * i + q] = F[q];
   if (wat)
@@ -618,11 +657,11 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
 int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                     const WsLayout& L, double* e_atom, double* e_struct, hipStream_t st) {
   TraceScope tr(st, "energy");
-  hipLaunchKernelGGL(k_atom_energy, dim3(grid_for(s.N, 256)), dim3(256), 0, st, (const int64_t*)nl.row_ptr, s.N,
+  hipLaunchKernelGGL(k_atom_energy, dim3(grid_for(s.N * kRowLanes, kRowBlock)), dim3(kRowBlock), 0, st, (const int64_t*)nl.row_ptr, s.N,
                      nl.capacity, (const float*)ws_ptr<float>(ws, L.eps), s.species, m->dims.S, m->W.sp_scale,
                      m->W.sp_shift, m->dims.escale, e_atom, nl.status);
   if (e_struct)
-    hipLaunchKernelGGL(k_struct_sum<1>, dim3((unsigned)s.B), dim3(256), 0, st, s.seg, (const double*)e_atom,
+    hipLaunchKernelGGL(k_struct_sum<1>, dim3((unsigned)s.B), dim3(kSumBlock), 0, st, s.seg, (const double*)e_atom,
                        e_struct);
   AFM_LAUNCH_CHECK();
   return AFM_OK;
@@ -632,11 +671,11 @@ int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl, cons
                       const WsLayout& L, double* forces, double* virial, hipStream_t st) {
   TraceScope tr(st, "force_scatter");
   double* wat = virial ? ws_ptr<double>(ws, L.atom_virial) : nullptr;
-  hipLaunchKernelGGL(k_force_scatter, dim3(grid_for(s.N, 128)), dim3(128), 0, st, s.pos, s.cell, s.pbc, s.seg,
+  hipLaunchKernelGGL(k_force_scatter, dim3(grid_for(s.N * kRowLanes, kRowBlock)), dim3(kRowBlock), 0, st, s.pos, s.cell, s.pbc, s.seg,
                      s.B, (const int64_t*)nl.row_ptr, s.N, (const int32_t*)nl.col, (const int8_t*)nl.shift,
                      (const int32_t*)nl.rev, (const float*)ws_ptr<float>(ws, L.g), nl.capacity, forces, wat);
   if (virial)
-    hipLaunchKernelGGL(k_struct_sum<9>, dim3((unsigned)s.B), dim3(256), 0, st, s.seg, (const double*)wat, virial);
+    hipLaunchKernelGGL(k_struct_sum<9>, dim3((unsigned)s.B), dim3(kSumBlock), 0, st, s.seg, (const double*)wat, virial);
   AFM_LAUNCH_CHECK();
   return AFM_OK;
 }

@@ -383,19 +383,19 @@ __global__ void __launch_bounds__(256) k_row_sort(const int64_t* __restrict__ se
   }
 }
 
-__global__ void k_rev(const int64_t* __restrict__ row_ptr, int64_t N, int64_t capacity,
-                      const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
-                      int32_t* __restrict__ rev, int32_t* status) {
+// rev[e] of every edge e = (i, j, n): the slot of (j, i, -n) in row j (a
+// binary search of the sorted row).  One group of kRevLanes lanes per row i.
+constexpr int kRevLanes = 16;
+__global__ void __launch_bounds__(256) k_rev(const int64_t* __restrict__ row_ptr, int64_t N, int64_t capacity,
+                                             const int32_t* __restrict__ col, const int8_t* __restrict__ shift,
+                                             int32_t* __restrict__ rev, int32_t* status) {
   const int64_t E = row_ptr[N];
   if (E > capacity) return;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = N;   // row_ptr[lo] <= e < row_ptr[hi]
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (row_ptr[mid] <= e) lo = mid; else hi = mid;
-    }
-    const int32_t i = (int32_t)lo, j = col[e];
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kRevLanes;
+  if (row >= N) return;
+  const int32_t i = (int32_t)row;
+  for (int64_t e = row_ptr[i] + threadIdx.x % kRevLanes; e < row_ptr[i + 1]; e += kRevLanes) {
+    const int32_t j = col[e];
     const int8_t nn[3] = {(int8_t)-shift[3 * e], (int8_t)-shift[3 * e + 1], (int8_t)-shift[3 * e + 2]};
     const uint64_t want = edge_key(i, nn);
     int64_t a = row_ptr[j], b = row_ptr[j + 1];   // search [a, b)
@@ -652,8 +652,8 @@ int launch_build_neighbors(const SysDev& s, double r_list, const NlDev& nl, cons
                      nl.capacity, nl.col, nl.shift, nl.status, (int)ws->max_row);
   hipLaunchKernelGGL(k_row_sort, dim3(nblk(N, 4)), dim3(256), 0, st, s.seg, N, B, (const StructMeta*)meta,
                      (const int64_t*)nl.row_ptr, nl.capacity, nl.col, nl.shift);
-  hipLaunchKernelGGL(k_rev, dim3(2048), dim3(256), 0, st, (const int64_t*)nl.row_ptr, N, nl.capacity,
-                     (const int32_t*)nl.col, (const int8_t*)nl.shift, nl.rev, nl.status);
+  hipLaunchKernelGGL(k_rev, dim3(nblk(N, 256 / kRevLanes)), dim3(256), 0, st, (const int64_t*)nl.row_ptr, N,
+                     nl.capacity, (const int32_t*)nl.col, (const int8_t*)nl.shift, nl.rev, nl.status);
   AFM_LAUNCH_CHECK();
   return AFM_OK;
 }
