@@ -667,22 +667,18 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     return ce;
   };
   // head: x^L = (x^{L-1} + u silu(a_D)) / sqrt 2; v = dE/dx^L on entry.  The
-  // residual share r2 v of dE/dx^{L-1} is parked in gx, except in the last
-  // layer, where it is rebuilt from w_eff at the end
+  // residual share r2 v of dE/dx^{L-1} is not kept: the last layer rebuilds
+  // it from w_eff at the end, the others from the stored part of gx (left
+  // in place) and the environment product, formed again there
   auto head = [&](int rb, int cb, f32x4& v) {
-    const int64_t t = col_t(cb);
     const f32x4 pa = ld_pre(a.pre[DEPTH - 1], tile, RBW, rb, cbA(cb), lane);
-    f32x4 res;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float gs_ = v[q] * r2;
       const float sg = sigm(pa[q]);
-      res[q] = gs_;
       gu[cb] += gs_ * pa[q] * sg;
       v[q] = gs_ * u[cb] * sg * (1.0f + pa[q] * (1.0f - sg));
     }
-    if constexpr (!LAST)
-      if (t < M) st4(a.gx + t * W + 16 * rb + 4 * g, res);
   };
   if constexpr (LAST) {
     // dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff
@@ -743,29 +739,57 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     __syncthreads();
     cur ^= 1;
   });
-  // dE/d[x | s] = W_1^T ga_1: x rows added to the residual share, s rows stored
-  layer_lds<cdiv(W + KS, 32), KBX, kSplitBwd>(
-      a.latb[0], S.act[cur], nullptr,
-      [&](int rb, int cb, f32x4& v) {
-        const int64_t t = col_t(cb);
-        if (t >= M) return;
-        if (rb < RBW) {
-          float* p = a.gx + t * W + 16 * rb + 4 * g;
-          f32x4 res;
-          if constexpr (LAST) {
-            const float ce = edge_coef(cb);
-            const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+  // dE/d[x | s] = W_1^T ga_1: x rows added to the residual share, s rows
+  // stored.  Not in the last layer, the x rows' accumulators start from
+  // r2 W_env^T dE/domega (dE/domega staged again into the free buffer), and
+  // the epilogue adds r2 x the stored part of gx.
+  if constexpr (!LAST) {
+    stage_rows_bf16<ENV>(S.act[cur ^ 1], a.gomega, tile, M, tid);
+    __syncthreads();
+  }
+  // a fresh copy of the tile index, so that the compiler forms the edge
+  // indices and addresses anew here instead of keeping the head's 64-bit
+  // ones live (spilled) across the whole chain
+  int64_t tile_o = tile;
+  asm volatile("" : "+s"(tile_o));
+  auto out_epi = [&](int rb, int cb, f32x4& v) {
+    const int64_t t = tile_o * TILE + 16 * cbA(cb) + (lane & 15);
+    if (t >= M) return;
+    if (rb < RBW) {
+      float* p = a.gx + t * W + 16 * rb + 4 * g;
+      f32x4 res;
+      if constexpr (LAST) {
+        const float ce = edge_coef(cb);
+        const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) res[q] = (ce * we[q]) * r2;
-          } else {
-            res = ld4(p);
-          }
-          st4(p, res + v);
-        } else if (16 * (rb - RBW) < KS) {
-          st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
+        for (int q = 0; q < 4; ++q) res[q] = (ce * we[q]) * r2;
+      } else {
+        res = ld4(p) * r2;
+      }
+      st4(p, res + v);
+    } else if (16 * (rb - RBW) < KS) {
+      st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
+    }
+  };
+  constexpr int NPO = cdiv(W + KS, 32);
+  static_for<0, cdiv(NPO, NPS)>([&](auto P) __attribute__((always_inline)) {
+    const int p = decltype(P)::value * NPS + pslot;
+    if (p < NPO) {
+      f32x4 acc[2][NCBW];
+      zero_acc(acc);
+      if constexpr (!LAST) {
+        if (p < NPW) {
+          mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, p, 0, S.act[cur ^ 1], acc, half, lane);
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < NCBW; ++c) acc[r][c] *= r2;
         }
-      },
-      pslot, half, lane);
+      }
+      mma_pair<KBX, KBX, kSplitBwd>(a.latb[0], p, 0, S.act[cur], acc, half, lane);
+      finish_pair(p, acc, nullptr, out_epi, half, lane);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
