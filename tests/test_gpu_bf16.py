@@ -67,6 +67,22 @@ def test_bf16_matches_fp32_structure():
     assert rel < 0.03
 
 
+def test_bf16_matches_fp32_dense_rows():
+    """Rows of ~200 edges (three times the headline lattice's): the
+    per-atom tensor-product kernels loop several times over their edge
+    slots and the per-row reductions over several lane-group steps."""
+    cfg = "B"
+    hp = synth.load_hparams(cfg)
+    s = synth.cubic_lattice(8, 1.5, 0.15, 4, 99)       # 12 A box, ~200 edges/row
+    w = weights_for(hp, 19)
+    a = gpu_run(hp, w, s, "bf16")
+    b = gpu_run(hp, w, s, "fp32")
+    assert a["status"] == 0 and b["status"] == 0
+    rel = np.linalg.norm(a["forces"] - b["forces"]) / np.linalg.norm(b["forces"])
+    _say(f"[bf16 vs fp32 dense] force rel {rel:.3e}")
+    assert rel < 0.03
+
+
 def test_bf16_deterministic_and_chunk_invariant():
     cfg = "B"
     hp = synth.load_hparams(cfg)
