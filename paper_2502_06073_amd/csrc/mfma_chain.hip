@@ -877,23 +877,48 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
     w0r[q] = nn < a.nb ? a.w0[(int64_t)f * K0 + 2 * a.S + nn] : 0.0f;
   }
   __syncthreads();
-  for (int n = 0; n < a.nb; ++n) {
-    float part[NCBW];
+  // this wavefront's share of sum_f W_0[f][2S + n] ga_0[f] for column block cb
+  auto rho_part = [&](int n, int cb) {
+    float p = 0.0f;
 #pragma unroll
-    for (int cb = 0; cb < NCBW; ++cb) {
-      float p = 0.0f;
-      if (pslot < NP0) {
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int f = 16 * (2 * pslot + r) + 4 * g + q;
-            if (f < T0) p += w0r[f * 16 + n] * acc[r][cb][q];
-          }
+      for (int q = 0; q < 4; ++q) {
+        const int f = 16 * (2 * pslot + r) + 4 * g + q;
+        if (f < T0) p += w0r[f * 16 + n] * acc[r][cb][q];
       }
-      part[cb] = sum_groups(p);
+    return sum_groups(p);
+  };
+  constexpr bool kOnePass = sizeof(S.act) >= sizeof(float) * NP0 * 16 * TILE;
+  if constexpr (kOnePass) {
+    // all radial channels at once: the activation buffers are free after
+    // the barrier above and hold the [pair slot][n][edge] partials, summed
+    // over the pair slots in slot order
+    float* red = reinterpret_cast<float*>(&S.act[0][0]);
+    if (pslot < NP0) {
+      for (int n = 0; n < a.nb; ++n)
+#pragma unroll
+        for (int cb = 0; cb < NCBW; ++cb) {
+          const float v = rho_part(n, cb);
+          if (g == 0) red[(pslot * 16 + n) * TILE + 16 * cbA(cb) + lane] = v;
+        }
     }
-    wg_edge_sum(S.red, part, tile, M, tid, [&](int64_t t, float v) { a.grho[t * 16 + n] = v; });
+    __syncthreads();
+    for (int idx = tid; idx < a.nb * TILE; idx += NTHR) {
+      const int e = idx / a.nb, n = idx % a.nb;
+      float v = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NP0; ++w) v += red[(w * 16 + n) * TILE + e];
+      const int64_t t = tile * TILE + e;
+      if (t < M) a.grho[t * 16 + n] = v;
+    }
+  } else {
+    for (int n = 0; n < a.nb; ++n) {
+      float part[NCBW];
+#pragma unroll
+      for (int cb = 0; cb < NCBW; ++cb) part[cb] = pslot < NP0 ? rho_part(n, cb) : 0.0f;
+      wg_edge_sum(S.red, part, tile, M, tid, [&](int64_t t, float v) { a.grho[t * 16 + n] = v; });
+    }
   }
 }
 
