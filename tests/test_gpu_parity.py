@@ -50,6 +50,9 @@ CASES = {
     "C_8clusters": lambda: (synth.load_hparams("C"), synth.clusters(8, 20, 200, 0.1, 0.9, 10, 92)),
     "D_12mixed": lambda: (synth.load_hparams("D"), synth.config_d(12)),
     "l2_c16_lattice": lambda: (small_l2(), synth.cubic_lattice(7, 2.2, 0.25, 4, 93)),
+    # one structure of 1,331 atoms: more atoms than threads in a structure-sum
+    # block, so its energy and virial sums take two strided terms per thread
+    "l2_c16_11cube": lambda: (small_l2(), synth.cubic_lattice(11, 2.2, 0.25, 4, 102)),
 }
 
 
