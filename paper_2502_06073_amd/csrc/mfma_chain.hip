@@ -182,13 +182,23 @@ __device__ __forceinline__ bf16x8 pack8(f32x4 lo, f32x4 hi) {
 
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 __device__ __forceinline__ void st4(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+// The forward's per-edge outputs (x^L, omega, pre-activations) are read
+// only by later kernels, after other large streams: streaming
+// (non-temporal) stores, so that they do not displace the weight fragments
+// every tile re-reads from L2.  The adjoint's outputs, read by the very next
+// kernel, use plain stores.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st4_stream(float* p, f32x4 v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+}
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
-// pre-activation tile storage: [tile][RB][NCB][64 lanes][4] bf16
+// pre-activation tile storage: [tile][RB][NCB][64 lanes][4] bf16 (streamed)
 __device__ __forceinline__ void st_pre(uint2* pre, int64_t tile, int RB, int rb, int cb, int lane, f32x4 v) {
   bf16x4 h;
   h[0] = (__bf16)v[0]; h[1] = (__bf16)v[1]; h[2] = (__bf16)v[2]; h[3] = (__bf16)v[3];
-  pre[((tile * RB + rb) * NCB + cb) * 64 + lane] = __builtin_bit_cast(uint2, h);
+  __builtin_nontemporal_store(__builtin_bit_cast(u32x2, h),
+                              reinterpret_cast<u32x2*>(pre + ((tile * RB + rb) * NCB + cb) * 64 + lane));
 }
 __device__ __forceinline__ f32x4 ld_pre(const uint2* pre, int64_t tile, int RB, int rb, int cb, int lane) {
   const bf16x4 h = __builtin_bit_cast(bf16x4, pre[((tile * RB + rb) * NCB + cb) * 64 + lane]);
@@ -247,10 +257,10 @@ __device__ __forceinline__ void stage_rows_bf16(uint4* __restrict__ act, const u
   }
 }
 
-// four consecutive bf16 values (8-byte store)
+// four consecutive bf16 values (8-byte streaming store)
 __device__ __forceinline__ void st_bf16x4(uint16_t* p, f32x4 v) {
   const uint4 w = __builtin_bit_cast(uint4, pack8(v, v));
-  *reinterpret_cast<uint2*>(p) = uint2{w.x, w.y};
+  __builtin_nontemporal_store(u32x2{w.x, w.y}, reinterpret_cast<u32x2*>(p));
 }
 
 // acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
@@ -505,7 +515,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
       for (int q = 0; q < 4; ++q) v[q] = out_layer ? u[cb] * v[q] * sigm(v[q]) : v[q] * sigm(v[q]);
       if (out_layer) {
         const int64_t t = col_t(cb);
-        if (t < M) st4(a.xnew + t * W + 16 * rb + 4 * g, v);
+        if (t < M) st4_stream(a.xnew + t * W + 16 * rb + 4 * g, v);
       }
     };
   };
@@ -561,7 +571,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = (xp[q] + u[cb] * v[q] * sigm(v[q])) * r2;
         if constexpr (!LAST) {
-          if (valid) st4(a.xnew + t * W + 16 * rb + 4 * g, v);
+          if (valid) st4_stream(a.xnew + t * W + 16 * rb + 4 * g, v);
         } else {
           const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
 #pragma unroll
