@@ -41,7 +41,10 @@ Weight layout (flat float64 vector, row-major out x in matrices, in order):
   species.shift [S] (N(0, 1)).
 
 Pins: invariances, finite differences, locality, the pair-potential special
-case (all W_env = 0) and Table 1's parameter counts (tests/test_oracle_*).
+case (all W_env = 0), Table 1's parameter counts, and a value pin of the
+equivariant branch: per-atom energies of open clusters (l_max = 1, two and
+three layers, alpha, sigma_Z, nbar and energy_scale away from 1) evaluated
+independently with dot and cross products (tests/test_oracle_*).
 The match to the trained Allegro-FM models themselves is parity unpinned (no
 weights or code exist).
 """
