@@ -356,6 +356,12 @@ typedef struct {
 int afm_stage_costs(const afm_hparams* hp /*host*/, afm_stage_cost* out /*host*/, int32_t max,
                     int32_t* n /*host*/);
 
+/* Number of MD-step graphs afm_md_step currently keeps instantiated
+ * (use_graph != 0).  A graph is keyed on the model's creation id and on
+ * every pointer and scalar it was captured with; afm_model_destroy destroys
+ * the graphs of that model, and the rest are destroyed at process exit. */
+int64_t afm_md_graph_count(void);
+
 /* ---- diagnostics ------------------------------------------------------- */
 const char* afm_strerror(int code);
 const char* afm_last_error(void);

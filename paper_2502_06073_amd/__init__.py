@@ -256,6 +256,12 @@ class Calculator:
         self.nl = NeighborList(N, capacity, dev)
         self.ws = Workspace(model, N, B, capacity, max_bytes, second_order)
         self.lib = load()
+        # generation counters of the workspace's per-edge state and of the
+        # neighbour list (see energy_and_forces), and the positions the list
+        # was last built from (None = sysd.pos)
+        self.state_gen = 0
+        self.nl_gen = 0
+        self.nl_pos = None
 
     def _estimate_capacity(self) -> int:
         # one build with a probe list to learn the edge count (host sync)
@@ -276,6 +282,9 @@ class Calculator:
                   self.lib.afm_build_neighbors(C.byref(self.sysd.struct(pos)), self.r_list,
                                                C.byref(self.nl.struct()), C.byref(self.ws.ws),
                                                _stream_ptr(self.model.device)))
+        self.nl_gen += 1
+        self.nl_pos = None if pos is None else pos.detach()
+        self.state_gen += 1       # the list build uses the workspace's scratch
 
     def status(self) -> int:
         return int(self.nl.status.item())
@@ -304,6 +313,7 @@ class Calculator:
                                              C.byref(self.nl.struct()), _ptr(e_atom), _ptr(e_struct),
                                              _ptr(F), _ptr(W) if virial else None, C.byref(self.ws.ws),
                                              _stream_ptr(self.model.device)))
+        self.state_gen += 1
         return dict(e_atom=e_atom, e_struct=e_struct, forces=F, virial=W if virial else None)
 
     def forward_energy(self, pos: Optional[torch.Tensor] = None):
@@ -313,10 +323,13 @@ class Calculator:
                   self.lib.afm_forward_energy(self.model.handle, C.byref(self.sysd.struct(pos)),
                                               C.byref(self.nl.struct()), _ptr(e_atom), _ptr(e_struct),
                                               C.byref(self.ws.ws), _stream_ptr(self.model.device)))
+        self.state_gen += 1
         return e_atom, e_struct
 
     def backward_forces(self, grad_e_struct: Optional[torch.Tensor] = None,
                         pos: Optional[torch.Tensor] = None, virial: bool = False):
+        """Forces (and virials) of the last forward_energy call, which must be
+        the calculator's last call (afm_backward_forces reads its state)."""
         _, _, F, W = self._outs(True)
         g = None if grad_e_struct is None else grad_e_struct.to(torch.float64).contiguous()
         with torch.cuda.device(self.model.device):
@@ -325,6 +338,7 @@ class Calculator:
                                                C.byref(self.nl.struct()), _ptr(g), _ptr(F),
                                                _ptr(W) if virial else None, C.byref(self.ws.ws),
                                                _stream_ptr(self.model.device)))
+        self.state_gen += 1
         return F, (W if virial else None)
 
 
@@ -342,6 +356,7 @@ def _forces_backward(calc: "Calculator", grad_e_struct: Optional[torch.Tensor],
               calc.lib.afm_backward_forces_backward(calc.model.handle, C.byref(calc.sysd.struct(pos)),
                                                     C.byref(calc.nl.struct()), _ptr(gE), _ptr(gF), _ptr(gW),
                                                     _ptr(g), None, C.byref(calc.ws.ws), _stream_ptr(dev)))
+    calc.state_gen += 1
     return g
 
 
@@ -400,19 +415,36 @@ class Adam:
 
 
 class _EnergyFn(torch.autograd.Function):
-    """E_s(pos); its backward returns -forces weighted by the upstream grad."""
+    """E_s(pos); its backward returns -forces weighted by the upstream grad.
+
+    afm_backward_forces reads the per-edge state afm_forward_energy left in
+    the workspace (and the calculator's neighbour list).  If the calculator
+    ran anything else in between -- another forward, a list rebuild -- the
+    backward first rebuilds the list (if it was rebuilt) and re-runs the
+    forward at the saved positions, so each E_s gets its own forces."""
 
     @staticmethod
     def forward(ctx, pos, calc):
-        e_atom, e_struct = calc.forward_energy(pos.detach())
+        if calc.nl_gen == 0:
+            raise RuntimeError("build the neighbour list (calc.build_neighbors) before energy_and_forces")
+        p = pos.detach()
+        e_atom, e_struct = calc.forward_energy(p)
         ctx.calc = calc
+        ctx.gens = (calc.state_gen, calc.nl_gen, calc.nl_pos)
         ctx.save_for_backward(pos)
         return e_struct
 
     @staticmethod
     def backward(ctx, grad_e):
         (pos,) = ctx.saved_tensors
-        F, _ = ctx.calc.backward_forces(grad_e.contiguous(), pos=pos.detach())
+        calc = ctx.calc
+        p = pos.detach()
+        state_gen, nl_gen, nl_pos = ctx.gens
+        if calc.nl_gen != nl_gen:
+            calc.build_neighbors(nl_pos)
+        if calc.state_gen != state_gen:
+            calc.forward_energy(p)
+        F, _ = calc.backward_forces(grad_e.contiguous(), pos=p)
         return -F, None
 
 
@@ -494,6 +526,9 @@ class MD:
                 check("afm_md_step", load().afm_md_step(
                     self.calc.model.handle, C.byref(self.calc.sysd.struct()), C.byref(self.calc.nl.struct()),
                     C.byref(self.state), n_steps, C.byref(self.calc.ws.ws), _stream_ptr(dev)))
+        self.calc.state_gen += 1
+        self.calc.nl_gen += 1
+        self.calc.nl_pos = None
         if self.state.t_target_K > 0:
             # thermostat energy Q xi^2/2 + g kB T eta per step (eV)
             self.thermostat_log = self._tlogs[n_steps].clone()

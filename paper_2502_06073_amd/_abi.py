@@ -94,11 +94,12 @@ EXPORTS = {
     "afm_trace_enable": [C.c_int32],
     "afm_trace_read": [C.POINTER(TraceStat), C.c_int32, C.POINTER(C.c_int32)],
     "afm_stage_costs": [C.POINTER(Hparams), C.POINTER(StageCost), C.c_int32, C.POINTER(C.c_int32)],
+    "afm_md_graph_count": [],
     "afm_strerror": [C.c_int],
     "afm_last_error": [],
     "afm_version": [],
 }
-RESTYPES = {"afm_strerror": C.c_char_p, "afm_last_error": C.c_char_p, "afm_version": C.c_char_p}
+RESTYPES = {"afm_md_graph_count": C.c_int64, "afm_strerror": C.c_char_p, "afm_last_error": C.c_char_p, "afm_version": C.c_char_p}
 
 _LIB = None
 

@@ -63,6 +63,7 @@ struct ModelDims {
 }  // namespace afm
 
 struct afm_model {
+  uint64_t uid = 0;            // creation id, never reused (graph cache key)
   afm_hparams hp;
   afm_precision prec;          // AFM_FP32_PLAIN or AFM_BF16_MFMA
   bool fast_adjoint = false;   // AFM_BF16_MFMA_FAST_ADJOINT was asked for
@@ -190,6 +191,9 @@ int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl,
                     double* e_struct, hipStream_t st);
 int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* state, int32_t n_steps,
             const afm_workspace* ws, const WsLayout& L, hipStream_t st);   // md.hip
+// destroys the cached MD graphs captured with the model of this id (md.hip)
+void md_evict_model(uint64_t model_uid);
+int64_t md_cached_graphs();
 int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
                  hipStream_t st);                                          // neighbors.hip
 

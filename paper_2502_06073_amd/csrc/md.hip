@@ -20,11 +20,11 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include <map>
+#include <cstdlib>
 #include <mutex>
-#include <tuple>
 
 #include "device_util.h"
+#include "graph_cache.h"
 #include "internal.h"
 #include "trace.h"
 
@@ -267,12 +267,27 @@ static int md_sequence(const afm_model* m, const SysDev& s, const NlDev& n, cons
   return AFM_OK;
 }
 
-// cached graphs keyed by every pointer and size the captured sequence uses
-typedef std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*,
-                   int64_t, int32_t, int64_t, hipStream_t, const void*, const void*, double, double, int64_t>
-    GraphKey;
-static std::mutex g_graph_mu;
-static std::map<GraphKey, hipGraphExec_t> g_graphs;
+// Instantiated graphs of MD sequences (graph_cache.h), created on first use
+// (after HIP is initialised) together with an exit handler that destroys
+// the graphs still cached; afm_model_destroy evicts the model's graphs.
+static GraphCache<hipGraphExec_t>* g_cache = nullptr;
+static std::once_flag g_cache_once;
+
+static GraphCache<hipGraphExec_t>& graph_cache() {
+  std::call_once(g_cache_once, [] {
+    g_cache = new GraphCache<hipGraphExec_t>([](hipGraphExec_t e) { (void)hipGraphExecDestroy(e); });
+    std::atexit([] {
+      if (g_cache) g_cache->clear();
+    });
+  });
+  return *g_cache;
+}
+
+void md_evict_model(uint64_t model_uid) {
+  if (g_cache) g_cache->evict_model(model_uid);
+}
+
+int64_t md_cached_graphs() { return g_cache ? (int64_t)g_cache->size() : 0; }
 
 int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* state, int32_t n_steps,
             const afm_workspace* ws, const WsLayout& L, hipStream_t st) {
@@ -289,17 +304,29 @@ int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* s
     return rc;
   }
   const int64_t phase = state->rebuild_every > 0 ? state->step % state->rebuild_every : 0;
-  const bool nvt = state->t_target_K > 0;
-  GraphKey key{m, ws->ptr, state->pos, state->vel, state->forces, state->energy_log, n.row_ptr, phase, n_steps,
-               (int64_t)s.N, st, nvt ? state->nh : nullptr, nvt ? state->thermostat_log : nullptr,
-               nvt ? state->t_target_K : 0.0, nvt ? state->tau_fs : 0.0, nvt ? state->n_dof : 0};
+  MdGraphFields f{};
+  f.model_uid = m->uid;
+  f.ws = ws;
+  f.n_atoms = s.N;
+  f.n_struct = s.B;
+  f.species = s.species;
+  f.cell = s.cell;
+  f.pbc = s.pbc;
+  f.seg = s.seg;
+  f.nl_capacity = n.capacity;
+  f.row_ptr = n.row_ptr;
+  f.col = n.col;
+  f.shift = n.shift;
+  f.rev = n.rev;
+  f.n_edges = n.n_edges;
+  f.status = n.status;
+  f.st = state;
+  f.phase = phase;
+  f.n_steps = n_steps;
+  f.stream = st;
+  const GraphKey key = md_graph_key(f);
   hipGraphExec_t exec = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) exec = it->second;
-  }
-  if (!exec) {
+  if (!graph_cache().find(key, &exec)) {
     AFM_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     int rc = md_sequence(m, s, n, state, n_steps, ws, L, st);
     hipGraph_t graph = nullptr;
@@ -312,8 +339,7 @@ int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* s
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) { set_error(std::string("graph instantiate: ") + hipGetErrorString(e)); return AFM_E_HIP; }
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    g_graphs[key] = exec;
+    graph_cache().insert(key, exec);
   }
   AFM_HIP_CHECK(hipGraphLaunch(exec, st));
   state->step += n_steps;
@@ -321,3 +347,5 @@ int md_step(const afm_model* m, const SysDev& s, const NlDev& n, afm_md_state* s
 }
 
 }  // namespace afm
+
+extern "C" int64_t afm_md_graph_count(void) { return afm::md_cached_graphs(); }

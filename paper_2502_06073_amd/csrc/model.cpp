@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <complex>
 #include <string>
 #include <vector>
@@ -371,7 +372,9 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
     set_error("precision not built (the FP64 reference is the CPU oracle)");
     return AFM_E_UNSUPPORTED;
   }
+  static std::atomic<uint64_t> next_uid{1};
   afm_model* m = new afm_model();
+  m->uid = next_uid.fetch_add(1);
   int rc = dims_of(hp, &m->dims);
   if (!rc) rc = build_layout(hp, m->blocks, &m->n_params);
   if (rc) { delete m; return rc; }
@@ -506,6 +509,8 @@ int afm_model_set_weights(afm_model* m, const double* weights, int64_t n_weights
 
 int afm_model_destroy(afm_model* m) {
   if (!m) return AFM_OK;
+  // graphs captured with this model read its weights: never replay them again
+  afm::md_evict_model(m->uid);
   if (m->dev_mem) {
     hipError_t e = hipFree(m->dev_mem);
     m->dev_mem = nullptr;

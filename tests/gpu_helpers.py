@@ -66,3 +66,22 @@ def parity_report(hp, weights, s, gpu, ref):
         force_rms_abs=float(np.sqrt(np.mean((gpu["forces"] - ref["forces"]) ** 2))),
     )
     return out
+
+
+def weights_nonunit(hp, seed):
+    """Seeded weights with the blocks whose default is all ones drawn away
+    from 1: every path-mixing weight alpha ~ +-U(0.4, 1.6) and every species
+    energy scale sigma_Z ~ U(0.5, 1.5) (the other blocks as weights_for)."""
+    from oracle import model as M
+    lay = M.param_layout(M.HParams.from_dict(hp))
+    w = synth.draw_weights(lay, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    off = 0
+    for b in lay:
+        n = b["size"]
+        if b["name"].endswith(".alpha"):
+            w[off:off + n] = rng.uniform(0.4, 1.6, n) * rng.choice([-1.0, 1.0], n)
+        elif b["name"] == "species.scale":
+            w[off:off + n] = rng.uniform(0.5, 1.5, n)
+        off += n
+    return w

@@ -1,6 +1,7 @@
 """GPU MD step: trajectory parity with the FP64 oracle integrator (FP32
 forces), bitwise equality of graph replays and eager steps, the skin flag,
-and bounded NVE drift with BF16 forces."""
+and NVE / NVT drift with BF16 forces bounded by the same trajectory's drift
+with FP32 forces."""
 
 import sys
 
@@ -79,13 +80,19 @@ def test_md_bf16_energy_drift_small():
     # the random-weight lattice heats up to ~1700 K; light atoms then move
     # up to ~0.07 A/fs, so the list is rebuilt every 2 fs to stay within the
     # half-skin bound
-    hp, w, s, masses, v0, md = _setup("bf16", s=s, cfg="E", rebuild=4)
-    log = md.run(100).cpu().numpy()
-    e = log.sum(1)
-    drift = np.abs(e - e[0]).max() / s.n_atoms
-    _say(f"[md bf16] 100 steps: max |E(t)-E(0)|/N = {drift * 1e3:.3f} meV/atom; KE/N {log[:, 0].mean() / s.n_atoms:.3f}")
-    assert drift < 0.05
-    assert md.calc.status() == 0
+    # The same trajectory with FP32 forces sets the bound: velocity Verlet's
+    # own O(dt^2) energy fluctuation at this temperature is the floor, and
+    # the BF16 forces may add at most a few times that.
+    drifts = {}
+    for prec in ("fp32", "bf16"):
+        hp, w, s, masses, v0, md = _setup(prec, s=s, cfg="E", rebuild=4)
+        log = md.run(100).cpu().numpy()
+        e = log.sum(1)
+        drifts[prec] = np.abs(e - e[0]).max() / s.n_atoms
+        _say(f"[md {prec}] 100 steps: max |E(t)-E(0)|/N = {drifts[prec] * 1e3:.4f} meV/atom; "
+             f"KE/N {log[:, 0].mean() / s.n_atoms:.3f}")
+        assert md.calc.status() == 0
+    assert drifts["bf16"] <= 5.0 * drifts["fp32"]
 
 
 def test_md_cutoff_compaction_matches_full_list():
@@ -162,17 +169,20 @@ def test_md_nvt_graph_replay_equals_eager():
 
 def test_md_nvt_bf16_extended_energy_bounded():
     s = synth.cubic_lattice(6, 2.3, 0.25, 4, 99)
-    hp, w, s, masses, v0, md = _setup("bf16", s=s, cfg="E", rebuild=4, t_target_K=300.0, tau_fs=20.0)
-    log = md.run(100).cpu().numpy()
-    th = md.thermostat_log.cpu().numpy()
-    h = log.sum(1) + th
-    drift = np.abs(h - h[0]).max() / s.n_atoms
-    moved = np.abs(th - th[0]).max() / s.n_atoms
-    _say(f"[md nvt bf16] 100 steps: max |H'(t)-H'(0)|/N = {drift * 1e3:.3f} meV/atom; "
-         f"thermostat moved {moved * 1e3:.1f} meV/atom")
-    assert drift < 0.05
-    assert moved > 5 * drift
-    assert md.calc.status() == 0
+    drifts = {}
+    for prec in ("fp32", "bf16"):
+        hp, w, s, masses, v0, md = _setup(prec, s=s, cfg="E", rebuild=4, t_target_K=300.0, tau_fs=20.0)
+        log = md.run(100).cpu().numpy()
+        th = md.thermostat_log.cpu().numpy()
+        h = log.sum(1) + th
+        drift = np.abs(h - h[0]).max() / s.n_atoms
+        moved = np.abs(th - th[0]).max() / s.n_atoms
+        drifts[prec] = drift
+        _say(f"[md nvt {prec}] 100 steps: max |H'(t)-H'(0)|/N = {drift * 1e3:.4f} meV/atom; "
+             f"thermostat moved {moved * 1e3:.1f} meV/atom")
+        assert moved > 5 * drift
+        assert md.calc.status() == 0
+    assert drifts["bf16"] <= 5.0 * drifts["fp32"]
 
 
 def test_md_nvt_rejects_missing_thermostat_state():

@@ -8,10 +8,10 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import weights_for
+from gpu_helpers import weights_for, weights_nonunit
 
 pytestmark = pytest.mark.gpu
-TOL = 2e-4          # FP32 relative norm
+TOL = 1e-5          # FP32 relative norm
 
 
 def _say(*a):
@@ -160,3 +160,30 @@ def test_training_loss_with_stress_through_autograd():
     _say(f"[train stress] loss gpu {loss.item():.6f} oracle {ref['loss']:.6f}; grad rel {err:.2e}")
     assert abs(loss.item() - ref["loss"]) < 1e-5 * abs(ref["loss"])
     assert err < TOL
+
+
+def test_second_order_nonunit_alpha_sigma():
+    """Path-mixing weights alpha and species scales sigma_Z away from 1: their
+    own gradient blocks and everything downstream of them."""
+    import torch
+    from oracle import model as M
+    hp, s = CASES["C_6clusters"]()
+    w = weights_nonunit(hp, 33)
+    rng = np.random.default_rng(4)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    calc = _calc(hp, w, s)
+    g = calc.forces_backward(torch.tensor(gE, device="cuda"), torch.tensor(gF, device="cuda"))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    ref = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, gF)["grad_weights"]
+    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    off, errs = 0, {}
+    for b in M.param_layout(M.HParams.from_dict(hp)):
+        seg = slice(off, off + b["size"])
+        if b["name"].endswith(".alpha") or b["name"] == "species.scale":
+            errs[b["name"]] = np.linalg.norm(g[seg] - ref[seg]) / max(np.linalg.norm(ref[seg]), 1e-30)
+        off += b["size"]
+    _say(f"[d2 alpha/sigma] rel {err:.2e}; {errs}")
+    assert err < TOL
+    assert max(errs.values()) < 10 * TOL
