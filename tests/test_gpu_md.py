@@ -12,6 +12,9 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+# BF16 energy gate against FP64, eV/atom
+BF16_E_GATE = 1e-3
+
 
 def _say(*a):
     print(*a, flush=True)
@@ -82,7 +85,10 @@ def test_md_bf16_energy_drift_small():
     # half-skin bound
     # The same trajectory with FP32 forces sets the bound: velocity Verlet's
     # own O(dt^2) energy fluctuation at this temperature is the floor, and
-    # the BF16 forces may add at most a few times that.
+    # the BF16 forces may add at most a few times that.  The BF16 potential
+    # energy is itself evaluated with an error (bf16 activations, up to the
+    # 1 meV/atom energy gate), which changes with the configuration: the
+    # logged E(t) - E(0) can carry that error twice, at t and at 0.
     drifts = {}
     for prec in ("fp32", "bf16"):
         hp, w, s, masses, v0, md = _setup(prec, s=s, cfg="E", rebuild=4)
@@ -92,7 +98,7 @@ def test_md_bf16_energy_drift_small():
         _say(f"[md {prec}] 100 steps: max |E(t)-E(0)|/N = {drifts[prec] * 1e3:.4f} meV/atom; "
              f"KE/N {log[:, 0].mean() / s.n_atoms:.3f}")
         assert md.calc.status() == 0
-    assert drifts["bf16"] <= 5.0 * drifts["fp32"]
+    assert drifts["bf16"] <= 5.0 * drifts["fp32"] + 2 * BF16_E_GATE
 
 
 def test_md_cutoff_compaction_matches_full_list():
@@ -182,7 +188,9 @@ def test_md_nvt_bf16_extended_energy_bounded():
              f"thermostat moved {moved * 1e3:.1f} meV/atom")
         assert moved > 5 * drift
         assert md.calc.status() == 0
-    assert drifts["bf16"] <= 5.0 * drifts["fp32"]
+    # as in the NVE test: the BF16 potential energy's evaluation error, up to
+    # the energy gate at t and at 0, on top of a few times the FP32 drift
+    assert drifts["bf16"] <= 5.0 * drifts["fp32"] + 2 * BF16_E_GATE
 
 
 def test_md_nvt_rejects_missing_thermostat_state():
