@@ -246,6 +246,29 @@ int afm_energy_forces(const afm_model* model, const afm_system* sys, const afm_n
                       double* e_atom, double* e_struct, double* forces, double* virial,
                       const afm_workspace* ws, void* stream);
 
+/* ---- energies and forces without allocation -------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * what afm_energy_forces computes, with the same kernels, but its workspace
+ * is a static device array inside the library (AFM_STATIC_SCRATCH_BYTES,
+ * 256 MiB, on each GPU the library runs on, held until the process ends)
+ * instead of a caller allocation.  The caller passes inputs and outputs as
+ * for afm_energy_forces (nl built by afm_build_neighbors with any
+ * workspace); the current device must be the model's.  No hipMalloc, no
+ * allocating library call, no synchronisation.  The workspace is planned as
+ * afm_workspace_plan would plan it with max_bytes = AFM_STATIC_SCRATCH_BYTES
+ * (rows processed in chunks when the edges do not fit at once); a system
+ * whose per-atom buffers and edge arrays alone exceed the array is rejected
+ * with AFM_E_CAPACITY (e.g. ~15k atoms of the 2-layer, latent-256, c = 64,
+ * l = 2 model fit; 1M atoms do not).  All calls on one GPU share its single
+ * array: calls that overlap in time on one GPU (several streams or host
+ * threads) race and must be serialised by the caller.  The array keeps the
+ * last call's contents; every buffer this path reads is written first. */
+#define AFM_STATIC_SCRATCH_BYTES (256LL << 20)
+int afm_energy_forces_noalloc(const afm_model* model, const afm_system* sys, const afm_nlist* nl,
+                              double* e_atom, double* e_struct, double* forces, double* virial,
+                              void* stream);
+
 /* Weight gradients for force and stress matching (Model Training: the loss
  * combines per-atom energy, force and stress errors): given upstream
  * grad_e_struct[n_struct], grad_forces[n_atoms,3] and

@@ -316,6 +316,23 @@ class Calculator:
         self.state_gen += 1
         return dict(e_atom=e_atom, e_struct=e_struct, forces=F, virial=W if virial else None)
 
+    def energy_forces_noalloc(self, out: Optional[Dict] = None, pos: Optional[torch.Tensor] = None,
+                              virial: bool = True) -> Dict:
+        """energy_forces through afm_energy_forces_noalloc: the library's
+        static device scratch instead of this calculator's workspace.  `out`
+        (from a previous call) supplies the output tensors, so that a call
+        allocates nothing."""
+        if out is None:
+            e_atom, e_struct, F, W = self._outs(True)
+            out = dict(e_atom=e_atom, e_struct=e_struct, forces=F, virial=W if virial else None)
+        with torch.cuda.device(self.model.device):
+            check("afm_energy_forces_noalloc",
+                  self.lib.afm_energy_forces_noalloc(self.model.handle, C.byref(self.sysd.struct(pos)),
+                                                     C.byref(self.nl.struct()), _ptr(out["e_atom"]),
+                                                     _ptr(out["e_struct"]), _ptr(out["forces"]),
+                                                     _ptr(out["virial"]), _stream_ptr(self.model.device)))
+        return out
+
     def forward_energy(self, pos: Optional[torch.Tensor] = None):
         e_atom, e_struct, _, _ = self._outs(False)
         with torch.cuda.device(self.model.device):

@@ -13,6 +13,7 @@ STATUS = {0: "AFM_OK", -1: "AFM_E_INVALID", -2: "AFM_E_CAPACITY", -3: "AFM_E_NON
           -4: "AFM_E_UNSUPPORTED", -5: "AFM_E_HIP", -6: "AFM_E_WEIGHTS"}
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_SPECIES, FLAG_SKIN, FLAG_IMAGES = 1, 2, 4, 8, 16
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_fast": 3}
+STATIC_SCRATCH_BYTES = 256 << 20   # AFM_STATIC_SCRATCH_BYTES
 
 
 class Hparams(C.Structure):
@@ -86,6 +87,8 @@ EXPORTS = {
                             C.c_void_p, C.POINTER(Workspace), C.c_void_p],
     "afm_energy_forces": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.POINTER(Workspace), C.c_void_p],
+    "afm_energy_forces_noalloc": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p],
     "afm_backward_forces_backward": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Workspace),
                                      C.c_void_p],

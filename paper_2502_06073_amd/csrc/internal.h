@@ -201,6 +201,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                      const WsLayout& L, const double* gE, const double* gF, const double* gW,
                      float* grad_out, hipStream_t st);                                      // second_order.hip
 
+// device address of the no-allocation entry point's static scratch array on
+// `device` (static_scratch.hip); resolved once per device
+int static_scratch_resolve(int device, void** out);
+
 int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl,
                       const afm_workspace* ws, const WsLayout& L, double* forces,
                       double* virial, hipStream_t st);

@@ -391,6 +391,10 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
   m->plan = make_plan(m->dims.lmax, m->dims.NL);
   hipError_t e = hipGetDevice(&m->device);
   if (e != hipSuccess) { set_error(hipGetErrorString(e)); delete m; return AFM_E_HIP; }
+  // library set-up on this device: the address of the no-allocation entry
+  // point's scratch array (afm_energy_forces_noalloc retries and reports a
+  // failure itself)
+  (void)static_scratch_resolve(m->device, nullptr);
   rc = pack_weights(m, weights);
   if (rc) { if (m->dev_mem) (void)hipFree(m->dev_mem); delete m; return rc; }
   if (!cg_tables_agree()) {
