@@ -1,26 +1,31 @@
 """Throughput of the energy+force hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config B]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config E|B|C|D]
 
-Workload (default): the 13,824-atom periodic system (24^3 simple-cubic
-lattice, spacing 2.2 A, +-0.25 A uniform jitter, 4 species drawn uniformly,
-cutoff 5.5 A, l_max = 2, 2 layers, latent width 256, 3-layer MLPs, 8 Bessel
-functions), seeded synthetic positions and N(0, 1/fan_in) weights.  One
-step = build the edge list + energies + forces + virial (every step of the
-path), with inputs resident in HBM.  The BF16-MFMA path is timed as the
-headline value; the plain-FP32 path is timed beside it for the speedup.
+Workload (default, --config E): NVE molecular dynamics of 1,000,000 atoms
+(100^3 simple-cubic lattice, spacing 2.3 A, +-0.25 A uniform jitter, 4
+species, masses 1-60 amu, Maxwell-Boltzmann velocities at 300 K), cutoff
+5.5 A, l_max = 2, 3 layers, latent width 256, 3-layer MLPs, 8 Bessel
+functions; velocity Verlet with dt = 0.5 fs, edge list rebuilt every 10
+steps at r_c + 0.5 A, steps replayed from captured HIP graphs.  One step =
+one energy+force evaluation of all atoms + the integrator (+ the amortised
+rebuild), inputs resident in HBM.  The BF16-MFMA path is the headline value;
+the plain-FP32 path is timed beside it on the same system (energy+force
+evaluations at the initial positions).  Seeded synthetic positions and
+N(0, 1/fan_in) weights.
 
 Other workloads (one JSON line each, same fields):
-    --config E   1M-atom NVE MD, graph-replayed steps incl. rebuilds
+    --config B   13,824-atom periodic lattice (24^3, spacing 2.2 A, 2 layers):
+                 edge list + energies + forces + virial per step, BF16 vs FP32
     --config C   force-matching training step (energies, forces, loss and
                  its weight gradient through the double backward)
     --config D   batched evaluation of 512 uneven structures
 
 Prints one JSON line with, besides the contract fields, a "roofline" entry
 for the dominant kernel (algorithmic FLOPs per launch / its average HIP-event
-duration during the timed steps) and a "cpu_baseline" entry (the FP64 oracle
-on a bounded sample of central atoms, on the host's cores), plus the force
-RMS error of both GPU paths against the FP64 oracle on sampled atoms.
+duration) and a "cpu_baseline" entry (the FP64 oracle on a bounded sample of
+central atoms, on the host's cores), plus the errors of the GPU paths
+against the FP64 oracle on seeded sampled atoms.
 """
 
 from __future__ import annotations
@@ -152,8 +157,39 @@ def force_errors(hp, s, w, outs, n_atoms=8):
     return res
 
 
-def load_traffic(kernel_stage):
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def sampled_errors(hp, s, w, outs, n_energy=256, n_force=16):
+    """Errors of the GPU paths against the FP64 oracle on seeded atoms of a
+    large system: E_i of n_energy atoms (their rows only, exact by
+    locality) and F_k of n_force atoms (the rows of k and of its
+    neighbours).  The mean of E_i - E_i(FP64) estimates |dE_s|/N."""
+    import synth
+    from oracle import model as M
+    r_list = hp.get("r_list", hp["r_cut"])
+    e_rows = synth.subset_rows(s.n_atoms, n_energy, 211)
+    f_atoms = synth.subset_rows(s.n_atoms, n_force, 212)
+    t0 = time.perf_counter()
+    ref_e = M.rows_energy_grad(hp, w, s, e_rows, r_list=r_list)["e_atom"]
+    ref_f = M.forces_subset(hp, w, s, f_atoms, r_list=r_list)["forces"]
+    t_oracle = time.perf_counter() - t0
+    res = {}
+    for name, (e_atom, forces) in outs.items():
+        dE = e_atom[e_rows] - ref_e
+        dF = forces[f_atoms] - ref_f
+        res[name] = dict(e_atom_mean_err=float(dE.mean()), e_atom_mean_abs_err=float(np.abs(dE).mean()),
+                         e_atom_max_abs_err=float(np.abs(dE).max()),
+                         force_rms_err=float(np.sqrt(np.mean(dF ** 2))),
+                         force_rel_err=float(np.linalg.norm(dF) / np.linalg.norm(ref_f)))
+    res["sample"] = (f"E_i of {n_energy} and F_k of {n_force} seeded atoms at the initial positions "
+                     f"(oracle {t_oracle:.1f} s)")
+    res["ref_force_rms"] = float(np.sqrt(np.mean(ref_f ** 2)))
+    return res
+
+
+def load_traffic(kernel_stage, workload="configB"):
+    """HBM bytes per launch of a stage, from rocprofv3 FETCH_SIZE/WRITE_SIZE
+    counters of this workload (scaled by the copy-kernel calibration),
+    committed under profiles/."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -182,7 +218,9 @@ def count_edges(calc, r):
 def bench_md(a):
     """1M-atom NVE MD (velocity Verlet, dt 0.5 fs, rebuild every 10 steps at
     r_c + 0.5 A), BF16 path, steps replayed from captured graphs; with --nvt T
-    the same run in the canonical ensemble (Nose-Hoover, tau 100 fs)."""
+    the same run in the canonical ensemble (Nose-Hoover, tau 100 fs).  The
+    FP32 plain path is timed beside it (energy+force evaluations of the same
+    system), and both are compared with the FP64 oracle on sampled atoms."""
     import torch
     import synth
     import paper_2502_06073_amd as afm
@@ -190,10 +228,40 @@ def bench_md(a):
     print("[bench] config E: building the 1M-atom system", file=sys.stderr, flush=True)
     s = synth.SYSTEMS["E"]()
     w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS["E"])
+    skin = hp["r_list"] - hp["r_cut"]
+    max_bytes = int(a.max_gib * 2 ** 30)
+    errs_in = {}
+    fp32 = None
+    if not a.no_fp32:
+        # plain FP32: energy+force evaluations (edge list included) at the
+        # initial positions; freed before the BF16 run
+        print("[bench] E: timing fp32 plain", file=sys.stderr, flush=True)
+        m32 = afm.Model(hp, w, precision="fp32")
+        c32 = afm.Calculator(m32, afm.DeviceSystem.from_synth(s), r_list=hp["r_list"], max_bytes=max_bytes)
+        c32.build_neighbors()
+        o32 = c32.energy_forces(virial=False)
+        torch.cuda.synchronize()
+        errs_in["fp32"] = (o32["e_atom"].cpu().numpy(), o32["forces"].cpu().numpy())
+        t0 = time.perf_counter()
+        for _ in range(a.fp32_steps):
+            c32.build_neighbors()
+            c32.energy_forces(virial=False)
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t0
+        fp32 = dict(value=s.n_atoms * a.fp32_steps / dt32, ms_per_step=dt32 / a.fp32_steps * 1e3,
+                    steps=a.fp32_steps, what="edge list + energies + forces per step (no integrator)")
+        print(f"[bench] E: fp32 {fp32['ms_per_step']:.0f} ms/evaluation", file=sys.stderr, flush=True)
+        del o32, c32, m32
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     model = afm.Model(hp, w, precision="bf16")
     sysd = afm.DeviceSystem.from_synth(s)
-    skin = hp["r_list"] - hp["r_cut"]
-    calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=int(a.max_gib * 2 ** 30))
+    calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=max_bytes)
+    calc.build_neighbors()
+    o16 = calc.energy_forces(virial=False)
+    torch.cuda.synchronize()
+    errs_in["bf16"] = (o16["e_atom"].cpu().numpy(), o16["forces"].cpu().numpy())
+    del o16
     masses = synth.species_masses(hp["n_species"], 3005)
     v0 = synth.maxwell_boltzmann(masses[s.species], 300.0, 3001)
     md = afm.MD(calc, masses, v0, dt_fs=0.5, skin=skin, rebuild_every=10, use_graph=True,
@@ -222,19 +290,24 @@ def bench_md(a):
     if a.nvt > 0:      # the conserved quantity of the thermostatted dynamics
         etot = etot + torch.cat(tlogs).cpu().numpy() / s.n_atoms
     print(f"[bench] E: {dt / K * 1e3:.1f} ms/step, {value:.4g} atom-steps/s", file=sys.stderr, flush=True)
-    # one traced MD step (eager): the stages of a step as the MD loop runs
-    # them (cutoff compaction included)
+    # traced MD steps (eager): the stages of a step as the MD loop runs them
+    # (cutoff compaction included), HIP events on the library's stream
     torch.cuda.synchronize()
+    n_tr = 2
     afm.trace_enable(True)
-    md.run(1)
+    te = time.perf_counter()
+    md.run(n_tr)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - te) / n_tr * 1e3
     stats = {k: v for k, v in afm.trace_read().items() if k != "md_step"}
     afm.trace_enable(False)
     costs = afm.stage_costs(hp)
-    roofs = stage_roofline(costs, stats, n_active, s.n_atoms, 1)
+    roofs = stage_roofline(costs, stats, n_active, s.n_atoms, n_tr)
     dom = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom]
     mlp_flops = sum(roofs[k]["flops_per_launch"] * stats[k]["launches"] for k in roofs if costs[k]["kind"] == "mfma")
-    step_ms = sum(v["total_ms"] for v in stats.values())
+    step_ms = sum(v["total_ms"] for v in stats.values()) / n_tr
+    tr = load_traffic(dom, "configE")
     out = dict(metric="atom-steps/s energy+forces, BF16-MFMA vs FP32 plain; force RMS err vs FP64",
                value=value, unit="atom-steps/s", n_gpus=1, steps=K, warmup=a.warmup, ms_per_step=dt / K * 1e3,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="bf16",
@@ -247,14 +320,38 @@ def bench_md(a):
                            n_atoms=s.n_atoms, n_edges_listed=n_listed, n_edges_within_rc=n_active,
                            n_chunks=int(calc.ws.ws.n_chunks), parallelism="single GPU"),
                roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
-                             frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
-               mlp_roofline_frac_one_step=mlp_flops / (step_ms * 1e-3) / PEAK_BF16,
-               stage_ms_one_step={k: round(v["total_ms"], 3) for k, v in stats.items()},
+                             frac=r["frac"], traffic=tr, kernel=dom, avg_ms=r["avg_ms"],
+                             per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]),
+                             launches_per_step=stats[dom]["launches"] / n_tr),
+               step_roofline_frac=4 * costs_total_mac(costs) * n_active / (dt / K) / PEAK_BF16,
+               mlp_roofline_frac_traced=mlp_flops / (step_ms * 1e-3 * n_tr) / PEAK_BF16,
+               eager_traced_ms_per_step=eager_ms,
+               stage_ms_per_step={k: round(v["total_ms"] / n_tr, 3) for k, v in stats.items()},
+               stage_roofline={k: dict(bound=v["bound"], frac=round(v["frac"], 4),
+                                       achieved=round(v["achieved"], 2), unit=v["unit"]) for k, v in roofs.items()},
                **{"nvt_extended_energy" if a.nvt > 0 else "nve": dict(max_abs_drift_mev_per_atom=float(np.abs(etot - etot[0]).max() * 1e3),
                         slope_mev_per_atom_per_ps=float(np.polyfit(np.arange(len(etot)) * 0.5e-3, etot, 1)[0] * 1e3),
                         steps=int(len(etot)))})
+    if fp32 is not None:
+        out["fp32_plain"] = fp32
+        out["speedup_bf16_vs_fp32"] = value / fp32["value"]
+    del md, calc, model
+    if not a.no_cpu_baseline:
+        print("[bench] oracle CPU baseline and FP64 errors", file=sys.stderr, flush=True)
+        cb = cpu_baseline(hp, s, w, budget_s=20.0)
+        cb["sample"] += (f"; per-atom rate of the sample, so one 1M-atom step would take "
+                         f"{s.n_atoms / cb['value']:.0f} s (extrapolated)")
+        out["cpu_baseline"] = cb
+        out["error_vs_fp64"] = sampled_errors(hp, s, w, errs_in)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def costs_total_mac(costs):
+    """Forward multiply-adds per edge of the whole network (MLP GEMMs and
+    tensor products; flops_per_edge counts 2 per MAC): an energy+force
+    evaluation needs 4 FLOP per forward MAC."""
+    return sum(c["flops_per_edge"] for k, c in costs.items() if "fwd" in k) / 2.0
 
 
 def bench_train(a):
@@ -363,7 +460,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="B")
+    ap.add_argument("--config", default="E")
     ap.add_argument("--nvt", type=float, default=0.0, metavar="KELVIN",
                     help="config E: canonical ensemble at this temperature (default: NVE)")
     ap.add_argument("--fp32-steps", type=int, default=3)
@@ -413,7 +510,7 @@ def main(argv=None):
     dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom_name]
     roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"], frac=r["frac"],
-                traffic=load_traffic(dom_name), kernel=dom_name, avg_ms=r["avg_ms"],
+                traffic=load_traffic(dom_name, "configB"), kernel=dom_name, avg_ms=r["avg_ms"],
                 per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]))
     mlp_flops = sum(roofs[k]["flops_per_launch"] for k in roofs if costs[k]["kind"] == "mfma")
     stage_ms = {k: round(v["total_ms"] / v["launches"], 4) for k, v in stats.items()}
