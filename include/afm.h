@@ -280,8 +280,13 @@ int afm_energy_forces_noalloc(const afm_model* model, const afm_system* sys, con
  * grad_virial stands for zeros.  (A stress sigma_s = W_s / V_s enters as
  * gW_s = g_sigma_s / V_s.)  Needs a workspace planned
  * with with_second_order = 1; runs in FP32 (GEMMs on FP32 MFMA) with FP64
- * accumulation of the weight gradients (deterministic).  grad_pos must be
- * NULL (position gradients are not built). */
+ * accumulation of the weight gradients (deterministic).  If grad_pos
+ * (device, float64 [n_atoms, 3]) is not NULL it receives the position
+ * gradient of the same objective, dJ/dr_i (overwritten; the cells are held
+ * fixed): the reverse pass then also carries the adjoints of each edge's
+ * basis (radial functions, envelope, spherical harmonics) and of their
+ * tangents, differentiated per edge with respect to delta_e (second
+ * derivatives of the basis) and scattered to the atoms like forces. */
 int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
                                  const afm_nlist* nl, const double* grad_e_struct,
                                  const double* grad_forces, const double* grad_virial,

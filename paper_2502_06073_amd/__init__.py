@@ -292,9 +292,11 @@ class Calculator:
     def model_n_params(self) -> int:
         return int(sum(b["size"] for b in param_layout(self.model.hp)))
 
-    def forces_backward(self, grad_e_struct=None, grad_forces=None, grad_virial=None) -> torch.Tensor:
-        """Weight gradient of sum gE E + sum gF . F + sum gW : W (needs second_order=True)."""
-        return _forces_backward(self, grad_e_struct, grad_forces, grad_virial=grad_virial)
+    def forces_backward(self, grad_e_struct=None, grad_forces=None, grad_virial=None, want_pos: bool = False):
+        """Weight gradient of J = sum gE E + sum gF . F + sum gW : W (needs
+        second_order=True); with want_pos also dJ/dr (float64 [N, 3]),
+        returned as (grad_weights, grad_pos)."""
+        return _forces_backward(self, grad_e_struct, grad_forces, grad_virial=grad_virial, want_pos=want_pos)
 
     def _outs(self, forces: bool):
         dev = self.model.device
@@ -361,10 +363,12 @@ class Calculator:
 
 def _forces_backward(calc: "Calculator", grad_e_struct: Optional[torch.Tensor],
                      grad_forces: Optional[torch.Tensor], pos: Optional[torch.Tensor] = None,
-                     grad_virial: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """d/dtheta [sum gE E + sum gF . F + sum gW : W] (float32, flat weight layout)."""
+                     grad_virial: Optional[torch.Tensor] = None, want_pos: bool = False):
+    """d/dtheta [sum gE E + sum gF . F + sum gW : W] (float32, flat weight
+    layout); with want_pos also its position gradient (float64 [N, 3])."""
     dev = calc.model.device
     g = torch.empty(calc.model_n_params(), dtype=torch.float32, device=dev)
+    gp = torch.empty(calc.sysd.n_atoms, 3, dtype=torch.float64, device=dev) if want_pos else None
     gE = None if grad_e_struct is None else grad_e_struct.to(torch.float64).contiguous()
     gF = None if grad_forces is None else grad_forces.to(torch.float64).contiguous()
     gW = None if grad_virial is None else grad_virial.to(torch.float64).contiguous()
@@ -372,9 +376,9 @@ def _forces_backward(calc: "Calculator", grad_e_struct: Optional[torch.Tensor],
         check("afm_backward_forces_backward",
               calc.lib.afm_backward_forces_backward(calc.model.handle, C.byref(calc.sysd.struct(pos)),
                                                     C.byref(calc.nl.struct()), _ptr(gE), _ptr(gF), _ptr(gW),
-                                                    _ptr(g), None, C.byref(calc.ws.ws), _stream_ptr(dev)))
+                                                    _ptr(g), _ptr(gp), C.byref(calc.ws.ws), _stream_ptr(dev)))
     calc.state_gen += 1
-    return g
+    return (g, gp) if want_pos else g
 
 
 class _ForceMatchFn(torch.autograd.Function):

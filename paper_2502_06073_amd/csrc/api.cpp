@@ -136,9 +136,8 @@ int afm_backward_forces_backward(const afm_model* m, const afm_system* sys, cons
   if (!rc) rc = check_model(m, ws, &L);
   if (rc) return rc;
   if (!grad_weights) { set_error("grad_weights is required"); return AFM_E_INVALID; }
-  if (grad_pos) { set_error("grad_pos is not built (must be NULL)"); return AFM_E_UNSUPPORTED; }
   if (!ws->with_second_order) { set_error("workspace was planned without the second-order buffers"); return AFM_E_INVALID; }
-  return run_second_order(m, s, n, ws, L, grad_e_struct, grad_forces, grad_virial, grad_weights,
+  return run_second_order(m, s, n, ws, L, grad_e_struct, grad_forces, grad_virial, grad_weights, grad_pos,
                           (hipStream_t)stream);
 }
 

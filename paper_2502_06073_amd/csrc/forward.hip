@@ -680,4 +680,14 @@ int run_force_scatter(const afm_model* m, const SysDev& s, const NlDev& nl, cons
   return AFM_OK;
 }
 
+// out_i = sum_{e in row i} (g_e - g_rev(e)) for a per-edge vector field g
+// [capacity][3] (the force scatter without virials)
+int run_edge_scatter(const SysDev& s, const NlDev& nl, const float* g, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_force_scatter, dim3(grid_for(s.N * kRowLanes, kRowBlock)), dim3(kRowBlock), 0, st, s.pos, s.cell,
+                     s.pbc, s.seg, s.B, (const int64_t*)nl.row_ptr, s.N, (const int32_t*)nl.col,
+                     (const int8_t*)nl.shift, (const int32_t*)nl.rev, g, nl.capacity, out, (double*)nullptr);
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
 }  // namespace afm

@@ -135,6 +135,8 @@ struct WsLayout {
   int64_t so_q = 0;                                      // double [w]
   int64_t so_galpha[kMaxLayers] = {};                    // float [N][n_paths][c]
   int64_t so_asig = 0, so_amu = 0;                       // double [N]
+  int64_t so_badj = 0;                                   // float [2CEX][32] basis adjoints (position gradient)
+  int64_t so_gpos = 0;                                   // float [capacity][3] dJ/d delta_e
 };
 
 WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws);
@@ -199,7 +201,9 @@ int check_chunks(const SysDev& s, const NlDev& nl, const afm_workspace* ws, cons
 
 int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                      const WsLayout& L, const double* gE, const double* gF, const double* gW,
-                     float* grad_out, hipStream_t st);                                      // second_order.hip
+                     float* grad_out, double* grad_pos, hipStream_t st);                    // second_order.hip
+// out_i = sum_{e in row i} (g_e - g_rev(e)), g [capacity][3] (forward.hip)
+int run_edge_scatter(const SysDev& s, const NlDev& nl, const float* g, double* out, hipStream_t st);
 
 // device address of the no-allocation entry point's static scratch array on
 // `device` (static_scratch.hip); resolved once per device

@@ -305,6 +305,8 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
     for (int l = 0; l + 1 < d.NL; ++l) L.so_galpha[l] = take(N * (int64_t)P.layer[l].n_paths * d.c * 4);
     L.so_asig = take(N * 8);
     L.so_amu = take(N * 8);
+    L.so_badj = take(E2 * 32 * 4);
+    L.so_gpos = take(cap * 12);
   }
   L.total = off;
   return L;

@@ -12,7 +12,14 @@
 // the primal rows, so each GEMM serves both), then J is reversed with
 // respect to the weights through primal and tangent together.  Basis and
 // spherical harmonics (and their tangents) do not depend on the weights, so
-// no second derivatives of the geometry are needed.  Everything runs in FP32:
+// the weight gradient needs no second derivatives of the geometry.  The
+// optional position gradient dJ/dr does: the reverse also collects, per
+// edge, the adjoints of the basis b = (rho_n, u, Y) and of its tangent b_dot
+// (primal and tangent rows), and a per-edge kernel differentiates
+// phi(delta, delta_dot) = b_bar . b + b_dot_bar . b_dot by forward-mode
+// dual numbers in delta and in delta_dot (delta_dot = (gF_j - gF_i) +
+// gW delta also depends on delta).  The per-edge results are scattered to
+// the atoms like forces.  Everything runs in FP32:
 // the GEMMs and weight-gradient reductions on the matrix cores
 // (v_mfma_f32_16x16x4f32), the tensor products on the vector ALUs over the
 // CG nonzeros; weight gradients are reduced in fixed-order slices and
@@ -36,6 +43,9 @@ namespace afm {
 // weight gradients reduce over edge rows in slices summed afterwards in a
 // fixed order; enough slices that a launch has ~1024 workgroups
 constexpr int kMaxSlices = 256;
+// per-edge basis adjoints for the position gradient: [row][kBadj] with
+// [0..8] Y, [9] u, [16 + n] rho_n (rows t primal, stack + t tangent)
+constexpr int kBadj = 32;
 
 __device__ __forceinline__ float sig_f(float a) { return 1.0f / (1.0f + expf(-a)); }
 __device__ __forceinline__ float d1silu(float a) {
@@ -71,6 +81,94 @@ __device__ __forceinline__ void sh9_jvp(float x, float y, float z, const float* 
   Yd[6] = s5h * 6.0f * z * w[2];
   Yd[7] = s15 * (x * w[2] + z * w[0]);
   Yd[8] = s15 * (x * w[0] - y * w[1]);
+}
+
+// ----------------------------------------------------------------------------
+// position gradient: dual numbers (a value and its gradient with respect to
+// three seeded inputs) through the edge basis and its tangent
+
+struct D3 {
+  float v, g[3];
+};
+__device__ __forceinline__ D3 dc(float v) { return D3{v, {0.0f, 0.0f, 0.0f}}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.v + b.v, {a.g[0] + b.g[0], a.g[1] + b.g[1], a.g[2] + b.g[2]}}; }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.v - b.v, {a.g[0] - b.g[0], a.g[1] - b.g[1], a.g[2] - b.g[2]}}; }
+__device__ __forceinline__ D3 operator*(D3 a, D3 b) {
+  return D3{a.v * b.v, {a.g[0] * b.v + a.v * b.g[0], a.g[1] * b.v + a.v * b.g[1], a.g[2] * b.v + a.v * b.g[2]}};
+}
+__device__ __forceinline__ D3 operator*(float s, D3 a) { return D3{s * a.v, {s * a.g[0], s * a.g[1], s * a.g[2]}}; }
+__device__ __forceinline__ D3 operator*(D3 a, float s) { return s * a; }
+__device__ __forceinline__ D3 operator+(float s, D3 a) { return D3{s + a.v, {a.g[0], a.g[1], a.g[2]}}; }
+// a function f of a dual: f(a.v) and chain rule with f'(a.v)
+__device__ __forceinline__ D3 dapply(D3 a, float f, float df) {
+  return D3{f, {df * a.g[0], df * a.g[1], df * a.g[2]}};
+}
+__device__ __forceinline__ D3 drcp(D3 a) {
+  const float r = 1.0f / a.v;
+  return dapply(a, r, -r * r);
+}
+__device__ __forceinline__ D3 dsqrt(D3 a) {
+  const float s = sqrtf(a.v);
+  return dapply(a, s, 0.5f / s);
+}
+__device__ __forceinline__ D3 dpow(D3 a, int n) {
+  D3 r = dc(1.0f);
+  for (int q = 0; q < n; ++q) r = r * a;
+  return r;
+}
+// polynomial envelope u(x) and its derivative du/dx, x = d / r_c < 1
+__device__ __forceinline__ D3 denv(D3 x, int p) {
+  const D3 xp = dpow(x, p);
+  return 1.0f + ((-0.5f * (p + 1) * (p + 2)) * xp + (float)(p * (p + 2)) * (xp * x) +
+                 (-0.5f * p * (p + 1)) * (xp * x * x));
+}
+__device__ __forceinline__ D3 denv_dx(D3 x, int p) {
+  const D3 omx = 1.0f + (-1.0f) * x;
+  return (-0.5f * p * (p + 1) * (p + 2)) * (dpow(x, p - 1) * omx * omx);
+}
+
+// phi = sum_k bbar_k b_k + bdbar_k b_dot_k over the edge basis b = (rho_n
+// (n < nb), u, Y (9)) and its tangent along delta_dot, evaluated with dual
+// inputs; bbar / bdbar: [0..8] Y, [9] u, [16 + n] rho_n.  Mirrors the basis
+// of the forward kernels: rho_n = B_n(d) u(d), B_n = sqrt(2/r_c) sin(k_n d)/d,
+// Y = sh9(delta/d), u_dot = u'(d) d_dot, Y_dot = the forward derivative of
+// Y along (delta_dot - u d_dot)/d.
+__device__ D3 basis_phi(const D3* dl, const D3* dd, float r_cut, int p, int nb, const float* bbar,
+                        const float* bdbar) {
+  const D3 r = dsqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+  const D3 inv = drcp(r);
+  const D3 ux = dl[0] * inv, uy = dl[1] * inv, uz = dl[2] * inv;
+  const D3 rd = ux * dd[0] + uy * dd[1] + uz * dd[2];
+  const D3 wx = (dd[0] - ux * rd) * inv, wy = (dd[1] - uy * rd) * inv, wz = (dd[2] - uz * rd) * inv;
+  D3 phi = dc(0.0f);
+  const D3 x = (1.0f / r_cut) * r;
+  if (x.v < 1.0f) {
+    const D3 u = denv(x, p);
+    const D3 up = (1.0f / r_cut) * denv_dx(x, p);
+    phi = phi + bbar[9] * u + bdbar[9] * (up * rd);
+    const float c = sqrtf(2.0f / r_cut);
+    for (int n = 0; n < nb; ++n) {
+      const float k = (n + 1) * 3.14159265358979323846f / r_cut;
+      const D3 kr = k * r;
+      const D3 sn = dapply(kr, sinf(kr.v), cosf(kr.v));
+      const D3 cs = dapply(kr, cosf(kr.v), -sinf(kr.v));
+      const D3 B = c * (sn * inv);
+      const D3 dB = c * ((k * cs) * inv + (-1.0f) * (sn * inv * inv));
+      phi = phi + bbar[16 + n] * (B * u) + bdbar[16 + n] * ((dB * u + B * up) * rd);
+    }
+  }
+  const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+  // Y without its constant parts (Y_0 = 1 and the -1 of Y_6): only the
+  // gradient of phi is used
+  D3 yv = bbar[1] * (s3 * uy) + bbar[2] * (s3 * uz) + bbar[3] * (s3 * ux);
+  yv = yv + bbar[4] * (s15 * (ux * uy)) + bbar[5] * (s15 * (uy * uz)) + bbar[6] * (s5h * (3.0f * (uz * uz)));
+  yv = yv + bbar[7] * (s15 * (ux * uz)) + bbar[8] * ((0.5f * s15) * (ux * ux + (-1.0f) * (uy * uy)));
+  // Y_dot
+  D3 ydv = bdbar[1] * (s3 * wy) + bdbar[2] * (s3 * wz) + bdbar[3] * (s3 * wx);
+  ydv = ydv + bdbar[4] * (s15 * (ux * wy + uy * wx)) + bdbar[5] * (s15 * (uy * wz + uz * wy));
+  ydv = ydv + bdbar[6] * ((6.0f * s5h) * (uz * wz)) + bdbar[7] * (s15 * (ux * wz + uz * wx));
+  ydv = ydv + bdbar[8] * (s15 * (ux * wx + (-1.0f) * (uy * wy)));
+  return phi + yv + ydv;
 }
 
 // tangent geometry: geo2[t] = (delta_dot[3], d_dot, u_dot, Y_dot[9], -, -)
@@ -284,6 +382,105 @@ __global__ void k_act2_bwd(RowRange rr, int stack, int F, const float* __restric
   }
 }
 
+// Position gradient, u adjoints: for the head y = s (x_prev + u h) (latent,
+// s = r2) or y = u h (two-body, s = 1) with h = silu(a), and its tangent
+// y_dot = s (x_prev_dot + u_dot h + u h_dot), given dJ/dy (rows t) and
+// dJ/dy_dot (rows stack + t) before k_act2_bwd rewrites them:
+//   dJ/du += s sum_f (ybar h + ydbar h_dot);  dJ/du_dot += s sum_f ydbar h.
+// One wavefront per edge.
+__global__ void __launch_bounds__(256) k_u2_adj(RowRange rr, int stack, int F, const float* __restrict__ pre,
+                                               const float* __restrict__ gin, float scale, float* __restrict__ badj) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const int lane = threadIdx.x & 63;
+  for (int64_t t = blockIdx.x * 4 + (threadIdx.x >> 6); t < M; t += (int64_t)gridDim.x * 4) {
+    const int64_t ts = stack + t;
+    float su = 0.0f, sud = 0.0f;
+    for (int f = lane; f < F; f += 64) {
+      const float a = pre[t * F + f], ad = pre[ts * F + f];
+      const float yb = gin[t * F + f], ydb = gin[ts * F + f];
+      const float h = a * sig_f(a), hd = d1silu(a) * ad;
+      su += yb * h + ydb * hd;
+      sud += ydb * h;
+    }
+    su = group_sum<64>(su);
+    sud = group_sum<64>(sud);
+    if (lane == 0) {
+      badj[t * kBadj + 9] += scale * su;
+      badj[ts * kBadj + 9] += scale * sud;
+    }
+  }
+}
+
+// rho adjoints from the first two-body layer a0 = W0 [onehot | onehot | rho],
+// a0_dot = W0_rho rho_dot:  dJ/drho_n = sum_f ga[t][f] W0[f][2S + n] (and
+// the same on the tangent rows).  One thread per (row, n).
+__global__ void k_rho2_adj(RowRange rr, int stack, const float* __restrict__ ga, const float* __restrict__ W0,
+                           int S, int nb, int T0, float* __restrict__ badj) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const int K = 2 * S + nb;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * M * nb;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(q % nb);
+    const int64_t rt = q / nb;
+    const int64_t row = rt < M ? rt : stack + (rt - M);
+    float v = 0.0f;
+    for (int f = 0; f < T0; ++f) v += ga[row * T0 + f] * W0[(int64_t)f * K + 2 * S + n];
+    badj[row * kBadj + 16 + n] = v;
+  }
+}
+
+// dJ/d delta_e = d phi/d delta + gW^T d phi/d delta_dot (phi: basis_phi),
+// written at the edge's global index.
+__global__ void k_gpos_edge(RowRange rr, int stack, const float* __restrict__ geo, const float* __restrict__ geo2,
+                            const float* __restrict__ badj, const int32_t* __restrict__ eidx,
+                            const double* __restrict__ gW, const int64_t* __restrict__ seg, int64_t B, float r_cut,
+                            int p, int nb, float* __restrict__ gpos_e) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M; t += (int64_t)gridDim.x * blockDim.x) {
+    const float* G = geo + t * GEO_STRIDE;
+    const float* G2 = geo2 + t * GEO_STRIDE;
+    float res[3] = {0.0f, 0.0f, 0.0f};
+    if (G[GEO_D] > 0.0f) {
+      const float* bb = badj + t * kBadj;
+      const float* bd = badj + (stack + t) * kBadj;
+      D3 dl[3], dd[3];
+      // d/d delta (delta_dot held)
+      for (int q = 0; q < 3; ++q) {
+        dl[q] = dc(G[q]);
+        dl[q].g[q] = 1.0f;
+        dd[q] = dc(G2[q]);
+      }
+      const D3 a = basis_phi(dl, dd, r_cut, p, nb, bb, bd);
+      // d/d delta_dot (delta held)
+      for (int q = 0; q < 3; ++q) {
+        dl[q] = dc(G[q]);
+        dd[q] = dc(G2[q]);
+        dd[q].g[q] = 1.0f;
+      }
+      const D3 b = basis_phi(dl, dd, r_cut, p, nb, bb, bd);
+      for (int q = 0; q < 3; ++q) res[q] = a.g[q];
+      if (gW) {
+        const double* w = gW + 9 * struct_of(seg, B, eidx[t]);
+        // delta_dot_q += sum_c gW[q][c] delta_c  =>  d/d delta_c += gW[q][c] b_q
+        for (int c = 0; c < 3; ++c)
+          res[c] += (float)(w[c] * b.g[0] + w[3 + c] * b.g[1] + w[6 + c] * b.g[2]);
+      }
+    }
+    for (int q = 0; q < 3; ++q) gpos_e[3 * (e0 + t) + q] = res[q];
+  }
+}
+
+__global__ void k_negate_f64(double* __restrict__ a, int64_t n) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    a[q] = -a[q];
+}
+
 // ----------------------------------------------------------------------------
 // tensor products with tangents
 
@@ -306,7 +503,28 @@ struct TP2Args {
   float* gvin;           // stacked dJ/dV^{L-1}
   float* gomega;         // stacked dJ/domega^L
   float* galpha;         // [N][n_paths][C] per-atom alpha-gradient shares
+  float* badj;           // position gradient: stacked per-edge basis adjoints (+= dJ/dY), or null
 };
+
+// sum over the C channel lanes of one edge slot (lanes of a slot are
+// contiguous), then lane n == 0 adds the 9 + 9 totals to the edge's Y and
+// Y_dot adjoints
+template <int C>
+__device__ __forceinline__ void add_ybar(float* __restrict__ badj, int64_t t, int64_t ts, int n, float* yb,
+                                         float* ydb) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    yb[q] = group_sum<C>(yb[q]);
+    ydb[q] = group_sum<C>(ydb[q]);
+  }
+  if (n == 0) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      badj[t * kBadj + q] += yb[q];
+      badj[ts * kBadj + q] += ydb[q];
+    }
+  }
+}
 
 template <int LMAX, int NL, int L>
 struct LayerCT2 {
@@ -541,6 +759,21 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
           a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
           a.gomega[(ts * (LMAX + 1) + l) * C + n] = god;
         }
+        if (a.badj) {
+          // dJ/dY += GV omega + GVd omega_dot;  dJ/dY_dot += GVd omega
+          float yb[9] = {}, ydb[9] = {};
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) {
+            const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
+            const float wd = a.omega1[(ts * (LMAX + 1) + l) * C + n];
+#pragma unroll
+            for (int m = 0; m < 2 * l + 1; ++m) {
+              yb[l * l + m] = GV[l * l + m] * w + GVd[l * l + m] * wd;
+              ydb[l * l + m] = GVd[l * l + m] * w;
+            }
+          }
+          add_ybar<C>(a.badj, t, ts, n, yb, ydb);
+        }
       }
     }
     // dJ/dGamma and dJ/dGamma_dot summed over the slots, scaled by nbar^-1/2
@@ -589,6 +822,23 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
         float* p0 = a.gomega + (t * (LMAX + 1) + l) * C + n;
         float* p1 = a.gomega + (ts * (LMAX + 1) + l) * C + n;
         if constexpr (L == 1) { *p0 += go; *p1 += god; } else { *p0 = go; *p1 = god; }
+      }
+      if (a.badj) {
+        // dJ/dY += dJ/dGamma omega + dJ/dGamma_dot omega_dot;
+        // dJ/dY_dot += dJ/dGamma_dot omega  (the sums carry nbar^-1/2)
+        float yb[9] = {}, ydb[9] = {};
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) {
+          const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
+          const float wd = a.omega[(ts * (LMAX + 1) + l) * C + n];
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) {
+            const float G = gg[(l * l + m) * C + n], Gd = gg[(NLM + l * l + m) * C + n];
+            yb[l * l + m] = G * w + Gd * wd;
+            ydb[l * l + m] = Gd * w;
+          }
+        }
+        add_ybar<C>(a.badj, t, ts, n, yb, ydb);
       }
     }
     __syncthreads();
@@ -792,7 +1042,7 @@ int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const 
 
 int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                      const WsLayout& L, const double* gE, const double* gF, const double* gW, float* grad_out,
-                     hipStream_t st) {
+                     double* grad_pos, hipStream_t st) {
   TraceScope tr(st, "second_order");
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
@@ -811,7 +1061,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   float* gom = ws_ptr<float>(ws, L.so_gomega);
   float* eps2 = ws_ptr<float>(ws, L.so_eps);
   float* coef = ws_ptr<float>(ws, L.so_coef);
+  float* badj = grad_pos ? ws_ptr<float>(ws, L.so_badj) : nullptr;
+  float* gpos_e = ws_ptr<float>(ws, L.so_gpos);
   int rc = zero_async(gacc, m->n_params * 8, st);
+  if (!rc && grad_pos) rc = zero_async(gpos_e, nl.capacity * 12, st);
   if (!rc) rc = zero_async(ws_ptr<double>(ws, L.so_q), (int64_t)d.w * 8, st);
   if (rc) return rc;
   rc = launch_chunk_rows(s, nl, ws, L, st);
@@ -821,6 +1074,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   const float inb = (float)(1.0 / sqrt(d.nbar));
   for (int chunk = 0; chunk < ws->n_chunks; ++chunk) {
     rr.chunk = chunk;
+    if (badj) {
+      rc = zero_async(badj, E2 * kBadj * 4, st);
+      if (rc) return rc;
+    }
     // ---- forward with tangents ----
     rc = launch_geometry(m, s, nl, ws, L, rr, st);
     if (rc) return rc;
@@ -904,6 +1161,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                    partial, gacc, block_offset(m, nm), d.c, d.lmax + 1);
         if (rc) return rc;
       }
+      if (badj)
+        hipLaunchKernelGGL(k_u2_adj, dim3(grid_for(stack, 4, 16384)), dim3(256), 0, st, rr, stack, d.w,
+                           (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), (const float*)gx,
+                           0.70710678118654752f, badj);
       hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack,
                          d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), gx, ga,
                          (const float*)geo, (const float*)geo2, 1, 0.70710678118654752f, 0.70710678118654752f);
@@ -945,6 +1206,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       ta.gvin = (layer > 1) ? (((d.NL - layer) % 2 == 0) ? gva : gvb) : nullptr;
       ta.gomega = gom;
       ta.galpha = layer < d.NL ? ws_ptr<float>(ws, L.so_galpha[layer - 1]) : nullptr;
+      ta.badj = badj;
       tp2_kernel_t kb = pick_tp2(d.lmax, d.NL, layer, d.c, true);
       if (!kb) { set_error("second-order tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
       hipLaunchKernelGGL(kb, dim3(grid_for(s.N, 1, 65536)), dim3(256), 0, st, ta);
@@ -958,6 +1220,9 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
     if (rc) return rc;
     {
       const int F = d.tb[d.ntb - 1];
+      if (badj)
+        hipLaunchKernelGGL(k_u2_adj, dim3(grid_for(stack, 4, 16384)), dim3(256), 0, st, rr, stack, F,
+                           (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), (const float*)gx, 1.0f, badj);
       hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * F, 256, 65536)), dim3(256), 0, st, rr, stack, F,
                          (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), gx, ga, (const float*)geo,
                          (const float*)geo2, 1, 1.0f, 0.0f);
@@ -982,6 +1247,23 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         }
       }
     }
+    if (badj) {
+      // basis adjoints complete for this chunk: rho from the first two-body
+      // layer, then dJ/d delta per edge
+      hipLaunchKernelGGL(k_rho2_adj, dim3(grid_for(2 * (int64_t)stack * d.nb, 256, 65536)), dim3(256), 0, st, rr,
+                         stack, (const float*)ga, m->W.tb[0], d.S, d.nb, d.tb[0], badj);
+      hipLaunchKernelGGL(k_gpos_edge, dim3(grid_for(stack, 256, 65536)), dim3(256), 0, st, rr, stack,
+                         (const float*)geo, (const float*)geo2, (const float*)badj, (const int32_t*)eidx, gW, s.seg,
+                         s.B, (float)d.r_cut, d.p, d.nb, gpos_e);
+      AFM_LAUNCH_CHECK();
+    }
+  }
+  if (grad_pos) {
+    // dJ/dr_i = sum_{e in row i} (dJ/d delta_rev(e) - dJ/d delta_e)
+    rc = run_edge_scatter(s, nl, gpos_e, grad_pos, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_negate_f64, dim3(grid_for(3 * s.N, 256, 4096)), dim3(256), 0, st, grad_pos, 3 * s.N);
+    AFM_LAUNCH_CHECK();
   }
   // per-atom shares: alpha, species scale / shift; edge-energy matrices
   char nm[32];

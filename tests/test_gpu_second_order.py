@@ -187,3 +187,39 @@ def test_second_order_nonunit_alpha_sigma():
     _say(f"[d2 alpha/sigma] rel {err:.2e}; {errs}")
     assert err < TOL
     assert max(errs.values()) < 10 * TOL
+
+
+@pytest.mark.parametrize("name", ["A", "mixed", "C_periodic_small"])
+def test_second_order_position_gradient_matches_oracle(name):
+    """grad_pos = dJ/dr of J = sum gE E + sum gF . F + sum gW : W (second
+    derivatives of the energy, incl. those of the edge basis), against the
+    oracle's double backward with respect to the positions; the weight
+    gradient of the same call is unchanged."""
+    import torch
+    from oracle import model as M
+    if name == "mixed":
+        hp, s = _mixed()
+    else:
+        hp, s = CASES[name]()
+    w = weights_nonunit(hp, 36)
+    rng = np.random.default_rng(7)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    gW = rng.standard_normal((s.n_struct, 3, 3))
+    calc = _calc(hp, w, s)
+    dev = "cuda"
+    g, gp = calc.forces_backward(torch.tensor(gE, device=dev), torch.tensor(gF, device=dev),
+                                 torch.tensor(gW, device=dev), want_pos=True)
+    g_only = calc.forces_backward(torch.tensor(gE, device=dev), torch.tensor(gF, device=dev),
+                                  torch.tensor(gW, device=dev))
+    torch.cuda.synchronize()
+    gp = gp.cpu().numpy()
+    ref = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, gF, grad_virial=gW, want_pos=True)
+    err = np.linalg.norm(gp - ref["grad_pos"]) / np.linalg.norm(ref["grad_pos"])
+    errw = np.linalg.norm(g.cpu().numpy() - ref["grad_weights"]) / np.linalg.norm(ref["grad_weights"])
+    _say(f"[d2 pos] {name}: {s.n_atoms} atoms, grad_pos rel {err:.2e} (|ref| {np.linalg.norm(ref['grad_pos']):.3e}), "
+         f"weights rel {errw:.2e}")
+    assert err < TOL
+    assert errw < TOL
+    np.testing.assert_array_equal(g.cpu().numpy(), g_only.cpu().numpy())
+    assert calc.status() == 0
