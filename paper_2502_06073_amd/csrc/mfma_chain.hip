@@ -31,6 +31,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "device_util.h"
@@ -226,24 +227,73 @@ __device__ __forceinline__ bf16x8 ld_frag32(const float* __restrict__ X, int64_t
   return pack8(lo, hi);
 }
 
-// Stage rows [tile*TILE, tile*TILE + TILE) of X[t][K] into LDS fragments.
+// Staging of tile rows [tile*TILE, tile*TILE + TILE) of a row-major matrix
+// X[t][K] into LDS B fragments.  A stager issues all of a thread's global
+// loads (load) before the first LDS write (store), so a tile costs one
+// memory round trip, not one per fragment; rows past the chunk load row
+// tile*TILE (always valid) and are zeroed.  F32 = true: float32 source
+// (rounded to bf16), false: bf16 source (8-byte words copied).
+template <int K, bool F32>
+struct Stager {
+  static constexpr int NF = cdiv(K, 32) * NCB * 64;
+  static constexpr int IT = cdiv(NF, NTHR);
+  typedef typename std::conditional<F32, f32x4, uint2>::type V;
+  V lo[IT], hi[IT];
+  __device__ __forceinline__ void load(const void* __restrict__ Xv, int64_t tile, int64_t M, int tid) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = tid + it * NTHR;
+      const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB);
+      const int64_t t = tile * TILE + 16 * cb + (l & 15);
+      const int fa = 32 * kb + 4 * (l >> 4), fb = fa + 16;
+      const bool valid = idx < NF && t < M;
+      const int64_t tr = valid ? t : tile * TILE;
+      if constexpr (F32) {
+        const float* X = static_cast<const float*>(Xv) + tr * K;
+        lo[it] = (K % 32 == 0 || fa + 4 <= K) ? ld4(X + fa) : zero4();
+        hi[it] = (K % 32 == 0 || fb + 4 <= K) ? ld4(X + fb) : zero4();
+        if (!valid) { lo[it] = zero4(); hi[it] = zero4(); }
+      } else {
+        const uint16_t* X = static_cast<const uint16_t*>(Xv) + tr * K;
+        lo[it] = (K % 32 == 0 || fa + 4 <= K) ? *reinterpret_cast<const uint2*>(X + fa) : uint2{0u, 0u};
+        hi[it] = (K % 32 == 0 || fb + 4 <= K) ? *reinterpret_cast<const uint2*>(X + fb) : uint2{0u, 0u};
+        if (!valid) { lo[it] = uint2{0u, 0u}; hi[it] = uint2{0u, 0u}; }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint4* __restrict__ act, int tid) const {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = tid + it * NTHR;
+      if (NF % NTHR == 0 || idx < NF) {
+        if constexpr (F32) act[idx] = __builtin_bit_cast(uint4, pack8(lo[it], hi[it]));
+        else act[idx] = uint4{lo[it].x, lo[it].y, hi[it].x, hi[it].y};
+      }
+    }
+  }
+};
+
 template <int K>
 __device__ __forceinline__ void stage_rows(uint4* __restrict__ act, const float* __restrict__ X, int64_t tile,
                                            int64_t M, int tid) {
-  constexpr int NF = cdiv(K, 32) * NCB * 64;
-#pragma unroll 1
-  for (int idx = tid; idx < NF; idx += NTHR) {
-    const int l = idx & 63, cb = (idx >> 6) % NCB, kb = idx / (64 * NCB);
-    const int64_t t = tile * TILE + 16 * cb + (l & 15);
-    act[idx] = __builtin_bit_cast(uint4, ld_frag32<K>(X, t, t < M, kb, l >> 4));
-  }
+  Stager<K, true> s;
+  s.load(X, tile, M, tid);
+  s.store(act, tid);
 }
 
-// The same from a bf16 matrix X[t][K] (K a multiple of 4): the fragment's
-// two runs of 4 features are copied as 8-byte words, no conversion.
 template <int K>
 __device__ __forceinline__ void stage_rows_bf16(uint4* __restrict__ act, const uint16_t* __restrict__ X,
                                                 int64_t tile, int64_t M, int tid) {
+  Stager<K, false> s;
+  s.load(X, tile, M, tid);
+  s.store(act, tid);
+}
+
+// The same one fragment at a time (few registers; for a restage of rows
+// the tile has just read, which hit in L2)
+template <int K>
+__device__ __forceinline__ void restage_rows_bf16(uint4* __restrict__ act, const uint16_t* __restrict__ X,
+                                                  int64_t tile, int64_t M, int tid) {
   constexpr int NF = cdiv(K, 32) * NCB * 64;
 #pragma unroll 1
   for (int idx = tid; idx < NF; idx += NTHR) {
@@ -297,6 +347,9 @@ __device__ __forceinline__ void mma_pair(const uint4* __restrict__ W, int pair, 
 #pragma unroll
     for (int c = 0; c < NCBW; ++c)
       b[c] = __builtin_bit_cast(bf16x8, act[frag_idx(kb, half * NCBW + c, lane)]);
+    // the next k-block's weight loads go out before this block's MFMAs (a
+    // whole block of MFMAs covers their L2 latency), not sunk among them
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int h = 0; h < NS; ++h)
 #pragma unroll
@@ -584,8 +637,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   // output overwrites the x buffer after a barrier
   f32x4 acc[2][NCBW];
   zero_acc(acc);
-  stage_rows<W>(S.act[0], a.xprev, tile, M, tid);
-  stage_rows_bf16<KS>(S.act[1], a.s16, tile, M, tid);
+  {
+    // x and s loads all in flight together
+    Stager<W, true> sx;
+    Stager<KS, false> ss;
+    sx.load(a.xprev, tile, M, tid);
+    ss.load(a.s16, tile, M, tid);
+    sx.store(S.act[0], tid);
+    ss.store(S.act[1], tid);
+  }
   __syncthreads();
   if (mine) {
     mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, half, lane);
@@ -754,7 +814,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
   // r2 W_env^T dE/domega (dE/domega staged again into the free buffer), and
   // the epilogue adds r2 x the stored part of gx.
   if constexpr (!LAST) {
-    stage_rows_bf16<ENV>(S.act[cur ^ 1], a.gomega, tile, M, tid);
+    restage_rows_bf16<ENV>(S.act[cur ^ 1], a.gomega, tile, M, tid);
     __syncthreads();
   }
   // a fresh copy of the tile index, so that the compiler forms the edge
