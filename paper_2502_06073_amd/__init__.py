@@ -26,7 +26,7 @@ from ._abi import AfmError, check, load
 
 __all__ = ["Model", "DeviceSystem", "NeighborList", "Workspace", "Calculator",
            "param_layout", "cg_real", "hparams_struct", "stage_costs", "energy_and_forces", "AfmError", "Adam",
-           "trace_enable", "trace_read", "energy_forces_for_training", "MD"]
+           "trace_enable", "trace_read", "energy_forces_for_training", "MD", "EvalGraph"]
 
 
 def trace_enable(on: bool = True) -> None:
@@ -142,6 +142,16 @@ class Model:
         with torch.cuda.device(self.device):
             check("afm_model_set_weights",
                   load().afm_model_set_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_double)), w.shape[0]))
+
+    @property
+    def edge_tile(self) -> int:
+        """Edges per workgroup tile of the BF16 MLP chains (0 for FP32)."""
+        v = C.c_int32()
+        check("afm_get_edge_tile", load().afm_get_edge_tile(self.handle, C.byref(v)))
+        return int(v.value)
+
+    def set_edge_tile(self, edges: int):
+        check("afm_set_edge_tile", load().afm_set_edge_tile(self.handle, int(edges)))
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -288,6 +298,21 @@ class Calculator:
 
     def status(self) -> int:
         return int(self.nl.status.item())
+
+    def tune_edge_tile(self, cache_path: Optional[str] = None) -> Dict:
+        """Pick the model's edge-tile shape by timing this workload (see
+        afm_tune_edge_tile); the list must be built.  Returns the chosen
+        shape, the per-shape times (ms) and whether the cache answered."""
+        chosen, hit = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 2)()
+        with torch.cuda.device(self.model.device):
+            check("afm_tune_edge_tile",
+                  self.lib.afm_tune_edge_tile(self.model.handle, C.byref(self.sysd.struct()),
+                                              C.byref(self.nl.struct()), C.byref(self.ws.ws),
+                                              cache_path.encode() if cache_path else None, C.byref(chosen), ms,
+                                              C.byref(hit), _stream_ptr(self.model.device)))
+        self.state_gen += 1
+        return dict(tile=int(chosen.value), ms_64=float(ms[0]), ms_128=float(ms[1]), from_cache=bool(hit.value))
 
     def model_n_params(self) -> int:
         return int(sum(b["size"] for b in param_layout(self.model.hp)))
@@ -467,6 +492,52 @@ class _EnergyFn(torch.autograd.Function):
             calc.forward_energy(p)
         F, _ = calc.backward_forces(grad_e.contiguous(), pos=p)
         return -F, None
+
+
+class EvalGraph:
+    """One evaluation step of a calculator -- the edge-list build (optional)
+    and afm_energy_forces -- captured once into a hipGraph on the current
+    stream and replayed: the launches of every stage for the whole batch go
+    out as one graph launch.  The outputs live in fixed tensors (`out`),
+    overwritten by each replay; positions are read from calc.sysd.pos at
+    replay time (update it in place)."""
+
+    def __init__(self, calc: Calculator, rebuild: bool = True, virial: bool = True):
+        self.calc = calc
+        dev = calc.model.device
+        self.rebuild = rebuild
+        e_atom, e_struct, F, W = calc._outs(True)
+        self.out = dict(e_atom=e_atom, e_struct=e_struct, forces=F, virial=W if virial else None)
+        self._nl = calc.nl.struct()
+        self._sys = calc.sysd.struct()
+        # one eager step first (same launches, so nothing is set up during
+        # the capture), then the capture
+        self._step(_stream_ptr(dev))
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step(_stream_ptr(dev))
+        torch.cuda.synchronize(dev)
+
+    def _step(self, stream):
+        lib, calc, o = load(), self.calc, self.out
+        with torch.cuda.device(calc.model.device):
+            if self.rebuild:
+                check("afm_build_neighbors",
+                      lib.afm_build_neighbors(C.byref(self._sys), calc.r_list, C.byref(self._nl),
+                                              C.byref(calc.ws.ws), stream))
+            check("afm_energy_forces",
+                  lib.afm_energy_forces(calc.model.handle, C.byref(self._sys), C.byref(self._nl),
+                                        _ptr(o["e_atom"]), _ptr(o["e_struct"]), _ptr(o["forces"]),
+                                        _ptr(o["virial"]), C.byref(calc.ws.ws), stream))
+
+    def replay(self) -> Dict:
+        self.graph.replay()
+        self.calc.state_gen += 1
+        if self.rebuild:
+            self.calc.nl_gen += 1
+            self.calc.nl_pos = None
+        return self.out
 
 
 def energy_and_forces(calc: Calculator, pos: torch.Tensor) -> torch.Tensor:

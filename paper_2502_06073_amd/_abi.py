@@ -92,6 +92,10 @@ EXPORTS = {
     "afm_backward_forces_backward": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Workspace),
                                      C.c_void_p],
+    "afm_set_edge_tile": [C.c_void_p, C.c_int32],
+    "afm_get_edge_tile": [C.c_void_p, C.POINTER(C.c_int32)],
+    "afm_tune_edge_tile": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(Workspace), C.c_char_p,
+                           C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p],
     "afm_md_step": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(MdState), C.c_int32,
                     C.POINTER(Workspace), C.c_void_p],
     "afm_trace_enable": [C.c_int32],

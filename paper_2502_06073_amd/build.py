@@ -25,7 +25,7 @@ ARCH = "gfx950"
 
 SOURCES = ["model.cpp", "weights.cpp", "api.cpp", "trace.cpp", "neighbors.hip", "forward.hip",
            "tp_kernels.hip", "mfma_chain.hip", "md.hip", "second_order.hip", "train.hip",
-           "static_scratch.hip"]
+           "static_scratch.hip", "tuner.cpp"]
 
 FLAGS = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

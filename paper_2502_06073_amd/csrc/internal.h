@@ -67,6 +67,7 @@ struct afm_model {
   afm_hparams hp;
   afm_precision prec;          // AFM_FP32_PLAIN or AFM_BF16_MFMA
   bool fast_adjoint = false;   // AFM_BF16_MFMA_FAST_ADJOINT was asked for
+  int edge_tile = 64;          // edges per workgroup tile of the BF16 MFMA chains (64 or 128)
   afm::ModelDims dims;
   afm::Plan plan;
   int device;
