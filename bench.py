@@ -89,6 +89,7 @@ def setup(config, precision):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]))
     calc.build_neighbors()
+    calc.tune = calc.tune_edge_tile()
     torch.cuda.synchronize()
     return hp, s, w, calc
 
@@ -258,6 +259,8 @@ def bench_md(a):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=max_bytes)
     calc.build_neighbors()
+    tune = calc.tune_edge_tile()
+    print(f"[bench] E: edge tile {tune['tile']} (ms per evaluation: {tune['ms']})", file=sys.stderr, flush=True)
     o16 = calc.energy_forces(virial=False)
     torch.cuda.synchronize()
     errs_in["bf16"] = (o16["e_atom"].cpu().numpy(), o16["forces"].cpu().numpy())
@@ -318,7 +321,9 @@ def bench_md(a):
                                     f"rebuild every 10 steps at r_c 5.5 + 0.5 A skin, l_max 2, 3 layers, latent 256, "
                                     f"graph-replayed steps incl. rebuilds",
                            n_atoms=s.n_atoms, n_edges_listed=n_listed, n_edges_within_rc=n_active,
-                           n_chunks=int(calc.ws.ws.n_chunks), parallelism="single GPU"),
+                           n_chunks=int(calc.ws.ws.n_chunks), edge_tile="%dx%d" % tune["tile"],
+                           parallelism="single GPU"),
+               edge_tile_tuner_ms=tune["ms"],
                roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
                              frac=r["frac"], traffic=tr, kernel=dom, avg_ms=r["avg_ms"],
                              per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]),
@@ -436,6 +441,7 @@ def bench_batch(a):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]))
     calc.build_neighbors()
+    tune = calc.tune_edge_tile()
     dt_eager, out_, stats = time_steps(calc, a.steps, a.warmup, trace=True)
     n_edges = int(calc.nl.n_edges.item())
     # captured step, replayed
@@ -463,7 +469,9 @@ def bench_batch(a):
                                     f"half periodic triclinic, half clusters, 89 species), r_c 6 A, l_max 2, "
                                     f"3 layers, latent 256: edge lists + energies + forces + virials of the "
                                     f"flattened batch per step, replayed from a captured hipGraph",
-                           n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=n_edges, parallelism="single GPU"),
+                           n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=n_edges,
+                           edge_tile="%dx%d" % tune["tile"], parallelism="single GPU"),
+               edge_tile_tuner_ms=tune["ms"],
                roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
                              frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
                eager_ms_per_step=dt_eager / a.steps * 1e3,
@@ -570,7 +578,9 @@ def main(argv=None):
                config=dict(workload=f"{s.n_atoms}-atom periodic jittered SC lattice (24^3, a=2.2 A), 4 species, "
                                     f"r_c 5.5 A, l_max 2, 2 layers, latent 256, 3-layer MLPs, energy+forces+virial "
                                     f"incl. edge-list build" if a.config == "B" else f"config {a.config}",
-                           n_atoms=s.n_atoms, n_edges=n_edges, parallelism="single GPU"),
+                           n_atoms=s.n_atoms, n_edges=n_edges, edge_tile="%dx%d" % calc.tune["tile"],
+                           parallelism="single GPU"),
+               edge_tile_tuner_ms=calc.tune["ms"],
                roofline=roof, stage_ms=stage_ms,
                stage_roofline={k: dict(bound=v["bound"], frac=round(v["frac"], 4),
                                        achieved=round(v["achieved"], 2), unit=v["unit"]) for k, v in roofs.items()},

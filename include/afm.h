@@ -295,28 +295,30 @@ int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
 
 /* ---- edge-tile shape of the MLP chains --------------------------------------
  * The per-edge MLPs (two-body, latent and embedding; Methodology / Model
- * Training) run on BF16 MFMA in workgroup tiles of 64 edges x 8 wavefronts
- * or 128 edges x 16 wavefronts.  Every edge's result is the same with
- * either shape (bit for bit); only the speed differs.  The shape is a
- * property of the model (default 64) and must not change between
- * afm_forward_energy and the afm_backward_forces that follows it.  For
- * FP32 models the shape has no effect (afm_get_edge_tile reports 0). */
-int afm_set_edge_tile(afm_model* model, int32_t edges /* 64 or 128 */);
-int afm_get_edge_tile(const afm_model* model, int32_t* edges /*host*/);
+ * Training) run on BF16 MFMA in workgroup tiles of edges x wavefronts =
+ * 64 x 8 (two workgroups per compute unit), 128 x 16 or 128 x 8 (one; the
+ * last with twice the columns per wavefront).  Every edge's result is the
+ * same with any shape (bit for bit); only the speed differs.  The shape is
+ * a property of the model (default 64 x 8) and must not change between
+ * afm_forward_energy and the afm_backward_forces that follows it.  For FP32
+ * models the shape has no effect (afm_get_edge_tile reports 0 x 0). */
+int afm_set_edge_tile(afm_model* model, int32_t edges, int32_t waves);
+int afm_get_edge_tile(const afm_model* model, int32_t* edges /*host*/, int32_t* waves /*host*/);
 /* Tuner: times afm_energy_forces on the caller's system, list and workspace
  * (1 warm-up + 3 timed evaluations per shape, HIP events on `stream`),
- * selects the fastest shape for the model and returns it in *chosen (0 for
- * FP32 models).  With cache_path (host string, may be NULL) the choice is
- * looked up first in that JSON file, keyed on the device architecture, the
- * model's shape (w, c, l_max, layers, depth, two-body widths, n_b,
- * precision) and the mean number of edges per atom; a hit sets the shape
- * without timing (*from_cache = 1), a miss adds the measured entry.  ms
- * (host, 2 doubles, may be NULL) receives the mean evaluation time with 64
- * and 128 edges per tile.  Not for the hot path: it synchronises the stream,
- * allocates and frees scratch outputs, and overwrites the workspace. */
+ * selects the fastest shape for the model and returns it in *edges, *waves
+ * (0 for FP32 models).  With cache_path (host string, may be NULL) the
+ * choice is looked up first in that JSON file, keyed on the device
+ * architecture, the model's shape (w, c, l_max, layers, depth, two-body
+ * widths, n_b, precision) and the mean number of edges per atom; a hit sets
+ * the shape without timing (*from_cache = 1), a miss adds the measured
+ * entry.  ms (host, 3 doubles, may be NULL) receives the mean evaluation
+ * time of the shapes 64x8, 128x16 and 128x8.  Not for the hot path: it
+ * synchronises the stream, allocates and frees scratch outputs, and
+ * overwrites the workspace. */
 int afm_tune_edge_tile(afm_model* model, const afm_system* sys, const afm_nlist* nl,
                        const afm_workspace* ws, const char* cache_path /*host or NULL*/,
-                       int32_t* chosen /*host*/, double* ms /*host [2] or NULL*/,
+                       int32_t* edges /*host*/, int32_t* waves /*host*/, double* ms /*host [3] or NULL*/,
                        int32_t* from_cache /*host or NULL*/, void* stream);
 
 /* ---- molecular dynamics ---------------------------------------------------

@@ -144,14 +144,15 @@ class Model:
                   load().afm_model_set_weights(self.handle, w.ctypes.data_as(C.POINTER(C.c_double)), w.shape[0]))
 
     @property
-    def edge_tile(self) -> int:
-        """Edges per workgroup tile of the BF16 MLP chains (0 for FP32)."""
-        v = C.c_int32()
-        check("afm_get_edge_tile", load().afm_get_edge_tile(self.handle, C.byref(v)))
-        return int(v.value)
+    def edge_tile(self):
+        """(edges, wavefronts) per workgroup tile of the BF16 MLP chains
+        ((0, 0) for FP32)."""
+        e, w = C.c_int32(), C.c_int32()
+        check("afm_get_edge_tile", load().afm_get_edge_tile(self.handle, C.byref(e), C.byref(w)))
+        return int(e.value), int(w.value)
 
-    def set_edge_tile(self, edges: int):
-        check("afm_set_edge_tile", load().afm_set_edge_tile(self.handle, int(edges)))
+    def set_edge_tile(self, edges: int, waves: int):
+        check("afm_set_edge_tile", load().afm_set_edge_tile(self.handle, int(edges), int(waves)))
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -303,16 +304,17 @@ class Calculator:
         """Pick the model's edge-tile shape by timing this workload (see
         afm_tune_edge_tile); the list must be built.  Returns the chosen
         shape, the per-shape times (ms) and whether the cache answered."""
-        chosen, hit = C.c_int32(), C.c_int32()
-        ms = (C.c_double * 2)()
+        e, w, hit = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = (C.c_double * len(_abi.TILE_SHAPES))()
         with torch.cuda.device(self.model.device):
             check("afm_tune_edge_tile",
                   self.lib.afm_tune_edge_tile(self.model.handle, C.byref(self.sysd.struct()),
                                               C.byref(self.nl.struct()), C.byref(self.ws.ws),
-                                              cache_path.encode() if cache_path else None, C.byref(chosen), ms,
-                                              C.byref(hit), _stream_ptr(self.model.device)))
+                                              cache_path.encode() if cache_path else None, C.byref(e), C.byref(w),
+                                              ms, C.byref(hit), _stream_ptr(self.model.device)))
         self.state_gen += 1
-        return dict(tile=int(chosen.value), ms_64=float(ms[0]), ms_128=float(ms[1]), from_cache=bool(hit.value))
+        return dict(tile=(int(e.value), int(w.value)), from_cache=bool(hit.value),
+                    ms={f"{a}x{b}": float(ms[k]) for k, (a, b) in enumerate(_abi.TILE_SHAPES)})
 
     def model_n_params(self) -> int:
         return int(sum(b["size"] for b in param_layout(self.model.hp)))

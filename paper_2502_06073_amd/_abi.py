@@ -14,6 +14,7 @@ STATUS = {0: "AFM_OK", -1: "AFM_E_INVALID", -2: "AFM_E_CAPACITY", -3: "AFM_E_NON
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_SPECIES, FLAG_SKIN, FLAG_IMAGES = 1, 2, 4, 8, 16
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_fast": 3}
 STATIC_SCRATCH_BYTES = 256 << 20   # AFM_STATIC_SCRATCH_BYTES
+TILE_SHAPES = ((64, 8), (128, 16), (128, 8))   # edge-tile shapes, in the tuner's order
 
 
 class Hparams(C.Structure):
@@ -92,10 +93,11 @@ EXPORTS = {
     "afm_backward_forces_backward": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Workspace),
                                      C.c_void_p],
-    "afm_set_edge_tile": [C.c_void_p, C.c_int32],
-    "afm_get_edge_tile": [C.c_void_p, C.POINTER(C.c_int32)],
+    "afm_set_edge_tile": [C.c_void_p, C.c_int32, C.c_int32],
+    "afm_get_edge_tile": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "afm_tune_edge_tile": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(Workspace), C.c_char_p,
-                           C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p],
+                           C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                           C.POINTER(C.c_int32), C.c_void_p],
     "afm_md_step": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(MdState), C.c_int32,
                     C.POINTER(Workspace), C.c_void_p],
     "afm_trace_enable": [C.c_int32],

@@ -68,6 +68,7 @@ struct afm_model {
   afm_precision prec;          // AFM_FP32_PLAIN or AFM_BF16_MFMA
   bool fast_adjoint = false;   // AFM_BF16_MFMA_FAST_ADJOINT was asked for
   int edge_tile = 64;          // edges per workgroup tile of the BF16 MFMA chains (64 or 128)
+  int tile_waves = 8;          // wavefronts per workgroup (64: 8; 128: 16 or 8)
   afm::ModelDims dims;
   afm::Plan plan;
   int device;

@@ -258,17 +258,32 @@ static const uint4* frag_ptr(const afm_model* m, int64_t off) {
   return reinterpret_cast<const uint4*>(static_cast<const char*>(m->W.frag) + off);
 }
 
-// The edge-tile shape of a model's chains: 64 edges x 8 wavefronts (t64)
-// or 128 edges x 16 wavefronts (t128); chosen per model (afm_set_edge_tile,
-// or measured by afm_tune_edge_tile).
+// The edge-tile shapes of the chains, chosen per model (afm_set_edge_tile,
+// or measured by afm_tune_edge_tile):
+//   t64:   64 edges,  8 wavefronts of 4 column blocks, 4 wavefronts per SIMD
+//          (two workgroups per CU);
+//   t128:  128 edges, 16 wavefronts of 4 column blocks, 4 per SIMD (one
+//          workgroup per CU);
+//   t128w: 128 edges, 8 wavefronts of 8 column blocks, 2 per SIMD (one
+//          workgroup per CU): a weight fragment feeds twice the MFMAs, so
+//          the L2 weight stream per edge halves and each k-block's MFMAs
+//          cover more of its loads' latency, with half the wavefronts.
 namespace t64 {
-constexpr int NCB = 4;
+constexpr int NCB = 4, NCBW = 4, WPE = 4;
 #include "mfma_chain_tile.h"
 }  // namespace t64
 namespace t128 {
-constexpr int NCB = 8;
+constexpr int NCB = 8, NCBW = 4, WPE = 4;
 #include "mfma_chain_tile.h"
 }  // namespace t128
+namespace t128w {
+constexpr int NCB = 8, NCBW = 8, WPE = 2;
+#include "mfma_chain_tile.h"
+}  // namespace t128w
+
+// dispatch a launcher on the model's tile shape
+#define AFM_TILE_DISPATCH(m, call) \
+  ((m)->edge_tile == 128 ? ((m)->tile_waves == 8 ? t128w::call : t128::call) : t64::call)
 
 static int checked(const afm_model* m, int rc) { return rc == AFM_E_UNSUPPORTED ? mfma_check_shape(m) : rc; }
 
@@ -282,7 +297,7 @@ int mfma_twobody_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   a.xnew = ws_ptr<float>(ws, L.x[0]);
   a.omega = ws_ptr<uint16_t>(ws, L.omega[0]);
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
-  return checked(m, m->edge_tile == 128 ? t128::launch_tb_fwd(d, a, L, st) : t64::launch_tb_fwd(d, a, L, st));
+  return checked(m, AFM_TILE_DISPATCH(m, launch_tb_fwd(d, a, L, st)));
 }
 
 int mfma_twobody_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
@@ -293,8 +308,7 @@ int mfma_twobody_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout
   a.envb = frag_ptr(m, fo->envb[0]);
   for (int k = 0; k < d.ntb; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.tb_pre[k]);
   const bool fast = m->fast_adjoint;
-  return checked(m, m->edge_tile == 128 ? t128::launch_tb_bwd(d, fast, a, L, st)
-                                        : t64::launch_tb_bwd(d, fast, a, L, st));
+  return checked(m, AFM_TILE_DISPATCH(m, launch_tb_bwd(d, fast, a, L, st)));
 }
 
 int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer,
@@ -311,8 +325,7 @@ int mfma_latent_fwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   a.eps = ws_ptr<float>(ws, L.eps);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
   const bool last = layer == d.NL;
-  return checked(m, m->edge_tile == 128 ? t128::launch_lat_fwd(d, last, a, L, st)
-                                        : t64::launch_lat_fwd(d, last, a, L, st));
+  return checked(m, AFM_TILE_DISPATCH(m, launch_lat_fwd(d, last, a, L, st)));
 }
 
 int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer,
@@ -329,8 +342,7 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   if (layer < d.NL) a.envb = frag_ptr(m, fo->envb[layer]);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
   const bool last = layer == d.NL, fast = m->fast_adjoint;
-  return checked(m, m->edge_tile == 128 ? t128::launch_lat_bwd(d, last, fast, a, L, st)
-                                        : t64::launch_lat_bwd(d, last, fast, a, L, st));
+  return checked(m, AFM_TILE_DISPATCH(m, launch_lat_bwd(d, last, fast, a, L, st)));
 }
 
 }  // namespace afm

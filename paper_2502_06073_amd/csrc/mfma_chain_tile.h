@@ -1,12 +1,13 @@
 // Kernels and launchers of the BF16 MFMA chains for one edge-tile shape.
 // Included by mfma_chain.hip once per tile shape, inside a namespace that
-// defines NCB (16-edge column blocks per workgroup tile); everything here
-// depends on it.  A workgroup of NPS x NCB / NCBW wavefronts owns a tile of
-// TILE = 16 NCB edges: 8 pair slots times NCB / 4 column groups of 64 edges.
+// defines NCB (16-edge column blocks per workgroup tile), NCBW (column
+// blocks per wavefront) and WPE (wavefronts per SIMD the kernels are
+// compiled for); everything here depends on them.  A workgroup of
+// NPS x NCB / NCBW wavefronts owns a tile of TILE = 16 NCB edges: 8 pair
+// slots times NCB / NCBW column groups of 16 NCBW edges.
 
 constexpr int TILE = 16 * NCB;    // edges per workgroup
 constexpr int NPS = 8;            // output-row pair slots per workgroup
-constexpr int NCBW = 4;           // column blocks per wavefront
 constexpr int NWAVE = NPS * (NCB / NCBW);  // wavefronts: pair slot x column group
 constexpr int NTHR = 64 * NWAVE;
 static_assert(NCB % NCBW == 0, "whole column groups");
@@ -350,7 +351,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // two-body MLP + environment embedding of layer 1 (forward)
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_tb_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_tb_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int TL = NT == 3 ? T2 : T1;
@@ -455,7 +456,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 // latent MLP of one layer (forward) + next environment embedding or energies
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_lat_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_lat_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
   static_assert(NPW <= NPS, "one pair per pair slot");
@@ -568,7 +569,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 // adjoint of one latent layer: dE/dx^L -> dE/dx^{L-1}, dE/ds^L, dE/du
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST, int kSplitBwd>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_lat_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_lat_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
   static_assert(NPW <= NPS, "one pair per pair slot");
@@ -727,7 +728,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) 
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
 template <int T0, int T1, int T2, int W, int ENV, int kSplitBwd>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(4))) k_tb_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_tb_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int RBW = W / 16, RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), NPW = W / 32;

@@ -3,7 +3,8 @@
 // number of edges per atom of the tuned workload:
 //
 //   {
-//   "gfx950/w256/c64/l2/L2/d3/tb64-128-256/nb8/bf16/deg72": {"tile": 64, "ms_64": 11.3, "ms_128": 12.9},
+//   "gfx950/w256/c64/l2/L2/d3/tb64-128-256/nb8/bf16/deg72": {"edges": 64, "waves": 8,
+//       "ms_64x8": 11.3, "ms_128x16": 12.9, "ms_128x8": 10.8},   (one line)
 //   ...
 //   }
 //
@@ -20,9 +21,24 @@
 
 namespace afm {
 
+// the built shapes (edges per tile, wavefronts per workgroup), in the
+// order of TuneEntry::ms
+constexpr int kTileShapes = 3;
+constexpr int kTileEdges[kTileShapes] = {64, 128, 128};
+constexpr int kTileWaves[kTileShapes] = {8, 16, 8};
+inline const char* tile_shape_name(int s) {
+  static const char* names[kTileShapes] = {"64x8", "128x16", "128x8"};
+  return names[s];
+}
+inline int tile_shape_index(int edges, int waves) {
+  for (int s = 0; s < kTileShapes; ++s)
+    if (kTileEdges[s] == edges && kTileWaves[s] == waves) return s;
+  return -1;
+}
+
 struct TuneEntry {
-  int tile = 0;
-  double ms_64 = 0.0, ms_128 = 0.0;
+  int edges = 0, waves = 0;
+  double ms[kTileShapes] = {};
 };
 
 // Parses the entries of a cache file's text; lines that are not entries
@@ -46,13 +62,13 @@ inline std::map<std::string, TuneEntry> tune_cache_parse(const std::string& text
       *v = strtod(s, &end);
       return end != s;
     };
-    double tile = 0.0;
+    double edges = 0.0, waves = 0.0;
     TuneEntry e;
-    if (!num("tile", &tile)) continue;
-    e.tile = (int)tile;
-    if (e.tile != 64 && e.tile != 128) continue;
-    num("ms_64", &e.ms_64);
-    num("ms_128", &e.ms_128);
+    if (!num("edges", &edges) || !num("waves", &waves)) continue;
+    e.edges = (int)edges;
+    e.waves = (int)waves;
+    if (tile_shape_index(e.edges, e.waves) < 0) continue;
+    for (int s = 0; s < kTileShapes; ++s) num((std::string("ms_") + tile_shape_name(s)).c_str(), &e.ms[s]);
     out[key] = e;
   }
   return out;
@@ -62,10 +78,14 @@ inline std::string tune_cache_format(const std::map<std::string, TuneEntry>& m) 
   std::string s = "{\n";
   size_t k = 0;
   for (const auto& kv : m) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "\": {\"tile\": %d, \"ms_64\": %.6g, \"ms_128\": %.6g}", kv.second.tile,
-             kv.second.ms_64, kv.second.ms_128);
-    s += "\"" + kv.first + buf + (++k < m.size() ? ",\n" : "\n");
+    std::string line = "\"" + kv.first + "\": {\"edges\": " + std::to_string(kv.second.edges) +
+                       ", \"waves\": " + std::to_string(kv.second.waves);
+    for (int q = 0; q < kTileShapes; ++q) {
+      char buf[64];
+      snprintf(buf, sizeof buf, ", \"ms_%s\": %.6g", tile_shape_name(q), kv.second.ms[q]);
+      line += buf;
+    }
+    s += line + "}" + (++k < m.size() ? ",\n" : "\n");
   }
   s += "}\n";
   return s;

@@ -35,25 +35,33 @@ using namespace afm;
 
 extern "C" {
 
-int afm_set_edge_tile(afm_model* m, int32_t edges) {
+int afm_set_edge_tile(afm_model* m, int32_t edges, int32_t waves) {
   if (!m) { set_error("null model"); return AFM_E_INVALID; }
-  if (edges != 64 && edges != 128) { set_error("edge tile must be 64 or 128"); return AFM_E_INVALID; }
+  if (tile_shape_index(edges, waves) < 0) {
+    set_error("edge-tile shape must be 64x8, 128x16 or 128x8 (edges x wavefronts)");
+    return AFM_E_INVALID;
+  }
   m->edge_tile = edges;
+  m->tile_waves = waves;
   return AFM_OK;
 }
 
-int afm_get_edge_tile(const afm_model* m, int32_t* edges) {
-  if (!m || !edges) { set_error("null argument"); return AFM_E_INVALID; }
-  *edges = m->prec == AFM_BF16_MFMA ? m->edge_tile : 0;
+int afm_get_edge_tile(const afm_model* m, int32_t* edges, int32_t* waves) {
+  if (!m || !edges || !waves) { set_error("null argument"); return AFM_E_INVALID; }
+  const bool mfma = m->prec == AFM_BF16_MFMA;
+  *edges = mfma ? m->edge_tile : 0;
+  *waves = mfma ? m->tile_waves : 0;
   return AFM_OK;
 }
 
 int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl, const afm_workspace* ws,
-                       const char* cache_path, int32_t* chosen, double* ms, int32_t* from_cache, void* stream) {
-  if (!m || !sys || !nl || !ws || !chosen) { set_error("null argument"); return AFM_E_INVALID; }
-  if (ms) ms[0] = ms[1] = 0.0;
+                       const char* cache_path, int32_t* edges, int32_t* waves, double* ms, int32_t* from_cache,
+                       void* stream) {
+  if (!m || !sys || !nl || !ws || !edges || !waves) { set_error("null argument"); return AFM_E_INVALID; }
+  if (ms)
+    for (int q = 0; q < kTileShapes; ++q) ms[q] = 0.0;
   if (from_cache) *from_cache = 0;
-  if (m->prec != AFM_BF16_MFMA) { *chosen = 0; return AFM_OK; }   // no MFMA chains to tune
+  if (m->prec != AFM_BF16_MFMA) { *edges = *waves = 0; return AFM_OK; }   // no MFMA chains to tune
   hipStream_t st = (hipStream_t)stream;
   int64_t n_edges = 0;
   AFM_HIP_CHECK(hipMemcpyAsync(&n_edges, nl->n_edges, sizeof n_edges, hipMemcpyDeviceToHost, st));
@@ -61,9 +69,10 @@ int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl,
   const std::string key = tune_key(m, sys->n_atoms, n_edges);
   TuneEntry e;
   if (tune_cache_lookup(cache_path, key, &e)) {
-    m->edge_tile = e.tile;
-    *chosen = e.tile;
-    if (ms) { ms[0] = e.ms_64; ms[1] = e.ms_128; }
+    m->edge_tile = *edges = e.edges;
+    m->tile_waves = *waves = e.waves;
+    if (ms)
+      for (int q = 0; q < kTileShapes; ++q) ms[q] = e.ms[q];
     if (from_cache) *from_cache = 1;
     return AFM_OK;
   }
@@ -74,15 +83,15 @@ int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl,
   double *e_atom = buf, *e_struct = buf + N, *F = e_struct + B, *W = F + 3 * N;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   int rc = AFM_OK;
-  const int tiles[2] = {64, 128};
-  double t_ms[2] = {0.0, 0.0};
-  const int keep = m->edge_tile;
+  double t_ms[kTileShapes] = {};
+  const int keep_e = m->edge_tile, keep_w = m->tile_waves;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
     set_error("hipEventCreate failed");
     rc = AFM_E_HIP;
   }
-  for (int v = 0; v < 2 && !rc; ++v) {
-    m->edge_tile = tiles[v];
+  for (int v = 0; v < kTileShapes && !rc; ++v) {
+    m->edge_tile = kTileEdges[v];
+    m->tile_waves = kTileWaves[v];
     rc = afm_energy_forces(m, sys, nl, e_atom, e_struct, F, W, ws, stream);   // warm-up
     const int reps = 3;
     if (!rc && hipEventRecord(t0, st) != hipSuccess) rc = AFM_E_HIP;
@@ -99,15 +108,18 @@ int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl,
   if (t1) (void)hipEventDestroy(t1);
   (void)hipStreamSynchronize(st);
   (void)hipFree(buf);
-  if (rc) { m->edge_tile = keep; return rc; }
-  const int best = t_ms[1] < t_ms[0] ? 128 : 64;
-  m->edge_tile = best;
-  *chosen = best;
-  if (ms) { ms[0] = t_ms[0]; ms[1] = t_ms[1]; }
+  if (rc) { m->edge_tile = keep_e; m->tile_waves = keep_w; return rc; }
+  int best = 0;
+  for (int v = 1; v < kTileShapes; ++v)
+    if (t_ms[v] < t_ms[best]) best = v;
+  m->edge_tile = *edges = kTileEdges[best];
+  m->tile_waves = *waves = kTileWaves[best];
+  if (ms)
+    for (int q = 0; q < kTileShapes; ++q) ms[q] = t_ms[q];
   if (cache_path) {
-    e.tile = best;
-    e.ms_64 = t_ms[0];
-    e.ms_128 = t_ms[1];
+    e.edges = kTileEdges[best];
+    e.waves = kTileWaves[best];
+    for (int q = 0; q < kTileShapes; ++q) e.ms[q] = t_ms[q];
     if (!tune_cache_store(cache_path, key, e)) {
       set_error(std::string("could not write the tuning cache ") + cache_path);
       return AFM_E_INVALID;
