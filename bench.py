@@ -78,6 +78,19 @@ def stage_roofline(costs, stats, n_edges, n_atoms, evals):
     return out
 
 
+FORCED_TILE = None   # (edges, waves) from --edge-tile, else the tuner decides
+
+
+def choose_tile(calc):
+    """Edge-tile shape of the BF16 chains: the tuner's choice on this
+    workload, or the shape given on the command line (profiler runs fix it,
+    since counter collection slows kernels unevenly)."""
+    if FORCED_TILE is None or calc.model.precision not in ("bf16", "bf16_fast"):
+        return calc.tune_edge_tile()
+    calc.model.set_edge_tile(*FORCED_TILE)
+    return {"tile": FORCED_TILE, "from_cache": False, "ms": "fixed by --edge-tile"}
+
+
 def setup(config, precision):
     import torch
     import synth
@@ -89,7 +102,7 @@ def setup(config, precision):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]))
     calc.build_neighbors()
-    calc.tune = calc.tune_edge_tile()
+    calc.tune = choose_tile(calc)
     torch.cuda.synchronize()
     return hp, s, w, calc
 
@@ -259,7 +272,7 @@ def bench_md(a):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp["r_list"], max_bytes=max_bytes)
     calc.build_neighbors()
-    tune = calc.tune_edge_tile()
+    tune = choose_tile(calc)
     print(f"[bench] E: edge tile {tune['tile']} (ms per evaluation: {tune['ms']})", file=sys.stderr, flush=True)
     o16 = calc.energy_forces(virial=False)
     torch.cuda.synchronize()
@@ -441,7 +454,7 @@ def bench_batch(a):
     sysd = afm.DeviceSystem.from_synth(s)
     calc = afm.Calculator(model, sysd, r_list=hp.get("r_list", hp["r_cut"]))
     calc.build_neighbors()
-    tune = calc.tune_edge_tile()
+    tune = choose_tile(calc)
     dt_eager, out_, stats = time_steps(calc, a.steps, a.warmup, trace=True)
     n_edges = int(calc.nl.n_edges.item())
     # captured step, replayed
@@ -526,6 +539,8 @@ def main(argv=None):
     ap.add_argument("--no-fast", action="store_true", help="skip timing the fast-adjoint variant")
     ap.add_argument("--max-gib", type=float, default=96.0,
                     help="workspace limit for the 1M-atom MD workload (row chunks beyond it)")
+    ap.add_argument("--edge-tile", default="", metavar="EDGESxWAVES",
+                    help="fix the BF16 chains' edge-tile shape (64x8, 128x16, 128x8) instead of tuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -539,6 +554,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_probe_bytes=4 * n)), flush=True)
         return 0
+    if a.edge_tile:
+        global FORCED_TILE
+        FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
               f"--gpus {a.gpus} is not supported", file=sys.stderr)

@@ -92,7 +92,7 @@ typedef struct {
   int32_t l_max;          /* 0, 1 or 2 */
   int32_t n_layers;       /* >= 1 */
   int32_t latent;         /* latent width w (multiple of 16) */
-  int32_t channels;       /* tensor channels c (multiple of 8, <= 256) */
+  int32_t channels;       /* tensor channels c: 8, 16, 32, 64 or 128 */
   int32_t n_bessel;       /* <= 16 */
   int32_t poly_p;         /* envelope power p >= 2 */
   int32_t n_twobody;      /* 1..4 */
@@ -300,7 +300,9 @@ int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
  * last with twice the columns per wavefront).  Every edge's result is the
  * same with any shape (bit for bit); only the speed differs.  The shape is
  * a property of the model (default 64 x 8) and must not change between
- * afm_forward_energy and the afm_backward_forces that follows it.  For FP32
+ * afm_forward_energy and the afm_backward_forces that follows it.  Latent
+ * widths above 256 are built for 64 x 8 only (AFM_E_UNSUPPORTED otherwise;
+ * the tuner skips the other shapes and reports -1 for them).  For FP32
  * models the shape has no effect (afm_get_edge_tile reports 0 x 0). */
 int afm_set_edge_tile(afm_model* model, int32_t edges, int32_t waves);
 int afm_get_edge_tile(const afm_model* model, int32_t* edges /*host*/, int32_t* waves /*host*/);

@@ -45,6 +45,9 @@ struct TPArgs {
   const float* gs;       // dE/ds^L
   void* gomega;          // dE/domega^L [t][lmax+1][C]
   float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
+  // first channel of this launch: a launch covers channels [c0, c0 + C)
+  // of the arrays' channels (the products are channelwise)
+  int c0;
 };
 
 int launch_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const TPArgs& a, int64_t n_atoms_max,

@@ -204,6 +204,10 @@ struct ChainArgs {
   X(64, 16, 2, 3, 16, 32, 64, 3)            \
   X(128, 32, 2, 3, 32, 64, 128, 3)          \
   X(256, 64, 2, 3, 64, 128, 256, 3)
+// the 512-wide model (Table 1's largest: c = 128, two-body [128, 256, 512]);
+// its LDS tiles fit only the 64-edge shape
+#define AFM_SHAPES_WIDE(X)                  \
+  X(512, 128, 2, 3, 128, 256, 512, 3)
 
 static bool shape_is(const ModelDims& d, int w, int c, int lmax, int depth, int t0, int t1, int t2, int n0e) {
   if (d.w != w || d.c != c || d.lmax != lmax || d.depth != depth) return false;
@@ -217,12 +221,18 @@ static bool shape_is(const ModelDims& d, int w, int c, int lmax, int depth, int 
 }
 
 int mfma_check_shape(const afm_model* m) {
-#define X(w, c, l, dp, a0, a1, a2, n0) \
-  if (shape_is(m->dims, w, c, l, dp, a0, a1, a2, n0)) return AFM_OK;
+#define X(w, c, l, dp, a0, a1, a2, n0)                                            \
+  if (shape_is(m->dims, w, c, l, dp, a0, a1, a2, n0)) {                          \
+    if (m->edge_tile == 64 || w <= 256) return AFM_OK;                           \
+    set_error("latent widths above 256 are built for 64-edge tiles only");       \
+    return AFM_E_UNSUPPORTED;                                                    \
+  }
   AFM_SHAPES(X)
+  AFM_SHAPES_WIDE(X)
 #undef X
   set_error("BF16 MFMA kernels are built for (w, c, l_max, depth, two-body) = (32,8,1,2,[16,32]), "
-            "(64,16,2,3,[16,32,64]), (128,32,2,3,[32,64,128]), (256,64,2,3,[64,128,256])");
+            "(64,16,2,3,[16,32,64]), (128,32,2,3,[32,64,128]), (256,64,2,3,[64,128,256]), "
+            "(512,128,2,3,[128,256,512]; 64-edge tiles only)");
   return AFM_E_UNSUPPORTED;
 }
 
@@ -270,7 +280,9 @@ static const uint4* frag_ptr(const afm_model* m, int64_t off) {
 //          cover more of its loads' latency, with half the wavefronts.
 namespace t64 {
 constexpr int NCB = 4, NCBW = 4, WPE = 4;
+#define AFM_TILE_WIDE 1
 #include "mfma_chain_tile.h"
+#undef AFM_TILE_WIDE
 }  // namespace t64
 namespace t128 {
 constexpr int NCB = 8, NCBW = 4, WPE = 4;

@@ -12,6 +12,12 @@ constexpr int NWAVE = NPS * (NCB / NCBW);  // wavefronts: pair slot x column gro
 constexpr int NTHR = 64 * NWAVE;
 static_assert(NCB % NCBW == 0, "whole column groups");
 
+// Latent widths above 256 (more output-row pairs than pair slots) give each
+// wavefront NPP pairs, pslot + j NPS; their LDS tiles leave one workgroup
+// per CU, so those kernels are compiled for 2 wavefronts per SIMD.
+template <int W>
+constexpr int wpe_for() { return W > 256 ? 2 : WPE; }
+
 // ---------------------------------------------------------------------------
 // device building blocks
 
@@ -351,7 +357,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // two-body MLP + environment embedding of layer 1 (forward)
 
 template <int T0, int T1, int T2, int W, int ENV>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_tb_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_for<W>()))) k_tb_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int TL = NT == 3 ? T2 : T1;
@@ -456,14 +462,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
 // latent MLP of one layer (forward) + next environment embedding or energies
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_lat_fwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_for<W>()))) k_lat_fwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
-  static_assert(NPW <= NPS, "one pair per pair slot");
+  constexpr int NPP = cdiv(NPW, NPS);   // output-row pairs per wavefront
+  static_assert(NPP == 1 || NPW % NPS == 0, "whole pairs per pair slot");
   const float r2 = 0.70710678118654752f;
   __shared__ ChainSmem<cmax(W, KS)> S;
-  const int pair = pslot;
-  const bool mine = pair < NPW;
+  const bool mine = pslot < NPW;
+  auto pair_of = [&](int j) { return pslot + j * NPS; };
   float ep[NCBW];
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) ep[cb] = 0.0f;
@@ -496,9 +503,11 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
     };
   };
   // layer 0 over [x | s]: x staged in one buffer, s in the other; the
-  // output overwrites the x buffer after a barrier
-  f32x4 acc[2][NCBW];
-  zero_acc(acc);
+  // output overwrites the x buffer after a barrier (so every pair of the
+  // wavefront keeps its accumulators across it)
+  f32x4 acc0[NPP][2][NCBW];
+#pragma unroll
+  for (int j = 0; j < NPP; ++j) zero_acc(acc0[j]);
   {
     // x and s loads all in flight together
     Stager<W, true> sx;
@@ -510,41 +519,43 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
   }
   __syncthreads();
   if (mine) {
-    mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc, half, lane);
-    mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[1], acc, half, lane);
-  }
-  __syncthreads();
-  if constexpr (DEPTH == 1) {
-    if (mine) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int cb = 0; cb < NCBW; ++cb) {
-          const int64_t t = col_t(cb);
-          xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
-        }
+    for (int j = 0; j < NPP; ++j) {
+      mma_pair<KB0, KBX>(a.latf[0], pair_of(j), 0, S.act[0], acc0[j], half, lane);
+      mma_pair<KB0, KB0 - KBX>(a.latf[0], pair_of(j), KBX, S.act[1], acc0[j], half, lane);
     }
   }
-  if (mine)
-    finish_pair(pair, acc, (LAST && DEPTH == 1) ? nullptr : S.act[0], epi(std::integral_constant<int, 0>{}),
-                half, lane);
+  __syncthreads();
+  auto load_xpf = [&](int pair) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int cb = 0; cb < NCBW; ++cb) {
+        const int64_t t = col_t(cb);
+        xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
+      }
+  };
+  if (mine) {
+#pragma unroll
+    for (int j = 0; j < NPP; ++j) {
+      if constexpr (DEPTH == 1) load_xpf(pair_of(j));
+      finish_pair(pair_of(j), acc0[j], (LAST && DEPTH == 1) ? nullptr : S.act[0],
+                  epi(std::integral_constant<int, 0>{}), half, lane);
+    }
+  }
   __syncthreads();
   int cur = 0;
   static_for<1, DEPTH>([&](auto K) __attribute__((always_inline)) {
     constexpr int k = decltype(K)::value;
     if (mine) {
-      zero_acc(acc);
-      mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, half, lane);
-      if constexpr (k == DEPTH - 1) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int cb = 0; cb < NCBW; ++cb) {
-            const int64_t t = col_t(cb);
-            xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
-          }
+      for (int j = 0; j < NPP; ++j) {
+        f32x4 acc[2][NCBW];
+        zero_acc(acc);
+        mma_pair<KBX, KBX>(a.latf[k], pair_of(j), 0, S.act[cur], acc, half, lane);
+        if constexpr (k == DEPTH - 1) load_xpf(pair_of(j));
+        finish_pair(pair_of(j), acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(K), half, lane);
       }
-      finish_pair(pair, acc, (LAST && k == DEPTH - 1) ? nullptr : S.act[cur ^ 1], epi(K), half, lane);
     }
     __syncthreads();
     cur ^= 1;
@@ -569,14 +580,15 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
 // adjoint of one latent layer: dE/dx^L -> dE/dx^{L-1}, dE/ds^L, dE/du
 
 template <int W, int KS, int ENV, int DEPTH, bool LAST, int kSplitBwd>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_lat_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_for<W>()))) k_lat_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int RBW = W / 16, KBX = W / 32, NPW = W / 32;
-  static_assert(NPW <= NPS, "one pair per pair slot");
+  constexpr int NPP = cdiv(NPW, NPS);   // output-row pairs per wavefront
+  static_assert(NPP == 1 || NPW % NPS == 0, "whole pairs per pair slot");
   const float r2 = 0.70710678118654752f;
   __shared__ ChainSmem<cmax(W, ENV)> S;
-  const int pair = pslot;
-  const bool mine = pair < NPW;
+  const bool mine = pslot < NPW;
+  auto pair_of = [&](int j) { return pslot + j * NPS; };
   float gu[NCBW];
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
@@ -618,33 +630,39 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
       float ce[NCBW];
 #pragma unroll
       for (int cb = 0; cb < NCBW; ++cb) ce[cb] = edge_coef(cb);
-      f32x4 acc[2][NCBW];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const f32x4 we = ld4(a.w_eff + 16 * (2 * pair + r) + 4 * g);
+      for (int j = 0; j < NPP; ++j) {
+        f32x4 acc[2][NCBW];
 #pragma unroll
-        for (int cb = 0; cb < NCBW; ++cb)
+        for (int r = 0; r < 2; ++r) {
+          const f32x4 we = ld4(a.w_eff + 16 * (2 * pair_of(j) + r) + 4 * g);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[r][cb][q] = ce[cb] * we[q];
+          for (int cb = 0; cb < NCBW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[r][cb][q] = ce[cb] * we[q];
+        }
+        finish_pair(pair_of(j), acc, S.act[0], head, half, lane);
       }
-      finish_pair(pair, acc, S.act[0], head, half, lane);
     }
   } else {
     // dE/dx^L = (stored) + W_env^{L+1 T} dE/domega^{L+1}
     stage_rows_bf16<ENV>(S.act[1], a.gomega, tile, M, tid);
     __syncthreads();
     if (mine) {
-      f32x4 acc[2][NCBW];
-      zero_acc(acc);
-      mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, pair, 0, S.act[1], acc, half, lane);
-      finish_pair(
-          pair, acc, S.act[0],
-          [&](int rb, int cb, f32x4& v) {
-            const int64_t t = col_t(cb);
-            if (t < M) v += ld4(a.gx + t * W + 16 * rb + 4 * g);
-            head(rb, cb, v);
-          },
-          half, lane);
+#pragma unroll
+      for (int j = 0; j < NPP; ++j) {
+        f32x4 acc[2][NCBW];
+        zero_acc(acc);
+        mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, pair_of(j), 0, S.act[1], acc, half, lane);
+        finish_pair(
+            pair_of(j), acc, S.act[0],
+            [&](int rb, int cb, f32x4& v) {
+              const int64_t t = col_t(cb);
+              if (t < M) v += ld4(a.gx + t * W + 16 * rb + 4 * g);
+              head(rb, cb, v);
+            },
+            half, lane);
+      }
     }
   }
 #pragma unroll
@@ -656,17 +674,20 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
   static_for<1, DEPTH>([&](auto KK) __attribute__((always_inline)) {
     constexpr int k = DEPTH - decltype(KK)::value;
     if (mine) {
-      f32x4 acc[2][NCBW];
-      zero_acc(acc);
-      mma_pair<KBX, KBX, kSplitBwd>(a.latb[k], pair, 0, S.act[cur], acc, half, lane);
-      finish_pair(
-          pair, acc, S.act[cur ^ 1],
-          [&](int rb, int cb, f32x4& v) {
-            const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, cbA(cb), lane);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
-          },
-          half, lane);
+      for (int j = 0; j < NPP; ++j) {
+        f32x4 acc[2][NCBW];
+        zero_acc(acc);
+        mma_pair<KBX, KBX, kSplitBwd>(a.latb[k], pair_of(j), 0, S.act[cur], acc, half, lane);
+        finish_pair(
+            pair_of(j), acc, S.act[cur ^ 1],
+            [&](int rb, int cb, f32x4& v) {
+              const f32x4 pa = ld_pre(a.pre[k - 1], tile, RBW, rb, cbA(cb), lane);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) v[q] *= dsilu_of(pa[q]);
+            },
+            half, lane);
+      }
     }
     __syncthreads();
     cur ^= 1;
@@ -728,14 +749,14 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
 template <int T0, int T1, int T2, int W, int ENV, int kSplitBwd>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))) k_tb_bwd(ChainArgs a) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_for<W>()))) k_tb_bwd(ChainArgs a) {
   AFM_TILE_PROLOGUE
   constexpr int NT = T2 ? 3 : 2;
   constexpr int RBW = W / 16, RB0 = cdiv(T0, 16), RB1 = cdiv(T1, 16), NPW = W / 32;
-  static_assert(NPW <= NPS, "one pair per pair slot");
+  constexpr int NPP = cdiv(NPW, NPS);   // output-row pairs per wavefront
+  static_assert(NPP == 1 || NPW % NPS == 0, "whole pairs per pair slot");
   __shared__ ChainSmem<cmax(cmax(ENV, W), T1)> S;
-  const int pair = pslot;
-  const bool mine = pair < NPW;
+  const bool mine = pslot < NPW;
   float gu[NCBW];
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) gu[cb] = 0.0f;
@@ -743,6 +764,9 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
   stage_rows_bf16<ENV>(S.act[1], a.gomega, tile, M, tid);
   __syncthreads();
   if (mine) {
+#pragma unroll
+  for (int j = 0; j < NPP; ++j) {
+    const int pair = pslot + j * NPS;
     f32x4 acc[2][NCBW];
     zero_acc(acc);
     mma_pair<cdiv(ENV, 32), cdiv(ENV, 32), kSplitEnv>(a.envb, pair, 0, S.act[1], acc, half, lane);
@@ -761,6 +785,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(WPE))
           }
         },
         half, lane);
+  }
   }
 #pragma unroll
   for (int cb = 0; cb < NCBW; ++cb) gu[cb] = sum_groups(gu[cb]);
@@ -867,6 +892,9 @@ static int launch_tb_fwd(const ModelDims& d, const ChainArgs& a, const WsLayout&
     return AFM_OK;                                                                                 \
   }
   AFM_SHAPES(X)
+#ifdef AFM_TILE_WIDE
+  AFM_SHAPES_WIDE(X)
+#endif
 #undef X
   return AFM_E_UNSUPPORTED;
 }
@@ -882,6 +910,9 @@ static int launch_tb_bwd(const ModelDims& d, bool fast, const ChainArgs& a, cons
     return AFM_OK;                                                                                 \
   }
   AFM_SHAPES(X)
+#ifdef AFM_TILE_WIDE
+  AFM_SHAPES_WIDE(X)
+#endif
 #undef X
   return AFM_E_UNSUPPORTED;
 }
@@ -897,6 +928,9 @@ static int launch_lat_fwd(const ModelDims& d, bool last, const ChainArgs& a, con
     return AFM_OK;                                                                                      \
   }
   AFM_SHAPES(X)
+#ifdef AFM_TILE_WIDE
+  AFM_SHAPES_WIDE(X)
+#endif
 #undef X
   return AFM_E_UNSUPPORTED;
 }
@@ -919,6 +953,9 @@ static int launch_lat_bwd(const ModelDims& d, bool last, bool fast, const ChainA
     return AFM_OK;                                                                                      \
   }
   AFM_SHAPES(X)
+#ifdef AFM_TILE_WIDE
+  AFM_SHAPES_WIDE(X)
+#endif
 #undef X
   return AFM_E_UNSUPPORTED;
 }

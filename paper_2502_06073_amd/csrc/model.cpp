@@ -32,8 +32,8 @@ static int dims_of(const afm_hparams* hp, ModelDims* d) {
   if (hp->twobody[hp->n_twobody - 1] != hp->latent) { set_error("last two-body width must equal latent"); return AFM_E_INVALID; }
   for (int k = 0; k < hp->n_twobody; ++k)
     if (hp->twobody[k] < 1) { set_error("bad two-body width"); return AFM_E_INVALID; }
-  if (hp->channels != 8 && hp->channels != 16 && hp->channels != 32 && hp->channels != 64) {
-    set_error("channels must be 8, 16, 32 or 64"); return AFM_E_UNSUPPORTED;
+  if (hp->channels != 8 && hp->channels != 16 && hp->channels != 32 && hp->channels != 64 && hp->channels != 128) {
+    set_error("channels must be 8, 16, 32, 64 or 128"); return AFM_E_UNSUPPORTED;
   }
   if (hp->n_bessel < 1 || hp->n_bessel > 16) { set_error("n_bessel must be 1..16"); return AFM_E_INVALID; }
   if (hp->poly_p < 2) { set_error("poly_p must be >= 2"); return AFM_E_INVALID; }

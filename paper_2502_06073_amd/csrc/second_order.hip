@@ -1046,6 +1046,11 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   TraceScope tr(st, "second_order");
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
+  for (int layer = 1; layer <= d.NL; ++layer)   // refuse before launching anything
+    if (!pick_tp2(d.lmax, d.NL, layer, d.c, false) || !pick_tp2(d.lmax, d.NL, layer, d.c, true)) {
+      set_error("second-order tensor-product kernel not built for this shape");
+      return AFM_E_UNSUPPORTED;
+    }
   const int stack = (int)L.cex;
   const int64_t E2 = 2 * (int64_t)stack;
   const int env = (d.lmax + 1) * d.c;

@@ -1,22 +1,17 @@
 // Environment sums and channelwise Clebsch-Gordan tensor products (the
 // "tensor features ... l = 2 in full O(3)" of Methodology / Model Training).
 //
-// One workgroup per central atom i (all edges of row i): 256 threads =
-// (256 / C) edge slots x C channels, channel fastest so every load is
-// coalesced over channels.
+// One group of C lanes (one lane per channel) per central atom:
 //   forward:  Gamma_i[lm][n] = nbar^-1/2 sum_{e in row i} omega_e[l][n] Y_e[lm]
 //             T^pi_e[m3][n] = sum C^{l1 l2 l3}[m1][m2][m3] V_e[l1 p1, m1][n] Gamma_i[l2 m2][n]
 //             s_e (0e paths), V'_e = sum_pi alpha[pi][n] T^pi_e   (next layer)
-//   backward: the adjoints of both lines; dE/dGamma_i is accumulated per
-//             thread over the row's edges (9 registers) and reduced over the
-//             edge slots in LDS.
-// Per-edge tensor features never go to memory: V^{L-1} is rebuilt from
-// V^0 = omega^1 (x) Y through the earlier layers' Gammas, and dE/dV^L from
-// the later layers' dE/ds and Gammas, a few hundred FLOP per channel in
-// place of 2-4 KB per edge written and read back.
-// The sums run over the nonzero CG entries only, unrolled with immediate
-// coefficients from the compile-time tables (cg_ct.h); Gamma_i of the
-// thread's channel stays in registers for the whole row.
+//   backward: the adjoints of both lines.
+// With the Gammas fixed, an edge's tensor track is linear in its layer-1
+// input V^0 = omega^1 (x) Y, so the kernels form small per-atom, per-channel
+// linear maps once per row and apply them per edge; per-edge tensor features
+// and their adjoints never go to memory.  The products run over the nonzero
+// CG entries only, unrolled with immediate coefficients from the
+// compile-time tables (cg_ct.h).
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -54,301 +49,429 @@ __device__ __forceinline__ void add_channel_sums(float (&v)[16], float* dst, int
   }
 }
 
-template <int LMAX, int NL, int L>
+template <int LMAX, int NL, int K>
 struct LayerCT {
-  static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
+  static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[K - 1];
 };
 
-// Gamma of layers L0 + 1 .. L0 + NG of atom i, channel n (registers)
-template <int LMAX, int L0, int NG, int C, int ND>
-__device__ __forceinline__ void load_gammas(const TPArgs& a, int64_t i, int n,
-                                            float (&Gs)[ND][(LMAX + 1) * (LMAX + 1)]) {
+// components of V^J (J = 0: the layer-1 inputs omega^1 (x) Y, index l*l+m)
+template <int LMAX, int NL, int J>
+constexpr int n_comps() {
+  if constexpr (J == 0) return (LMAX + 1) * (LMAX + 1);
+  else return LayerCT<LMAX, NL, J>::lp.n_out_comps;
+}
+
+constexpr int scalar_path_of(const LayerPlan& lp, int s) {
+  for (int k = 0; k < lp.n_paths; ++k)
+    if (lp.p[k].s_idx == s) return k;
+  return -1;
+}
+
+// dE/ds inputs of the layer-L adjoint: the scalar slots of layers L..NL,
+// layer by layer; slot b belongs to layer slot_layer(b), index slot_sub(b)
+template <int LMAX, int NL, int L>
+struct Slots {
+  static constexpr int count() {
+    int n = 0;
+    for (int K = L; K <= NL; ++K) n += PlanCT<LMAX, NL>::plan.layer[K - 1].n0e;
+    return n;
+  }
+  static constexpr int layer(int b) {
+    for (int K = L; K <= NL; ++K) {
+      const int n0 = PlanCT<LMAX, NL>::plan.layer[K - 1].n0e;
+      if (b < n0) return K;
+      b -= n0;
+    }
+    return -1;
+  }
+  static constexpr int sub(int b) {
+    for (int K = L; K <= NL; ++K) {
+      const int n0 = PlanCT<LMAX, NL>::plan.layer[K - 1].n0e;
+      if (b < n0) return b;
+      b -= n0;
+    }
+    return -1;
+  }
+};
+
+// the scalar path feeding slot S of layer K and the block of V^{K-1} it reads
+template <int LMAX, int NL, int K, int S>
+struct UnitCT {
+  static constexpr PathT pt = LayerCT<LMAX, NL, K>::lp.p[scalar_path_of(LayerCT<LMAX, NL, K>::lp, S)];
+  static constexpr int off = pt.in_off, len = 2 * pt.l1 + 1;
+};
+
+// Gamma of layers 1..NG of atom i, channel nc (G[K-1] = Gamma^K)
+template <int LMAX, int NL, int NG, int CS>
+__device__ __forceinline__ void load_gammas(const TPArgs& a, int64_t i, int nc,
+                                            float (&G)[NL][(LMAX + 1) * (LMAX + 1)]) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
-  static_assert(NG <= ND, "gamma registers");
 #pragma unroll
   for (int l = 0; l < NG; ++l)
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) Gs[l][q] = a.gamma_l[L0 + l][(i * NLM + q) * C + n];
+    for (int q = 0; q < NLM; ++q) G[l][q] = a.gamma_l[l][(i * NLM + q) * CS + nc];
 }
 
-template <int LMAX, int NL, int L, int K>
-__device__ __forceinline__ void path_fwd(const float* V, const float* G, float* T);
-
-// Output features of layer K (V^K, the input of layer K + 1) for edge t,
-// channel n, recomputed from V^0 = omega^1 (x) Y through layers 1..K with
-// Gamma^l = Gp[l - 1] and the mixing weights alpha^l.
-template <int LMAX, int NL, int K, int C, bool B16, int NG>
-__device__ __forceinline__ void recompute_V(const TPArgs& a, int64_t t, int n, const float* Y,
-                                            const float (&Gp)[NG][(LMAX + 1) * (LMAX + 1)], float* V) {
-  if constexpr (K == 0) {
+// Layer K forward on given input features: V^K = sum over paths with an
+// output of alpha^K (C V^{K-1} Gamma^K).
+template <int LMAX, int NL, int K, int CS>
+__device__ __forceinline__ void fwd_layer(const TPArgs& a, int nc, const float* G, const float* vin, float* vout) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, K>::lp;
 #pragma unroll
-    for (int l = 0; l <= LMAX; ++l) {
-      const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * C + n);
-#pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) V[l * l + m] = w * Y[l * l + m];
-    }
-  } else {
-    constexpr LayerPlan LP = PlanCT<LMAX, NL>::plan.layer[K - 1];
-    float Vin[LP.n_in_comps];
-    recompute_V<LMAX, NL, K - 1, C, B16, NG>(a, t, n, Y, Gp, Vin);
-#pragma unroll
-    for (int q = 0; q < LP.n_out_comps; ++q) V[q] = 0.0f;
-    static_for<0, LP.n_paths>([&](auto P) {
-      constexpr int k = decltype(P)::value;
-      constexpr PathT pt = LP.p[k];
-      if constexpr (pt.out_off >= 0) {
-        float T[2 * pt.l3 + 1];
-        path_fwd<LMAX, NL, K, k>(Vin, Gp[K - 1], T);
-        const float al = a.alpha_l[K - 1][k * C + n];
-#pragma unroll
-        for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) V[pt.out_off + m3] += al * T[m3];
-      }
-    });
-  }
-}
-
-// T^pi[m3] = sum over the nonzeros of C^{l1 l2 l3}: C V[m1] Gamma[m2]
-template <int LMAX, int NL, int L, int K>
-__device__ __forceinline__ void path_fwd(const float* V, const float* G, float* T) {
-  constexpr PathT pt = LayerCT<LMAX, NL, L>::lp.p[K];
-  constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
-#pragma unroll
-  for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) T[m3] = 0.0f;
-  static_for<0, nz.n>([&](auto Q) {
-    constexpr int q = decltype(Q)::value;
-    T[nz.m3[q]] += nz.c[q] * V[pt.in_off + nz.m1[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
-  });
-}
-
-// dE/dV^K (K < NL) of edge t, channel n: the adjoint of layer K + 1's
-// products, dE/dV^K[m1] = sum over paths and nonzeros of
-// C dE/dT^{K+1}[m3] Gamma^{K+1}[m2], where dE/dT^{K+1} = dE/ds^{K+1} on the
-// 0e paths plus alpha^{K+1} dE/dV^{K+1} (rebuilt the same way) on the
-// others.  Gn[j] holds Gamma^{L+1+j} (registers).
-template <int LMAX, int NL, int L, int K, int C, int NG>
-__device__ __forceinline__ void recompute_gV(const TPArgs& a, int64_t t, int n,
-                                             const float (&Gn)[NG][(LMAX + 1) * (LMAX + 1)], float* GV) {
-  constexpr LayerPlan LP = PlanCT<LMAX, NL>::plan.layer[K];  // layer K + 1
-  float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
-  if constexpr (K + 1 < NL) recompute_gV<LMAX, NL, L, K + 1, C, NG>(a, t, n, Gn, GVO);
-#pragma unroll
-  for (int q = 0; q < LP.n_in_comps; ++q) GV[q] = 0.0f;
-  const float* G = Gn[K - L];
+  for (int q = 0; q < LP.n_out_comps; ++q) vout[q] = 0.0f;
   static_for<0, LP.n_paths>([&](auto P) {
     constexpr int k = decltype(P)::value;
     constexpr PathT pt = LP.p[k];
-    constexpr int d3 = 2 * pt.l3 + 1;
-    constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
-    float GT[d3];
-#pragma unroll
-    for (int m3 = 0; m3 < d3; ++m3) GT[m3] = 0.0f;
-    if constexpr (pt.s_idx >= 0) GT[0] = a.gs_l[K][(t * LP.n0e + pt.s_idx) * C + n];
     if constexpr (pt.out_off >= 0) {
-      const float al = a.alpha_l[K][k * C + n];
+      constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+      float T[2 * pt.l3 + 1];
 #pragma unroll
-      for (int m3 = 0; m3 < d3; ++m3) GT[m3] += al * GVO[pt.out_off + m3];
+      for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) T[m3] = 0.0f;
+      static_for<0, nz.n>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        T[nz.m3[q]] += nz.c[q] * vin[pt.in_off + nz.m1[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+      });
+      const float al = a.alpha_l[K - 1][k * CS + nc];
+#pragma unroll
+      for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) vout[pt.out_off + m3] += al * T[m3];
     }
-    static_for<0, nz.n>([&](auto Q) {
-      constexpr int q = decltype(Q)::value;
-      GV[pt.in_off + nz.m1[q]] += nz.c[q] * GT[nz.m3[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
-    });
   });
 }
 
-// Layers up to 2 fit 5 wavefronts per SIMD; the deeper rebuild of V^{L-1}
-// needs 4 and an edge loop that is not unrolled.
-template <int LMAX, int NL, int L, int C, bool B16>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L >= 3 ? 4 : 5))) k_tp_fwd(TPArgs a) {
-  constexpr int UNR = L >= 3 ? 1 : 2;
+// V^J for given V^0 (layers 1..J forward)
+template <int LMAX, int NL, int J, int CS>
+__device__ __forceinline__ void fwd_chain(const TPArgs& a, int nc, const float (&G)[NL][(LMAX + 1) * (LMAX + 1)],
+                                          const float* v0, float* vJ) {
+  if constexpr (J == 0) {
+#pragma unroll
+    for (int q = 0; q < (LMAX + 1) * (LMAX + 1); ++q) vJ[q] = v0[q];
+  } else {
+    float vin[n_comps<LMAX, NL, J - 1>()];
+    fwd_chain<LMAX, NL, J - 1, CS>(a, nc, G, v0, vin);
+    fwd_layer<LMAX, NL, J, CS>(a, nc, G[J - 1], vin, vJ);
+  }
+}
+
+// Adjoint of layer K's mixing and products: dE/dV^{K-1} from dE/dV^K,
+// where dE/dV^K is nonzero only on components [OFF, OFF + LEN).
+template <int LMAX, int NL, int K, int OFF, int LEN, int CS>
+__device__ __forceinline__ void adj_layer(const TPArgs& a, int nc, const float* G, const float* gvo, float* gv) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, K>::lp;
+#pragma unroll
+  for (int q = 0; q < LP.n_in_comps; ++q) gv[q] = 0.0f;
+  static_for<0, LP.n_paths>([&](auto P) {
+    constexpr int k = decltype(P)::value;
+    constexpr PathT pt = LP.p[k];
+    if constexpr (pt.out_off >= OFF && pt.out_off < OFF + LEN) {
+      constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+      const float al = a.alpha_l[K - 1][k * CS + nc];
+      float GT[2 * pt.l3 + 1];
+#pragma unroll
+      for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) GT[m3] = al * gvo[pt.out_off + m3];
+      static_for<0, nz.n>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        gv[pt.in_off + nz.m1[q]] += nz.c[q] * GT[nz.m3[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+      });
+    }
+  });
+}
+
+// dE/dV^J (dense) from dE/dV^M (nonzero on [OFF, OFF + LEN)), J < M
+template <int LMAX, int NL, int M, int J, int OFF, int LEN, int CS>
+__device__ __forceinline__ void adj_down(const TPArgs& a, int nc, const float (&G)[NL][(LMAX + 1) * (LMAX + 1)],
+                                         const float* gM, float* gJ) {
+  if constexpr (M - 1 == J) {
+    adj_layer<LMAX, NL, M, OFF, LEN, CS>(a, nc, G[M - 1], gM, gJ);
+  } else {
+    float t[n_comps<LMAX, NL, M - 1>()];
+    adj_layer<LMAX, NL, M, OFF, LEN, CS>(a, nc, G[M - 1], gM, t);
+    adj_down<LMAX, NL, M - 1, J, 0, n_comps<LMAX, NL, M - 1>(), CS>(a, nc, G, t, gJ);
+  }
+}
+
+// dE/dV^{K-1} for dE/ds = 1 on scalar slot S of layer K: C Gamma^K on the
+// block [UnitCT::off, + len) of the path's input irrep (other entries unset)
+template <int LMAX, int NL, int K, int S>
+__device__ __forceinline__ void unit_inject(const float* G, float* g) {
+  using U = UnitCT<LMAX, NL, K, S>;
+  constexpr PathT pt = U::pt;
+  constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, 0>::nz;
+#pragma unroll
+  for (int m = 0; m < U::len; ++m) g[U::off + m] = 0.0f;
+  static_for<0, nz.n>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    g[pt.in_off + nz.m1[q]] += nz.c[q] * G[pt.l2 * pt.l2 + nz.m2[q]];
+  });
+}
+
+// dE/dGamma^L += sum over layer L's paths of C (dE/dT^L) X, with
+// dE/dT^L = alpha^L dE/dV^L (dV nonzero on [OFF, OFF + LEN)) and X given
+// input features; with WANT_D also the products' adjoint in their input,
+// D += C (dE/dT^L) Gamma^L.
+template <int LMAX, int NL, int L, int OFF, int LEN, bool WANT_D, int CS>
+__device__ __forceinline__ void contract(const TPArgs& a, int nc, const float* G, const float* dv, const float* X,
+                                         float* GG, float* D) {
+  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
+  static_for<0, LP.n_paths>([&](auto P) {
+    constexpr int k = decltype(P)::value;
+    constexpr PathT pt = LP.p[k];
+    if constexpr (pt.out_off >= OFF && pt.out_off < OFF + LEN) {
+      constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+      const float al = a.alpha_l[L - 1][k * CS + nc];
+      float GT[2 * pt.l3 + 1];
+#pragma unroll
+      for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) GT[m3] = al * dv[pt.out_off + m3];
+      static_for<0, nz.n>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        const float cg = nz.c[q] * GT[nz.m3[q]];
+        GG[pt.l2 * pt.l2 + nz.m2[q]] += cg * X[pt.in_off + nz.m1[q]];
+        if constexpr (WANT_D) D[pt.in_off + nz.m1[q]] += cg * G[pt.l2 * pt.l2 + nz.m2[q]];
+      });
+    }
+  });
+}
+
+// Given the Gammas, the tensor track of an edge is linear in its layer-1
+// input V^0 = omega^1 (x) Y: V^L = R^L V^0 and s^L = P^L V^0 with per-atom,
+// per-channel matrices (products with fixed Gammas, then channelwise
+// mixing).  The kernels therefore form these small maps once per atom and
+// apply them per edge, instead of running every earlier (forward) or later
+// (adjoint) layer's products again for each edge.
+//
+// One group of C lanes per central atom (lane = channel), 256 / C atoms per
+// workgroup; a group walks all edges of its row, so the row sums need no
+// cross-lane reduction and no LDS.
+template <int LMAX, int NL, int L, int C, bool B16, int CS>
+__global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
-  constexpr int NS = 256 / C;
-  constexpr int NCI = LP.n_in_comps, NCO = LP.n_out_comps > 0 ? LP.n_out_comps : 1;
-  __shared__ float red[NS * NLM * C];
-  __shared__ float gam[NLM * C];
-  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  constexpr int NA = 256 / C;
+  constexpr int NS0 = LP.n0e;
+  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int nc = a.c0 + n;   // channel in the arrays (a launch covers channels [c0, c0 + C))
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
-  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+  for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
     const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
-    float acc[NLM];
+    float G[NL][NLM];
+    // Gamma^L_i = nbar^-1/2 sum over the row of omega^L (x) Y
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) acc[q] = 0.0f;
-#pragma unroll UNR
-    for (int64_t e = eb + slot; e < ee; e += NS) {
+    for (int q = 0; q < NLM; ++q) G[L - 1][q] = 0.0f;
+#pragma unroll 2
+    for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
+        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) acc[l * l + m] += w * Y[l * l + m];
+        for (int m = 0; m < 2 * l + 1; ++m) G[L - 1][l * l + m] += w * Y[l * l + m];
       }
     }
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) red[(slot * NLM + q) * C + n] = acc[q];
-    __syncthreads();
-    for (int q = slot; q < NLM; q += NS) {
-      float g = 0.0f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) g += red[(s * NLM + q) * C + n];
-      g *= a.inv_sqrt_nbar;
-      gam[q * C + n] = g;
-      a.gamma[(i * NLM + q) * C + n] = g;
+    for (int q = 0; q < NLM; ++q) {
+      G[L - 1][q] *= a.inv_sqrt_nbar;
+      a.gamma[(i * NLM + q) * CS + nc] = G[L - 1][q];
     }
-    __syncthreads();
-    float G[NLM];
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) G[q] = gam[q * C + n];
-    float Gp[L > 1 ? L - 1 : 1][NLM];
-    load_gammas<LMAX, 0, L - 1, C>(a, i, n, Gp);
-#pragma unroll UNR
-    for (int64_t e = eb + slot; e < ee; e += NS) {
+    load_gammas<LMAX, NL, L - 1, CS>(a, i, nc, G);
+    // rows of P^L: dE/dV^0 for a unit dE/ds on each scalar path (layer L's
+    // products, then the earlier layers' adjoints); for L = 1 a row is the
+    // path's C Gamma^1 block
+    float P[NS0 > 0 ? NS0 : 1][NLM];
+    static_for<0, NS0>([&](auto SS) {
+      constexpr int S = decltype(SS)::value;
+      if constexpr (L == 1) {
+        unit_inject<LMAX, NL, 1, S>(G[0], P[S]);
+      } else {
+        using U = UnitCT<LMAX, NL, L, S>;
+        float gb[n_comps<LMAX, NL, L - 1>()];
+        unit_inject<LMAX, NL, L, S>(G[L - 1], gb);
+        adj_down<LMAX, NL, L - 1, 0, U::off, U::len, CS>(a, nc, G, gb, P[S]);
+      }
+    });
+#pragma unroll 2
+    for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
-      float V[NCI];
-      recompute_V<LMAX, NL, L - 1, C, B16>(a, t, n, Y, Gp, V);
-      // only the scalar (0e) paths leave the kernel; V^L is recomputed by
-      // the layers that read it
-      static_for<0, LP.n_paths>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        constexpr PathT pt = LP.p[k];
-        if constexpr (pt.s_idx >= 0) {
-          float T[2 * pt.l3 + 1];
-          path_fwd<LMAX, NL, L, k>(V, G, T);
-          const int64_t si = (t * LP.n0e + pt.s_idx) * C + n;
-          st_w<B16>(a.s, si, T[0]);
-        }
+      float V0[NLM];
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) V0[l * l + m] = w * Y[l * l + m];
+      }
+      static_for<0, NS0>([&](auto SS) {
+        constexpr int S = decltype(SS)::value;
+        using U = UnitCT<LMAX, NL, L, S>;
+        constexpr int q0 = L == 1 ? U::off : 0, q1 = L == 1 ? U::off + U::len : NLM;
+        float s = 0.0f;
+#pragma unroll
+        for (int q = q0; q < q1; ++q) s += P[S][q] * V0[q];
+        st_w<B16>(a.s, (t * NS0 + S) * CS + nc, s);
       });
     }
-    __syncthreads();
   }
 }
 
-template <int LMAX, int NL, int L, int C, bool B16>
+// Adjoint of layer L.  With g'_e the edge's dE/ds of layers L..NL (the
+// slots), dE/dT^L_e and V^{L-1}_e are linear in g'_e and V^0_e, so
+// dE/dGamma^L needs only the row moment M = sum_e V^0_e g'_e^T: each slot b
+// contributes the layer-L product adjoint of (its unit dE/dT^L) with
+// R^{L-1} M[:, b].  Layer 1 also needs dE/dV^0_e = D g'_e per edge (D: the
+// rows of every layer's P, formed alongside).
+template <int LMAX, int NL, int L, int C, bool B16, int CS>
 __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
-  constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
-  constexpr int NS = 256 / C;
-  constexpr int NCI = LP.n_in_comps;
-  __shared__ float red[NS * NLM * C];
-  const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  constexpr int NA = 256 / C;
+  using SL = Slots<LMAX, NL, L>;
+  constexpr int NB = SL::count();
+  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int nc = a.c0 + n;   // channel in the arrays (a launch covers channels [c0, c0 + C))
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
-  for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
+  // dE/ds of slot b for edge t
+  auto load_slots = [&](int64_t t, float (&gp)[NB]) {
+    static_for<0, NB>([&](auto B) {
+      constexpr int b = decltype(B)::value;
+      constexpr int K = SL::layer(b), S = SL::sub(b);
+      constexpr int n0 = LayerCT<LMAX, NL, K>::lp.n0e;
+      gp[b] = a.gs_l[K - 1][(t * n0 + S) * CS + nc];
+    });
+  };
+  for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
     const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
-    float G[NLM], GG[NLM];
+    // row moment M[a][b] = sum_e V^0_e[a] g'_e[b]
+    float M[NLM][NB];
 #pragma unroll
-    for (int q = 0; q < NLM; ++q) {
-      G[q] = a.gamma[(i * NLM + q) * C + n];
-      GG[q] = 0.0f;
-    }
-    float Gp[L > 1 ? L - 1 : 1][NLM], Gn[L < NL ? NL - L : 1][NLM];
-    load_gammas<LMAX, 0, L - 1, C>(a, i, n, Gp);
-    load_gammas<LMAX, L, NL - L, C>(a, i, n, Gn);
-    for (int64_t e = eb + slot; e < ee; e += NS) {
+    for (int q = 0; q < NLM; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) M[q][b] = 0.0f;
+    for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
-      float V[NCI], GV[NCI];
-      recompute_V<LMAX, NL, L - 1, C, B16>(a, t, n, Y, Gp, V);
-      // dE/dV^L of this edge and channel
-      float GVO[LP.n_out_comps > 0 ? LP.n_out_comps : 1];
-      if constexpr (L < NL) recompute_gV<LMAX, NL, L, L, C, NL - L>(a, t, n, Gn, GVO);
+      float gp[NB];
+      load_slots(t, gp);
 #pragma unroll
-      for (int q = 0; q < NCI; ++q) GV[q] = 0.0f;
-      static_for<0, LP.n_paths>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        constexpr PathT pt = LP.p[k];
-        constexpr int d3 = 2 * pt.l3 + 1;
-        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
-        float GT[d3];
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
 #pragma unroll
-        for (int m3 = 0; m3 < d3; ++m3) GT[m3] = 0.0f;
-        if constexpr (pt.s_idx >= 0) GT[0] = a.gs[(t * LP.n0e + pt.s_idx) * C + n];
-        if constexpr (pt.out_off >= 0) {
-          const float al = a.alpha[k * C + n];
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const float v = w * Y[l * l + m];
 #pragma unroll
-          for (int m3 = 0; m3 < d3; ++m3) GT[m3] += al * GVO[pt.out_off + m3];
+          for (int b = 0; b < NB; ++b) M[l * l + m][b] += v * gp[b];
         }
-        static_for<0, nz.n>([&](auto Q) {
-          constexpr int q = decltype(Q)::value;
-          const float cg = nz.c[q] * GT[nz.m3[q]];
-          GV[pt.in_off + nz.m1[q]] += cg * G[pt.l2 * pt.l2 + nz.m2[q]];
-          GG[pt.l2 * pt.l2 + nz.m2[q]] += cg * V[pt.in_off + nz.m1[q]];
-        });
-      });
-      if constexpr (L == 1) {
-        // V^0 = omega^1 (x) Y
-        float gyc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) {
-          const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * C + n);
-          float go = 0.0f;
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) {
-            go += GV[l * l + m] * Y[l * l + m];
-            gyc[l * l + m] = GV[l * l + m] * w;
-          }
-          st_w<B16>(a.gomega, (t * (LMAX + 1) + l) * C + n, go);
-        }
-        add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
       }
     }
-    // dE/dGamma summed over the slots, scaled by nbar^-1/2
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) red[(slot * NLM + q) * C + n] = GG[q];
-    __syncthreads();
+    float G[NL][NLM];
+    load_gammas<LMAX, NL, NL, CS>(a, i, nc, G);
+    float GG[NLM], D[NLM][NB];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) {
-      float g = 0.0f;
+      GG[q] = 0.0f;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) g += red[(s * NLM + q) * C + n];
-      GG[q] = g * a.inv_sqrt_nbar;
+      for (int b = 0; b < NB; ++b) D[q][b] = 0.0f;
     }
-    for (int64_t e = eb + slot; e < ee; e += NS) {
+    static_for<0, NB>([&](auto B) {
+      constexpr int b = decltype(B)::value;
+      constexpr int K = SL::layer(b), S = SL::sub(b);
+      using U = UnitCT<LMAX, NL, K, S>;
+      float m0[NLM];
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) m0[q] = M[q][b];
+      float X[n_comps<LMAX, NL, L - 1>()];
+      fwd_chain<LMAX, NL, L - 1, CS>(a, nc, G, m0, X);
+      if constexpr (K == L) {
+        // unit dE/dT on the scalar path itself: C X on its block
+        constexpr PathT pt = U::pt;
+        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, 0>::nz;
+        static_for<0, nz.n>([&](auto Q) {
+          constexpr int q = decltype(Q)::value;
+          GG[pt.l2 * pt.l2 + nz.m2[q]] += nz.c[q] * X[pt.in_off + nz.m1[q]];
+        });
+      } else {
+        float gb[n_comps<LMAX, NL, K - 1>()], Dc[NLM];
+#pragma unroll
+        for (int q = 0; q < NLM; ++q) Dc[q] = 0.0f;
+        unit_inject<LMAX, NL, K, S>(G[K - 1], gb);
+        if constexpr (K - 1 == L) {
+          contract<LMAX, NL, L, U::off, U::len, L == 1, CS>(a, nc, G[L - 1], gb, X, GG, Dc);
+        } else {
+          float dv[n_comps<LMAX, NL, L>() > 0 ? n_comps<LMAX, NL, L>() : 1];
+          adj_down<LMAX, NL, K - 1, L, U::off, U::len, CS>(a, nc, G, gb, dv);
+          contract<LMAX, NL, L, 0, n_comps<LMAX, NL, L>(), L == 1, CS>(a, nc, G[L - 1], dv, X, GG, Dc);
+        }
+        if constexpr (L == 1) {
+#pragma unroll
+          for (int q = 0; q < NLM; ++q) D[q][b] = Dc[q];
+        }
+      }
+    });
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) GG[q] *= a.inv_sqrt_nbar;
+    // per edge: dE/domega^L (Gamma^L's adjoint; for L = 1 also V^0's) and
+    // the channel sums of dE/dY
+    for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      float tot[NLM];
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) tot[q] = GG[q];
+      if constexpr (L == 1) {
+        float gp[NB];
+        load_slots(t, gp);
+        static_for<0, NB>([&](auto B) {
+          constexpr int b = decltype(B)::value;
+          constexpr int K = SL::layer(b), S = SL::sub(b);
+          if constexpr (K == 1) {
+            using U = UnitCT<LMAX, NL, 1, S>;
+            constexpr PathT pt = U::pt;
+            constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, 0>::nz;
+            static_for<0, nz.n>([&](auto Q) {
+              constexpr int q = decltype(Q)::value;
+              tot[pt.in_off + nz.m1[q]] += nz.c[q] * G[0][pt.l2 * pt.l2 + nz.m2[q]] * gp[b];
+            });
+          } else {
+#pragma unroll
+            for (int q = 0; q < NLM; ++q) tot[q] += D[q][b] * gp[b];
+          }
+        });
+      }
       float gyc[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
+        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
         float go = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
-          const float gg = GG[l * l + m];
-          go += gg * Y[l * l + m];
-          gyc[l * l + m] = gg * w;
+          go += tot[l * l + m] * Y[l * l + m];
+          gyc[l * l + m] = tot[l * l + m] * w;
         }
-        const int64_t gi = (t * (LMAX + 1) + l) * C + n;
-        if constexpr (L == 1) go += ld_w<B16>(a.gomega, gi);
-        st_w<B16>(a.gomega, gi, go);
+        st_w<B16>(a.gomega, (t * (LMAX + 1) + l) * CS + nc, go);
       }
       add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
     }
-    __syncthreads();
   }
 }
 
 typedef void (*tp_kernel_t)(TPArgs);
 
-template <int LMAX, int NL, int C, bool B16>
+template <int LMAX, int NL, int C, bool B16, int CS>
 static tp_kernel_t pick(int L, bool bwd) {
-  if (L == 1) return bwd ? k_tp_bwd<LMAX, NL, 1, C, B16> : k_tp_fwd<LMAX, NL, 1, C, B16>;
-  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp_bwd<LMAX, NL, 2, C, B16> : k_tp_fwd<LMAX, NL, 2, C, B16>;
-  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp_bwd<LMAX, NL, 3, C, B16> : k_tp_fwd<LMAX, NL, 3, C, B16>;
+  if (L == 1) return bwd ? k_tp_bwd<LMAX, NL, 1, C, B16, CS> : k_tp_fwd<LMAX, NL, 1, C, B16, CS>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp_bwd<LMAX, NL, 2, C, B16, CS> : k_tp_fwd<LMAX, NL, 2, C, B16, CS>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp_bwd<LMAX, NL, 3, C, B16, CS> : k_tp_fwd<LMAX, NL, 3, C, B16, CS>;
   return nullptr;
 }
 
-template <int LMAX, int C, bool B16>
+// C: channels per launch (threads' channel groups); CS: channels in the arrays
+template <int LMAX, int C, bool B16, int CS>
 static tp_kernel_t pick_nl(int NL, int L, bool bwd) {
   switch (NL) {
-    case 1: return pick<LMAX, 1, C, B16>(L, bwd);
-    case 2: return pick<LMAX, 2, C, B16>(L, bwd);
-    case 3: return pick<LMAX, 3, C, B16>(L, bwd);
+    case 1: return pick<LMAX, 1, C, B16, CS>(L, bwd);
+    case 2: return pick<LMAX, 2, C, B16, CS>(L, bwd);
+    case 3: return pick<LMAX, 3, C, B16, CS>(L, bwd);
   }
   return nullptr;
 }
@@ -356,10 +479,11 @@ static tp_kernel_t pick_nl(int NL, int L, bool bwd) {
 template <int LMAX, bool B16>
 static tp_kernel_t pick_c(int C, int NL, int L, bool bwd) {
   switch (C) {
-    case 8: return pick_nl<LMAX, 8, B16>(NL, L, bwd);
-    case 16: return pick_nl<LMAX, 16, B16>(NL, L, bwd);
-    case 32: return pick_nl<LMAX, 32, B16>(NL, L, bwd);
-    case 64: return pick_nl<LMAX, 64, B16>(NL, L, bwd);
+    case 8: return pick_nl<LMAX, 8, B16, 8>(NL, L, bwd);
+    case 16: return pick_nl<LMAX, 16, B16, 16>(NL, L, bwd);
+    case 32: return pick_nl<LMAX, 32, B16, 32>(NL, L, bwd);
+    case 64: return pick_nl<LMAX, 64, B16, 64>(NL, L, bwd);
+    case 128: return pick_nl<LMAX, 64, B16, 128>(NL, L, bwd);
   }
   return nullptr;
 }
@@ -374,12 +498,20 @@ static tp_kernel_t pick_l(int lmax, int C, int NL, int L, bool bwd) {
   return nullptr;
 }
 
+// 128 channels run as two consecutive launches of 64-channel kernels over
+// the channel groups (the products are channelwise); the per-edge sums over
+// channels (dE/dY) accumulate group after group in a fixed order.
 int launch_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const TPArgs& a, int64_t n_atoms_max,
               hipStream_t st) {
+  const int CK = C > 64 ? 64 : C;
   tp_kernel_t k = bf16 ? pick_l<true>(lmax, C, NL, L, bwd) : pick_l<false>(lmax, C, NL, L, bwd);
   if (!k) { set_error("tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
-  const unsigned grid = grid_for(n_atoms_max, 1, 65536);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, a);
+  const unsigned grid = grid_for(n_atoms_max, 256 / CK, 65536);
+  for (int c0 = 0; c0 < C; c0 += CK) {
+    TPArgs ag = a;
+    ag.c0 = c0;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, st, ag);
+  }
   AFM_LAUNCH_CHECK();
   return AFM_OK;
 }

@@ -41,6 +41,10 @@ int afm_set_edge_tile(afm_model* m, int32_t edges, int32_t waves) {
     set_error("edge-tile shape must be 64x8, 128x16 or 128x8 (edges x wavefronts)");
     return AFM_E_INVALID;
   }
+  if (m->prec == AFM_BF16_MFMA && m->dims.w > 256 && edges != 64) {
+    set_error("latent widths above 256 are built for 64-edge tiles only");
+    return AFM_E_UNSUPPORTED;
+  }
   m->edge_tile = edges;
   m->tile_waves = waves;
   return AFM_OK;
@@ -90,6 +94,8 @@ int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl,
     rc = AFM_E_HIP;
   }
   for (int v = 0; v < kTileShapes && !rc; ++v) {
+    t_ms[v] = -1.0;   // not built for this model
+    if (m->dims.w > 256 && kTileEdges[v] != 64) continue;
     m->edge_tile = kTileEdges[v];
     m->tile_waves = kTileWaves[v];
     rc = afm_energy_forces(m, sys, nl, e_atom, e_struct, F, W, ws, stream);   // warm-up
@@ -111,7 +117,7 @@ int afm_tune_edge_tile(afm_model* m, const afm_system* sys, const afm_nlist* nl,
   if (rc) { m->edge_tile = keep_e; m->tile_waves = keep_w; return rc; }
   int best = 0;
   for (int v = 1; v < kTileShapes; ++v)
-    if (t_ms[v] < t_ms[best]) best = v;
+    if (t_ms[v] >= 0.0 && t_ms[v] < t_ms[best]) best = v;
   m->edge_tile = *edges = kTileEdges[best];
   m->tile_waves = *waves = kTileWaves[best];
   if (ms)
