@@ -40,9 +40,8 @@ struct TPArgs {
   // later layers' Gammas and dE/ds.
   const float* gamma_l[kMaxTpLayers];
   const float* alpha_l[kMaxTpLayers];
-  const float* gs_l[kMaxTpLayers];
+  const void* gs_l[kMaxTpLayers];   // dE/ds: float (FP32 path) or bf16 bits
   float inv_sqrt_nbar;
-  const float* gs;       // dE/ds^L
   void* gomega;          // dE/domega^L [t][lmax+1][C]
   float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
   // first channel of this launch: a launch covers channels [c0, c0 + C)

@@ -454,7 +454,7 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   for (int l = 0; l < d.NL; ++l) {
     a.gamma_l[l] = ws_ptr<float>(ws, L.gamma[l]);
     a.alpha_l[l] = l + 1 < d.NL ? m->W.alpha[l] : nullptr;
-    a.gs_l[l] = ws_ptr<float>(ws, L.gs[l]);
+    a.gs_l[l] = ws_ptr<float>(ws, L.gs[l]);   // bf16 bits in the BF16 path
   }
   a.s = ws_ptr<float>(ws, L.s[layer - 1]);
   a.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
@@ -616,7 +616,6 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
     }
     TraceScope tr(st, "tp_bwd", layer);
     TPArgs ta = tp_args(m, ws, L, rr, layer);
-    ta.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
     rc = launch_tp(d.lmax, d.NL, layer, d.c, true, m->prec == AFM_BF16_MFMA, ta, s.N, st);
     if (rc) return rc;
   }

@@ -190,7 +190,7 @@ struct ChainArgs {
   float* eps;             // edge energies (global edge index)
   uint2* pre[kMaxDepth];  // bf16 pre-activations per MLP layer
   float* gx;              // dE/dx (in: of x^L / x^0; out: of x^{L-1})
-  float* gs;              // dE/ds^L
+  uint16_t* gs;           // dE/ds^L (bf16)
   const uint16_t* gomega; // dE/domega^{L+1} (or of omega^1), bf16 bits
   float* gy;              // [t][16], dE/du at [9]
   float* grho;            // [t][16]
@@ -349,7 +349,7 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   a.seg = seg;
   a.B = B;
   a.ges = grad_e_struct;
-  a.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
+  a.gs = ws_ptr<uint16_t>(ws, L.gs[layer - 1]);
   for (int k = 0; k < d.depth; ++k) a.latb[k] = frag_ptr(m, fo->latb[layer - 1][k]);
   if (layer < d.NL) a.envb = frag_ptr(m, fo->envb[layer]);
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);

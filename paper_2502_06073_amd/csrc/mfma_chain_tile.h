@@ -182,6 +182,11 @@ __device__ __forceinline__ void st_bf16x4(uint16_t* p, f32x4 v) {
   const uint4 w = __builtin_bit_cast(uint4, pack8(v, v));
   __builtin_nontemporal_store(u32x2{w.x, w.y}, reinterpret_cast<u32x2*>(p));
 }
+// the same with a plain store (for outputs the next kernel reads at once)
+__device__ __forceinline__ void st_bf16x4_plain(uint16_t* p, f32x4 v) {
+  const uint4 w = __builtin_bit_cast(uint4, pack8(v, v));
+  *reinterpret_cast<u32x2*>(p) = u32x2{w.x, w.y};
+}
 
 // acc[r][cb] += sum over k-blocks kb in [kb0, kb0 + NKB) of
 //   W[2 pair + r][kb] x act[kb - kb0][cb]
@@ -721,7 +726,7 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_f
       }
       st4(p, res + v);
     } else if (16 * (rb - RBW) < KS) {
-      st4(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
+      st_bf16x4_plain(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
     }
   };
   constexpr int NPO = cdiv(W + KS, 32);

@@ -54,6 +54,73 @@ struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[K - 1];
 };
 
+// A group of C = 64 lanes is one whole wavefront: its atom, edge indices
+// and spherical harmonics are then wavefront-uniform and live in SGPRs
+// (loaded once by nine lanes and broadcast), which keeps the per-edge
+// vector-memory instructions to the per-channel streams.
+template <int C>
+__device__ __forceinline__ int group_index() {
+  if constexpr (C == 64) return __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  else return threadIdx.x / C;
+}
+template <int C>
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  if constexpr (C == 64) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  } else {
+    return v;
+  }
+}
+// Y^{l <= LMAX} of an edge, fetched ahead of its use (the edge loops issue
+// the next edge's loads before working on the current one)
+template <int C, int NLM>
+struct YFetch {
+  float v[C == 64 ? 1 : NLM];
+  __device__ __forceinline__ void fetch(const float* geo, int64_t t) {
+    const float* p = geo + t * GEO_STRIDE + GEO_Y;
+    if constexpr (C == 64) {
+      const int lane = threadIdx.x & 63;
+      v[0] = lane < NLM ? p[lane] : 0.0f;
+    } else {
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) v[q] = p[q];
+    }
+  }
+  __device__ __forceinline__ void get(float (&Y)[NLM]) const {
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      if constexpr (C == 64)
+        Y[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), q));
+      else
+        Y[q] = v[q];
+    }
+  }
+};
+
+// the dE/dY accumulators an edge's channel sums are added to (C = 64: lane
+// 4k holds value k), fetched ahead like the other per-edge inputs
+template <int C, int NV>
+struct GyFetch {
+  float v;
+  __device__ __forceinline__ void fetch(const float* gy_t, int n) {
+    if constexpr (C == 64) v = ((n & 3) == 0 && (n >> 2) < NV) ? gy_t[n >> 2] : 0.0f;
+    else v = 0.0f;
+  }
+};
+// dst[q] = (fetched) dst[q] + sum over the C channels of v[q], q < NV
+template <int C, int NV>
+__device__ __forceinline__ void add_channel_sums_to(float (&v)[16], float* dst, int n, const GyFetch<C, NV>& old) {
+  if constexpr (C == 64) {
+    const float y = wave_sum16(v, n);
+    if ((n & 3) == 0 && (n >> 2) < NV) dst[n >> 2] = old.v + y;
+  } else {
+    add_channel_sums<C, NV>(v, dst, n);
+  }
+}
+
 // components of V^J (J = 0: the layer-1 inputs omega^1 (x) Y, index l*l+m)
 template <int LMAX, int NL, int J>
 constexpr int n_comps() {
@@ -247,25 +314,40 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NA = 256 / C;
   constexpr int NS0 = LP.n0e;
-  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int n = threadIdx.x % C, grp = group_index<C>();
   const int nc = a.c0 + n;   // channel in the arrays (a launch covers channels [c0, c0 + C))
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
-  const int64_t e0 = a.rr.row_ptr[a0];
+  const int64_t e0 = uniform64<C>(a.rr.row_ptr[a0]);
+  // per-edge inputs: Y and one omega (omega^L for Gamma^L, omega^1 for V^0)
+  struct EdgeIn {
+    YFetch<C, NLM> y;
+    float w[LMAX + 1];
+  };
+  auto fetch = [&](int64_t t, const void* om, EdgeIn& x) {
+    x.y.fetch(a.geo, t);
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(om, (t * (LMAX + 1) + l) * CS + nc);
+  };
   for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
-    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    const int64_t eb = uniform64<C>(a.rr.row_ptr[i]), ee = uniform64<C>(a.rr.row_ptr[i + 1]);
     float G[NL][NLM];
     // Gamma^L_i = nbar^-1/2 sum over the row of omega^L (x) Y
 #pragma unroll
     for (int q = 0; q < NLM; ++q) G[L - 1][q] = 0.0f;
-#pragma unroll 2
-    for (int64_t e = eb; e < ee; ++e) {
-      const int64_t t = e - e0;
-      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+    {
+      EdgeIn cur, nxt;
+      if (eb < ee) fetch(eb - e0, a.omega, cur);
+      nxt = cur;
+      for (int64_t e = eb; e < ee; ++e) {
+        const int64_t t = e - e0;
+        if (e + 1 < ee) fetch(t + 1, a.omega, nxt);
+        float Y[NLM];
+        cur.y.get(Y);
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
+        for (int l = 0; l <= LMAX; ++l)
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) G[L - 1][l * l + m] += w * Y[l * l + m];
+          for (int m = 0; m < 2 * l + 1; ++m) G[L - 1][l * l + m] += cur.w[l] * Y[l * l + m];
+        cur = nxt;
       }
     }
 #pragma unroll
@@ -289,17 +371,19 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
         adj_down<LMAX, NL, L - 1, 0, U::off, U::len, CS>(a, nc, G, gb, P[S]);
       }
     });
-#pragma unroll 2
+    EdgeIn cur, nxt;
+    if (eb < ee) fetch(eb - e0, a.omega1, cur);
+    nxt = cur;
     for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
-      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      if (e + 1 < ee) fetch(t + 1, a.omega1, nxt);
+      float Y[NLM];
+      cur.y.get(Y);
       float V0[NLM];
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
+      for (int l = 0; l <= LMAX; ++l)
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) V0[l * l + m] = w * Y[l * l + m];
-      }
+        for (int m = 0; m < 2 * l + 1; ++m) V0[l * l + m] = cur.w[l] * Y[l * l + m];
       static_for<0, NS0>([&](auto SS) {
         constexpr int S = decltype(SS)::value;
         using U = UnitCT<LMAX, NL, L, S>;
@@ -309,6 +393,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
         for (int q = q0; q < q1; ++q) s += P[S][q] * V0[q];
         st_w<B16>(a.s, (t * NS0 + S) * CS + nc, s);
       });
+      cur = nxt;
     }
   }
 }
@@ -319,47 +404,80 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
 // contributes the layer-L product adjoint of (its unit dE/dT^L) with
 // R^{L-1} M[:, b].  Layer 1 also needs dE/dV^0_e = D g'_e per edge (D: the
 // rows of every layer's P, formed alongside).
+// occupancy floor of the adjoint kernels (register budget 512 / waves)
+template <int NL, int L>
+constexpr int tp_bwd_waves() { return (L == 1 && NL >= 3) ? 3 : 4; }
+
 template <int LMAX, int NL, int L, int C, bool B16, int CS>
-__global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_bwd_waves<NL, L>())))
+k_tp_bwd(TPArgs a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NA = 256 / C;
   using SL = Slots<LMAX, NL, L>;
   constexpr int NB = SL::count();
-  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int n = threadIdx.x % C, grp = group_index<C>();
   const int nc = a.c0 + n;   // channel in the arrays (a launch covers channels [c0, c0 + C))
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
-  const int64_t e0 = a.rr.row_ptr[a0];
+  const int64_t e0 = uniform64<C>(a.rr.row_ptr[a0]);
   // dE/ds of slot b for edge t
   auto load_slots = [&](int64_t t, float (&gp)[NB]) {
     static_for<0, NB>([&](auto B) {
       constexpr int b = decltype(B)::value;
       constexpr int K = SL::layer(b), S = SL::sub(b);
       constexpr int n0 = LayerCT<LMAX, NL, K>::lp.n0e;
-      gp[b] = a.gs_l[K - 1][(t * n0 + S) * CS + nc];
+      gp[b] = ld_w<B16>(a.gs_l[K - 1], (t * n0 + S) * CS + nc);
     });
   };
+  // per-edge inputs of the moment pass and of the dE/domega pass
+  struct In1 {
+    YFetch<C, NLM> y;
+    float w[LMAX + 1], gp[NB];
+  };
+  struct In3 {
+    YFetch<C, NLM> y;
+    float w[LMAX + 1], gp[L == 1 ? NB : 1];
+    GyFetch<C, NLM> gy;
+  };
+  auto fetch1 = [&](int64_t t, In1& x) {
+    x.y.fetch(a.geo, t);
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
+    load_slots(t, x.gp);
+  };
+  auto fetch3 = [&](int64_t t, In3& x) {
+    x.y.fetch(a.geo, t);
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
+    if constexpr (L == 1) load_slots(t, x.gp);
+    x.gy.fetch(a.gy + t * GEO_STRIDE, n);
+  };
   for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
-    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    const int64_t eb = uniform64<C>(a.rr.row_ptr[i]), ee = uniform64<C>(a.rr.row_ptr[i + 1]);
     // row moment M[a][b] = sum_e V^0_e[a] g'_e[b]
     float M[NLM][NB];
 #pragma unroll
     for (int q = 0; q < NLM; ++q)
 #pragma unroll
       for (int b = 0; b < NB; ++b) M[q][b] = 0.0f;
-    for (int64_t e = eb; e < ee; ++e) {
-      const int64_t t = e - e0;
-      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
-      float gp[NB];
-      load_slots(t, gp);
+    {
+      In1 cur, nxt;
+      if (eb < ee) fetch1(eb - e0, cur);
+      nxt = cur;
+      for (int64_t e = eb; e < ee; ++e) {
+        const int64_t t = e - e0;
+        if (e + 1 < ee) fetch1(t + 1, nxt);
+        float Y[NLM];
+        cur.y.get(Y);
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
+        for (int l = 0; l <= LMAX; ++l) {
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) {
-          const float v = w * Y[l * l + m];
+          for (int m = 0; m < 2 * l + 1; ++m) {
+            const float v = cur.w[l] * Y[l * l + m];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) M[l * l + m][b] += v * gp[b];
+            for (int b = 0; b < NB; ++b) M[l * l + m][b] += v * cur.gp[b];
+          }
         }
+        cur = nxt;
       }
     }
     float G[NL][NLM];
@@ -410,15 +528,19 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
     for (int q = 0; q < NLM; ++q) GG[q] *= a.inv_sqrt_nbar;
     // per edge: dE/domega^L (Gamma^L's adjoint; for L = 1 also V^0's) and
     // the channel sums of dE/dY
+    In3 cur, nxt;
+    if (eb < ee) fetch3(eb - e0, cur);
+    nxt = cur;
     for (int64_t e = eb; e < ee; ++e) {
       const int64_t t = e - e0;
-      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+      if (e + 1 < ee) fetch3(t + 1, nxt);
+      float Y[NLM];
+      cur.y.get(Y);
       float tot[NLM];
 #pragma unroll
       for (int q = 0; q < NLM; ++q) tot[q] = GG[q];
       if constexpr (L == 1) {
-        float gp[NB];
-        load_slots(t, gp);
+        const float (&gp)[NB] = cur.gp;
         static_for<0, NB>([&](auto B) {
           constexpr int b = decltype(B)::value;
           constexpr int K = SL::layer(b), S = SL::sub(b);
@@ -441,16 +563,16 @@ __global__ void __launch_bounds__(256) k_tp_bwd(TPArgs a) {
       for (int q = 0; q < 16; ++q) gyc[q] = 0.0f;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
         float go = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
           go += tot[l * l + m] * Y[l * l + m];
-          gyc[l * l + m] = tot[l * l + m] * w;
+          gyc[l * l + m] = tot[l * l + m] * cur.w[l];
         }
         st_w<B16>(a.gomega, (t * (LMAX + 1) + l) * CS + nc, go);
       }
-      add_channel_sums<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n);
+      add_channel_sums_to<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n, cur.gy);
+      cur = nxt;
     }
   }
 }
