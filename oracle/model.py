@@ -218,7 +218,15 @@ def sh_torch(l: int, u: torch.Tensor) -> torch.Tensor:
         return torch.stack([s15 * x * y, s15 * y * z,
                             0.5 * math.sqrt(5.0) * (3.0 * z * z - 1.0),
                             s15 * x * z, 0.5 * s15 * (x * x - y * y)], dim=1)
-    raise ValueError("l_max <= 2 in the oracle model")
+    if l == 3:
+        # the l = 3 real harmonics of the same convention (no Condon-Shortley
+        # phase, sum_m Y^2 = 7), m = -3..3
+        a3, a2, a1, a0 = math.sqrt(35.0 / 8.0), math.sqrt(105.0), math.sqrt(21.0 / 8.0), math.sqrt(7.0) / 2.0
+        return torch.stack([a3 * y * (3.0 * x * x - y * y), a2 * x * y * z,
+                            a1 * y * (5.0 * z * z - 1.0), a0 * z * (5.0 * z * z - 3.0),
+                            a1 * x * (5.0 * z * z - 1.0), 0.5 * a2 * z * (x * x - y * y),
+                            a3 * x * (x * x - 3.0 * y * y)], dim=1)
+    raise ValueError("l_max <= 3 in the oracle model")
 
 
 def silu(a: torch.Tensor) -> torch.Tensor:

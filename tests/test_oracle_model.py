@@ -99,6 +99,37 @@ def test_workload_parameter_counts_and_paths():
         assert [len(p) for p in M.path_sets(hp)[0]] == paths
 
 
+def test_sh_torch_matches_scipy_up_to_l3():
+    """The model's torch harmonics against scipy's complex Y_lm (converted to
+    the real, phase-free, component-normalised convention)."""
+    import scipy.special as sps
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((60, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    th, ph = np.arccos(u[:, 2]), np.arctan2(u[:, 1], u[:, 0])
+    for l in range(4):
+        ref = []
+        for m in range(-l, l + 1):
+            Y = sps.sph_harm_y(l, abs(m), th, ph) * math.sqrt(4 * math.pi)
+            ref.append(Y.real if m == 0 else math.sqrt(2) * (-1) ** m * (Y.real if m > 0 else Y.imag))
+        got = M.sh_torch(l, torch.tensor(u, dtype=torch.float64)).numpy()
+        np.testing.assert_allclose(got, np.stack(ref, 1), atol=1e-12)
+
+
+def test_lmax3_path_counts_and_parities():
+    """l_max = 3 in full O(3): 34 + 34 + 4 paths over three layers (23 + 4
+    over two), four scalar paths per layer, every path parity-consistent."""
+    for n_layers, counts in ((3, [34, 34, 4]), (2, [23, 4])):
+        hp = small_hp(l_max=3, n_layers=n_layers)
+        paths, ins, outs = M.path_sets(hp)
+        assert [len(p) for p in paths] == counts
+        assert [M.n_scalar_paths(p) for p in paths] == [4] * n_layers
+        for L, ps in enumerate(paths):
+            for (l1, p1, l2, l3, p3) in ps:
+                assert p3 == p1 * (-1) ** l2 and abs(l1 - l2) <= l3 <= min(l1 + l2, 3)
+                assert (l1, p1) in ins[L]
+
+
 def test_path_parities():
     hp = hp_of("E")
     paths, ins, outs = M.path_sets(hp)
@@ -144,6 +175,26 @@ def test_invariances_and_equivariance_cluster():
     np.testing.assert_allclose(Wv, Wv.T, atol=1e-11)
 
 
+def test_invariances_and_equivariance_lmax3():
+    """The same symmetries with l_max = 3 (rotation and rotoreflection of a
+    cluster, translation, permutation)."""
+    hp = small_hp(l_max=3)
+    w = weights(hp, 7)
+    s = cluster(12, 5)
+    base = _energy(hp, w, s)
+    rng = np.random.default_rng(8)
+    Q = so3.random_rotation(rng)
+    for R in (Q, -Q):
+        s2 = dataclasses.replace(s, pos=s.pos @ R.T + rng.standard_normal(3))
+        r2 = _energy(hp, w, s2)
+        np.testing.assert_allclose(r2["e_atom"], base["e_atom"], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(r2["forces"], base["forces"] @ R.T, atol=1e-11)
+    perm = rng.permutation(s.n_atoms)
+    r3 = _energy(hp, w, dataclasses.replace(s, pos=s.pos[perm], species=s.species[perm]))
+    np.testing.assert_allclose(r3["e_atom"], base["e_atom"][perm], rtol=1e-12)
+    np.testing.assert_allclose(base["forces"].sum(0), 0, atol=1e-12)
+
+
 def test_invariance_periodic_rotated_cell():
     hp = small_hp(r_cut=3.9, n_species=2)
     w = weights(hp)
@@ -160,13 +211,13 @@ def test_invariance_periodic_rotated_cell():
 
 # ------------------------------------------------------ finite differences
 
-@pytest.mark.parametrize("name", ["A", "small"])
+@pytest.mark.parametrize("name", ["A", "small", "small_lmax3"])
 def test_forces_central_differences(name):
     if name == "A":
         hp = hp_of("A", avg_num_neighbors=14.8)
         s = synth.config_a()
     else:
-        hp = small_hp()
+        hp = small_hp(l_max=3) if name == "small_lmax3" else small_hp()
         s = synth.config_a()
         s = dataclasses.replace(s, n_species=3)
     w = weights(hp)

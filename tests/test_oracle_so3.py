@@ -150,7 +150,29 @@ def _real_basis(l):
     return U
 
 
-@pytest.mark.parametrize("t", TRIPLES)
+# every coupling the l_max = 3 models use (l <= 3)
+TRIPLES3 = [(l1, l2, l3) for l1 in range(4) for l2 in range(4)
+            for l3 in range(abs(l1 - l2), min(l1 + l2, 3) + 1)]
+
+
+def test_cg_invariance_l3():
+    """C^{l1 l2 l3} is invariant under D^{l1} x D^{l2} x D^{l3}, with D^l taken
+    from the harmonics themselves (Y^l(R u) = D^l(R) Y^l(u), least squares over
+    random directions), for every coupling with l <= 3."""
+    rng = np.random.default_rng(11)
+    R = so3.random_rotation(rng)
+    u = _units(300, 12)
+    D = {l: np.linalg.lstsq(so3.real_sh(l, u), so3.real_sh(l, u @ R.T), rcond=None)[0].T
+         for l in range(4)}
+    for t in TRIPLES3:
+        l1, l2, l3 = t
+        C = so3.cg(*t)
+        rot = np.einsum("ia,jb,kc,abc->ijk", D[l1], D[l2], D[l3], C)
+        np.testing.assert_allclose(rot, C, atol=1e-10, err_msg=str(t))
+        np.testing.assert_allclose(np.sum(C ** 2), 2 * l3 + 1, atol=1e-12)
+
+
+@pytest.mark.parametrize("t", TRIPLES3)
 def test_cg_matches_sympy(t):
     """Real CG from sympy's exact complex coefficients, up to the convention
     (normalisation, sign of the first nonzero entry)."""
