@@ -89,7 +89,7 @@ typedef enum {
  * environment sum by its inverse square root. */
 typedef struct {
   int32_t n_species;
-  int32_t l_max;          /* 0, 1 or 2 */
+  int32_t l_max;          /* 0..3 (3: one or two layers, 16 or 64 channels) */
   int32_t n_layers;       /* >= 1 */
   int32_t latent;         /* latent width w (multiple of 16) */
   int32_t channels;       /* tensor channels c: 8, 16, 32, 64 or 128 */

@@ -1,4 +1,4 @@
-// Real Clebsch-Gordan tensors computed at compile time (l <= 2), so the
+// Real Clebsch-Gordan tensors computed at compile time (l <= 3), so the
 // tensor-product kernels can unroll over exactly the nonzero entries with
 // immediate coefficients.  Same derivation and conventions as the host
 // table (Racah's closed formula for the complex coefficients, real basis of
@@ -69,28 +69,37 @@ constexpr Cx basis(int l, int row, int col) {
 }
 
 struct Tensor {
-  double v[125] = {};
+  double v[343] = {};   // up to 7 x 7 x 7
 };
 
 constexpr Tensor real_cg(int l1, int l2, int l3) {
   Tensor T{};
   const int d1 = 2 * l1 + 1, d2 = 2 * l2 + 1, d3 = 2 * l3 + 1;
-  Cx C[125] = {};
+  Cx C[343] = {};
   double mr = 0.0, mi = 0.0;
   for (int i = 0; i < d1; ++i)
     for (int j = 0; j < d2; ++j)
       for (int k = 0; k < d3; ++k) {
         Cx acc{};
-        for (int a = 0; a < d1; ++a)
+        // each real-basis row has at most two nonzero complex entries, so
+        // test those before evaluating the Racah sum
+        for (int a = 0; a < d1; ++a) {
+          const Cx u1 = basis(l1, i, a);
+          if (u1.re == 0.0 && u1.im == 0.0) continue;
           for (int b = 0; b < d2; ++b) {
+            const Cx u2 = basis(l2, j, b);
+            if (u2.re == 0.0 && u2.im == 0.0) continue;
             const int c = (a - l1) + (b - l2) + l3;
             if (c < 0 || c >= d3) continue;
+            const Cx u3 = basis(l3, k, c);
+            if (u3.re == 0.0 && u3.im == 0.0) continue;
             const double cc = cg_complex(l1, a - l1, l2, b - l2, l3, c - l3);
             if (cc == 0.0) continue;
-            Cx t = mul(mul(conj(basis(l1, i, a)), conj(basis(l2, j, b))), basis(l3, k, c));
+            Cx t = mul(mul(conj(u1), conj(u2)), u3);
             acc.re += t.re * cc;
             acc.im += t.im * cc;
           }
+        }
         C[(i * d2 + j) * d3 + k] = acc;
         mr = mr > abs_(acc.re) ? mr : abs_(acc.re);
         mi = mi > abs_(acc.im) ? mi : abs_(acc.im);
@@ -117,8 +126,8 @@ constexpr Tensor real_cg(int l1, int l2, int l3) {
 // nonzero entries of one tensor
 struct Nz {
   int n = 0;
-  int m1[25] = {}, m2[25] = {}, m3[25] = {};
-  float c[25] = {};
+  int m1[48] = {}, m2[48] = {}, m3[48] = {};   // at most 42 nonzeros for l <= 3
+  float c[48] = {};
 };
 
 constexpr Nz nonzeros(int l1, int l2, int l3) {

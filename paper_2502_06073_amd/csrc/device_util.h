@@ -117,4 +117,34 @@ __device__ __forceinline__ void sh9_grad(float x, float y, float z, const float*
   gu[0] = gx; gu[1] = gy; gu[2] = gz;
 }
 
+// Y^3 (m = -3..3, no Condon-Shortley phase, sum_m Y^2 = 7 on the sphere),
+// written with x^2 + y^2 + z^2 = 1 substituted; the gradient of these
+// polynomial forms differs from the homogeneous ones only radially, which
+// the tangent-plane projection of the caller removes.
+__device__ __forceinline__ void sh_l3(float x, float y, float z, float* Y) {
+  const float a3 = 2.091650066335189f, a2 = 10.246950765959598f, a1 = 1.620185174601965f,
+              a0 = 1.3228756555322954f;
+  Y[0] = a3 * y * (3.0f * x * x - y * y);
+  Y[1] = a2 * x * y * z;
+  Y[2] = a1 * y * (5.0f * z * z - 1.0f);
+  Y[3] = a0 * z * (5.0f * z * z - 3.0f);
+  Y[4] = a1 * x * (5.0f * z * z - 1.0f);
+  Y[5] = 0.5f * a2 * z * (x * x - y * y);
+  Y[6] = a3 * x * (x * x - 3.0f * y * y);
+}
+// gu += sum_k gY[k] dY^3_k / d(x, y, z)
+__device__ __forceinline__ void sh_l3_grad(float x, float y, float z, const float* gY, float* gu) {
+  const float a3 = 2.091650066335189f, a2 = 10.246950765959598f, a1 = 1.620185174601965f,
+              a0 = 1.3228756555322954f;
+  float gx = 0, gy = 0, gz = 0;
+  gx += a3 * 6.0f * x * y * gY[0];            gy += a3 * 3.0f * (x * x - y * y) * gY[0];
+  gx += a2 * y * z * gY[1];                   gy += a2 * x * z * gY[1];               gz += a2 * x * y * gY[1];
+  gy += a1 * (5.0f * z * z - 1.0f) * gY[2];   gz += a1 * 10.0f * y * z * gY[2];
+  gz += a0 * (15.0f * z * z - 3.0f) * gY[3];
+  gx += a1 * (5.0f * z * z - 1.0f) * gY[4];   gz += a1 * 10.0f * x * z * gY[4];
+  gx += a2 * x * z * gY[5];                   gy -= a2 * y * z * gY[5];               gz += 0.5f * a2 * (x * x - y * y) * gY[5];
+  gx += a3 * 3.0f * (x * x - y * y) * gY[6];  gy -= a3 * 6.0f * x * y * gY[6];
+  gu[0] += gx; gu[1] += gy; gu[2] += gz;
+}
+
 }  // namespace afm

@@ -8,6 +8,8 @@ namespace afm {
 // geo[t][16]: delta (3, float32 from the float64 difference), |delta|,
 // envelope u, the 9 spherical-harmonic components (l <= 2), 2 unused.
 constexpr int GEO_D = 3, GEO_U = 4, GEO_Y = 5, GEO_STRIDE = 16;
+// l_max = 3 only: geo3[t][8] holds Y^3 (7 values), gy3[t][8] its adjoint
+constexpr int GEO3_STRIDE = 8;
 
 // Row (central atom) and edge range of one chunk, read on the device.
 struct RowRange {
@@ -44,6 +46,8 @@ struct TPArgs {
   float inv_sqrt_nbar;
   void* gomega;          // dE/domega^L [t][lmax+1][C]
   float* gy;             // dE/dY [t][16]  (+=), dE/du at [9]
+  const float* geo3;     // Y^3 [t][8] (l_max = 3, else null)
+  float* gy3;            // dE/dY^3 [t][8] (+=; l_max = 3, else null)
   // first channel of this launch: a launch covers channels [c0, c0 + C)
   // of the arrays' channels (the products are channelwise)
   int c0;

@@ -70,7 +70,8 @@ __device__ __forceinline__ float envelope_dx_f(float x, int p) {
 __global__ void k_geometry(RowRange rr, const double* __restrict__ pos, const double* __restrict__ cell,
                            const uint8_t* __restrict__ pbc, const int64_t* __restrict__ seg, int64_t B,
                            const int32_t* __restrict__ col, const int8_t* __restrict__ shift, float r_cut,
-                           int poly_p, int32_t* __restrict__ eidx, float* __restrict__ geo) {
+                           int poly_p, int32_t* __restrict__ eidx, float* __restrict__ geo,
+                           float* __restrict__ geo3) {
   const int64_t a0 = rr.chunk_rows[rr.chunk], a1 = rr.chunk_rows[rr.chunk + 1];
   const int64_t e0 = rr.row_ptr[a0], e1 = rr.row_ptr[a1];
   for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e1;
@@ -95,6 +96,14 @@ __global__ void k_geometry(RowRange rr, const double* __restrict__ pos, const do
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[GEO_Y + q] = Y[q];
     g[14] = 0.0f; g[15] = 0.0f;
+    if (geo3) {   // l_max = 3
+      float Y3[7];
+      sh_l3(dx * inv, dy * inv, dz * inv, Y3);
+      float* g3 = geo3 + t * GEO3_STRIDE;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) g3[q] = Y3[q];
+      g3[7] = 0.0f;
+    }
     eidx[t] = (int32_t)i;
   }
 }
@@ -281,8 +290,8 @@ __global__ void __launch_bounds__(256) k_mlp_head_bwd(RowRange rr, int w, const 
 
 // g_e = dE/d delta_e from dE/drho, dE/du and dE/dY
 __global__ void k_geometry_bwd(RowRange rr, const float* __restrict__ geo, const float* __restrict__ grho,
-                               const float* __restrict__ gy, int nb, float r_cut, int poly_p,
-                               float* __restrict__ g) {
+                               const float* __restrict__ gy, const float* __restrict__ gy3, int nb, float r_cut,
+                               int poly_p, float* __restrict__ g) {
   int64_t e0, e1;
   rr.get(e0, e1);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < e1 - e0;
@@ -308,6 +317,7 @@ __global__ void k_geometry_bwd(RowRange rr, const float* __restrict__ geo, const
       }
       float gu3[3];
       sh9_grad(ux, uy, uz, gy + t * GEO_STRIDE, gu3);
+      if (gy3) sh_l3_grad(ux, uy, uz, gy3 + t * GEO3_STRIDE, gu3);   // l_max = 3
       const float dot = gu3[0] * ux + gu3[1] * uy + gu3[2] * uz;
       out[0] = gd * ux + (gu3[0] - dot * ux) * inv;
       out[1] = gd * uy + (gu3[1] - dot * uy) * inv;
@@ -461,6 +471,8 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   a.alpha = layer < d.NL ? m->W.alpha[layer - 1] : nullptr;
   a.inv_sqrt_nbar = (float)(1.0 / sqrt(d.nbar));
   a.gy = ws_ptr<float>(ws, L.gy);
+  a.geo3 = d.lmax == 3 ? ws_ptr<float>(ws, L.geo3) : nullptr;
+  a.gy3 = d.lmax == 3 ? ws_ptr<float>(ws, L.gy3) : nullptr;
   a.gomega = ws_ptr<float>(ws, L.gomega);
   return a;
 }
@@ -469,7 +481,8 @@ int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const 
                     RowRange rr, hipStream_t st) {
   hipLaunchKernelGGL(k_geometry, dim3(grid_for(L.cex, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
                      s.seg, s.B, (const int32_t*)nl.col, (const int8_t*)nl.shift, (float)m->dims.r_cut, m->dims.p,
-                     ws_ptr<int32_t>(ws, L.eidx), ws_ptr<float>(ws, L.geo));
+                     ws_ptr<int32_t>(ws, L.eidx), ws_ptr<float>(ws, L.geo),
+                     m->dims.lmax == 3 ? ws_ptr<float>(ws, L.geo3) : nullptr);
   AFM_LAUNCH_CHECK();
   return AFM_OK;
 }
@@ -487,7 +500,7 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
     TraceScope tr(st, "geometry");
     hipLaunchKernelGGL(k_geometry, dim3(grid_for(E, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
                        s.seg, s.B, (const int32_t*)nl.col, (const int8_t*)nl.shift, (float)d.r_cut, d.p, eidx,
-                       geo);
+                       geo, d.lmax == 3 ? ws_ptr<float>(ws, L.geo3) : nullptr);
     AFM_LAUNCH_CHECK();
   }
   if (m->prec == AFM_BF16_MFMA) {
@@ -576,6 +589,7 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
   float* gy = ws_ptr<float>(ws, L.gy);
   const int cw = (d.lmax + 1) * d.c;
   int rc = zero_async(gy, E * 64, st);
+  if (!rc && d.lmax == 3) rc = zero_async(ws_ptr<float>(ws, L.gy3), E * GEO3_STRIDE * 4, st);
   if (rc) return rc;
   for (int layer = d.NL; layer >= 1; --layer) {
     const LayerPlan& lp = P.layer[layer - 1];
@@ -647,7 +661,8 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
   }
   TraceScope tr(st, "geometry_bwd");
   hipLaunchKernelGGL(k_geometry_bwd, dim3(grid_for(E, 256, 65536)), dim3(256), 0, st, rr, (const float*)geo,
-                     (const float*)ws_ptr<float>(ws, L.grho), (const float*)gy, d.nb, (float)d.r_cut, d.p,
+                     (const float*)ws_ptr<float>(ws, L.grho), (const float*)gy,
+                     d.lmax == 3 ? (const float*)ws_ptr<float>(ws, L.gy3) : nullptr, d.nb, (float)d.r_cut, d.p,
                      ws_ptr<float>(ws, L.g));
   AFM_LAUNCH_CHECK();
   return AFM_OK;

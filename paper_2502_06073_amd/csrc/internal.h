@@ -118,6 +118,7 @@ struct WsLayout {
   int64_t gy = 0;                            // float [CEX][16] (GY[9], Gu at [9])
   int64_t gomega = 0;                        // float [CEX][(lmax+1)c]
   int64_t grho = 0;                          // float [CEX][16]
+  int64_t geo3 = 0, gy3 = 0;                 // float [CEX][8] Y^3 and dE/dY^3 (l_max = 3 only)
   // second order (stacked rows: primal [0, CEX), tangent [CEX, 2 CEX))
   int64_t so_geo2 = 0;                                   // float [CEX][16]
   int64_t so_tb_pre[kMaxTwobody] = {};                   // float [2CEX][tb_k]

@@ -203,7 +203,9 @@ struct ChainArgs {
   X(32, 8, 1, 2, 16, 32, 0, 2)              \
   X(64, 16, 2, 3, 16, 32, 64, 3)            \
   X(128, 32, 2, 3, 32, 64, 128, 3)          \
-  X(256, 64, 2, 3, 64, 128, 256, 3)
+  X(256, 64, 2, 3, 64, 128, 256, 3)         \
+  X(64, 16, 3, 3, 16, 32, 64, 4)            \
+  X(256, 64, 3, 3, 64, 128, 256, 4)
 // the 512-wide model (Table 1's largest: c = 128, two-body [128, 256, 512]);
 // its LDS tiles fit only the 64-edge shape
 #define AFM_SHAPES_WIDE(X)                  \
@@ -232,6 +234,7 @@ int mfma_check_shape(const afm_model* m) {
 #undef X
   set_error("BF16 MFMA kernels are built for (w, c, l_max, depth, two-body) = (32,8,1,2,[16,32]), "
             "(64,16,2,3,[16,32,64]), (128,32,2,3,[32,64,128]), (256,64,2,3,[64,128,256]), "
+            "(64,16,3,3,[16,32,64]), (256,64,3,3,[64,128,256]), "
             "(512,128,2,3,[128,256,512]; 64-edge tiles only)");
   return AFM_E_UNSUPPORTED;
 }

@@ -24,7 +24,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 static int dims_of(const afm_hparams* hp, ModelDims* d) {
   if (!hp) { set_error("null hparams"); return AFM_E_INVALID; }
   if (hp->n_species < 1 || hp->n_species > kMaxSpecies) { set_error("n_species out of range"); return AFM_E_INVALID; }
-  if (hp->l_max < 0 || hp->l_max > kMaxLmax) { set_error("l_max must be 0..2"); return AFM_E_UNSUPPORTED; }
+  if (hp->l_max < 0 || hp->l_max > kMaxLmax) { set_error("l_max must be 0..3"); return AFM_E_UNSUPPORTED; }
   if (hp->n_layers < 1 || hp->n_layers > 3) { set_error("n_layers must be 1..3"); return AFM_E_UNSUPPORTED; }
   if (hp->n_twobody < 1 || hp->n_twobody > kMaxTwobody) { set_error("n_twobody must be 1..4"); return AFM_E_INVALID; }
   if (hp->latent_depth < 1 || hp->latent_depth > kMaxDepth) { set_error("latent_depth must be 1..4"); return AFM_E_INVALID; }
@@ -34,6 +34,9 @@ static int dims_of(const afm_hparams* hp, ModelDims* d) {
     if (hp->twobody[k] < 1) { set_error("bad two-body width"); return AFM_E_INVALID; }
   if (hp->channels != 8 && hp->channels != 16 && hp->channels != 32 && hp->channels != 64 && hp->channels != 128) {
     set_error("channels must be 8, 16, 32, 64 or 128"); return AFM_E_UNSUPPORTED;
+  }
+  if (hp->l_max == 3 && (hp->n_layers > 2 || (hp->channels != 16 && hp->channels != 64))) {
+    set_error("l_max = 3 is built for 1 or 2 layers and 16 or 64 channels"); return AFM_E_UNSUPPORTED;
   }
   if (hp->n_bessel < 1 || hp->n_bessel > 16) { set_error("n_bessel must be 1..16"); return AFM_E_INVALID; }
   if (hp->poly_p < 2) { set_error("poly_p must be >= 2"); return AFM_E_INVALID; }
@@ -193,7 +196,7 @@ int real_cg(int l1, int l2, int l3, double* out) {
 
 // the kernels' compile-time tables must equal the runtime derivation
 static bool cg_tables_agree() {
-  double buf[125];
+  double buf[343];
   for (int a = 0; a <= kMaxLmax; ++a)
     for (int b = 0; b <= kMaxLmax; ++b)
       for (int c = abs(a - b); c <= a + b && c <= kMaxLmax; ++c) {
@@ -272,6 +275,10 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
   L.gy = take(E * 64);
   L.gomega = take(E * (d.lmax + 1) * d.c * 4);
   L.grho = take(E * 64);
+  if (d.lmax == 3) {
+    L.geo3 = take(E * GEO3_STRIDE * 4);
+    L.gy3 = take(E * GEO3_STRIDE * 4);
+  }
   if (ws->with_second_order) {
     const int64_t E2 = 2 * E;
     const int envw = (d.lmax + 1) * d.c;

@@ -17,11 +17,11 @@
 
 namespace afm {
 
-constexpr int kMaxLmax = 2;
+constexpr int kMaxLmax = 3;
 constexpr int kMaxLayers = 4;
-constexpr int kMaxPaths = 24;
-constexpr int kMaxIrreps = 6;
-constexpr int kMaxComps = 18;   // sum of (2l+1) over the irreps of one layer
+constexpr int kMaxPaths = 40;   // l_max = 3 in full O(3): 34 in a hidden layer
+constexpr int kMaxIrreps = 8;
+constexpr int kMaxComps = 32;   // sum of (2l+1) over the irreps of one layer
 
 struct Irrep {
   int l = 0, p = 1;

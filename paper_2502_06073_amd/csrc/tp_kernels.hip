@@ -34,21 +34,6 @@ __device__ __forceinline__ void st_w(void* p, int64_t i, float v) {
   if constexpr (B16) static_cast<uint16_t*>(p)[i] = to_bf16_bits(v);
   else static_cast<float*>(p)[i] = v;
 }
-// dst[q] += sum over the C channels (lanes n of one group) of v[q], q < NV
-template <int C, int NV>
-__device__ __forceinline__ void add_channel_sums(float (&v)[16], float* dst, int n) {
-  if constexpr (C == 64) {
-    const float y = wave_sum16(v, n);
-    if ((n & 3) == 0 && (n >> 2) < NV) dst[n >> 2] += y;
-  } else {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const float y = group_sum<C>(v[q]);
-      if (n == 0) dst[q] += y;
-    }
-  }
-}
-
 template <int LMAX, int NL, int K>
 struct LayerCT {
   static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[K - 1];
@@ -76,17 +61,21 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 }
 // Y^{l <= LMAX} of an edge, fetched ahead of its use (the edge loops issue
 // the next edge's loads before working on the current one)
+// (Y^0..Y^2 in the geometry record, Y^3 in its own for l_max = 3)
 template <int C, int NLM>
 struct YFetch {
   float v[C == 64 ? 1 : NLM];
-  __device__ __forceinline__ void fetch(const float* geo, int64_t t) {
-    const float* p = geo + t * GEO_STRIDE + GEO_Y;
+  __device__ __forceinline__ void fetch(const TPArgs& a, int64_t t) {
+    const float* p = a.geo + t * GEO_STRIDE + GEO_Y;
     if constexpr (C == 64) {
       const int lane = threadIdx.x & 63;
-      v[0] = lane < NLM ? p[lane] : 0.0f;
+      if constexpr (NLM > 9)
+        v[0] = lane < 9 ? p[lane] : (lane < NLM ? a.geo3[t * GEO3_STRIDE + lane - 9] : 0.0f);
+      else
+        v[0] = lane < NLM ? p[lane] : 0.0f;
     } else {
 #pragma unroll
-      for (int q = 0; q < NLM; ++q) v[q] = p[q];
+      for (int q = 0; q < NLM; ++q) v[q] = q < 9 ? p[q] : a.geo3[t * GEO3_STRIDE + q - 9];
     }
   }
   __device__ __forceinline__ void get(float (&Y)[NLM]) const {
@@ -100,24 +89,33 @@ struct YFetch {
   }
 };
 
+// accumulator of dE/dY_q of edge t (q >= 9: the l = 3 record)
+__device__ __forceinline__ float* gy_slot(const TPArgs& a, int64_t t, int q) {
+  return q < 9 ? a.gy + t * GEO_STRIDE + q : a.gy3 + t * GEO3_STRIDE + (q - 9);
+}
 // the dE/dY accumulators an edge's channel sums are added to (C = 64: lane
 // 4k holds value k), fetched ahead like the other per-edge inputs
 template <int C, int NV>
 struct GyFetch {
   float v;
-  __device__ __forceinline__ void fetch(const float* gy_t, int n) {
-    if constexpr (C == 64) v = ((n & 3) == 0 && (n >> 2) < NV) ? gy_t[n >> 2] : 0.0f;
+  __device__ __forceinline__ void fetch(const TPArgs& a, int64_t t, int n) {
+    if constexpr (C == 64) v = ((n & 3) == 0 && (n >> 2) < NV) ? *gy_slot(a, t, n >> 2) : 0.0f;
     else v = 0.0f;
   }
 };
-// dst[q] = (fetched) dst[q] + sum over the C channels of v[q], q < NV
+// dE/dY_q(t) = (fetched) dE/dY_q(t) + sum over the C channels of v[q], q < NV
 template <int C, int NV>
-__device__ __forceinline__ void add_channel_sums_to(float (&v)[16], float* dst, int n, const GyFetch<C, NV>& old) {
+__device__ __forceinline__ void add_channel_sums_to(float (&v)[16], const TPArgs& a, int64_t t, int n,
+                                                    const GyFetch<C, NV>& old) {
   if constexpr (C == 64) {
     const float y = wave_sum16(v, n);
-    if ((n & 3) == 0 && (n >> 2) < NV) dst[n >> 2] = old.v + y;
+    if ((n & 3) == 0 && (n >> 2) < NV) *gy_slot(a, t, n >> 2) = old.v + y;
   } else {
-    add_channel_sums<C, NV>(v, dst, n);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const float y = group_sum<C>(v[q]);
+      if (n == 0) *gy_slot(a, t, q) += y;
+    }
   }
 }
 
@@ -324,7 +322,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
     float w[LMAX + 1];
   };
   auto fetch = [&](int64_t t, const void* om, EdgeIn& x) {
-    x.y.fetch(a.geo, t);
+    x.y.fetch(a, t);
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(om, (t * (LMAX + 1) + l) * CS + nc);
   };
@@ -405,11 +403,11 @@ __global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
 // R^{L-1} M[:, b].  Layer 1 also needs dE/dV^0_e = D g'_e per edge (D: the
 // rows of every layer's P, formed alongside).
 // occupancy floor of the adjoint kernels (register budget 512 / waves)
-template <int NL, int L>
-constexpr int tp_bwd_waves() { return (L == 1 && NL >= 3) ? 3 : 4; }
+template <int LMAX, int NL, int L>
+constexpr int tp_bwd_waves() { return LMAX == 3 ? 2 : (L == 1 && NL >= 3) ? 3 : 4; }
 
 template <int LMAX, int NL, int L, int C, bool B16, int CS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_bwd_waves<NL, L>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_bwd_waves<LMAX, NL, L>())))
 k_tp_bwd(TPArgs a) {
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NA = 256 / C;
@@ -439,17 +437,17 @@ k_tp_bwd(TPArgs a) {
     GyFetch<C, NLM> gy;
   };
   auto fetch1 = [&](int64_t t, In1& x) {
-    x.y.fetch(a.geo, t);
+    x.y.fetch(a, t);
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(a.omega1, (t * (LMAX + 1) + l) * CS + nc);
     load_slots(t, x.gp);
   };
   auto fetch3 = [&](int64_t t, In3& x) {
-    x.y.fetch(a.geo, t);
+    x.y.fetch(a, t);
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) x.w[l] = ld_w<B16>(a.omega, (t * (LMAX + 1) + l) * CS + nc);
     if constexpr (L == 1) load_slots(t, x.gp);
-    x.gy.fetch(a.gy + t * GEO_STRIDE, n);
+    x.gy.fetch(a, t, n);
   };
   for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
     const int64_t eb = uniform64<C>(a.rr.row_ptr[i]), ee = uniform64<C>(a.rr.row_ptr[i + 1]);
@@ -571,7 +569,7 @@ k_tp_bwd(TPArgs a) {
         }
         st_w<B16>(a.gomega, (t * (LMAX + 1) + l) * CS + nc, go);
       }
-      add_channel_sums_to<C, NLM>(gyc, a.gy + t * GEO_STRIDE, n, cur.gy);
+      add_channel_sums_to<C, NLM>(gyc, a, t, n, cur.gy);
       cur = nxt;
     }
   }
@@ -610,12 +608,21 @@ static tp_kernel_t pick_c(int C, int NL, int L, bool bwd) {
   return nullptr;
 }
 
+// l_max = 3: one or two layers, 16 or 64 channels
+template <bool B16>
+static tp_kernel_t pick_c3(int C, int NL, int L, bool bwd) {
+  if (NL == 1) return C == 16 ? pick<3, 1, 16, B16, 16>(L, bwd) : C == 64 ? pick<3, 1, 64, B16, 64>(L, bwd) : nullptr;
+  if (NL == 2) return C == 16 ? pick<3, 2, 16, B16, 16>(L, bwd) : C == 64 ? pick<3, 2, 64, B16, 64>(L, bwd) : nullptr;
+  return nullptr;
+}
+
 template <bool B16>
 static tp_kernel_t pick_l(int lmax, int C, int NL, int L, bool bwd) {
   switch (lmax) {
     case 0: return pick_c<0, B16>(C, NL, L, bwd);
     case 1: return pick_c<1, B16>(C, NL, L, bwd);
     case 2: return pick_c<2, B16>(C, NL, L, bwd);
+    case 3: return pick_c3<B16>(C, NL, L, bwd);
   }
   return nullptr;
 }

@@ -57,7 +57,7 @@ def test_table1_counts_through_library():
         assert sum(b["size"] for b in afm.param_layout(hp)) == want[w]
 
 
-@pytest.mark.parametrize("t", [(l1, l2, l3) for l1 in range(3) for l2 in range(3)
+@pytest.mark.parametrize("t", [(l1, l2, l3) for l1 in range(4) for l2 in range(4)
                                for l3 in range(abs(l1 - l2), min(l1 + l2, 3) + 1)])
 def test_cg_tables_match_oracle(t):
     _lib()
@@ -77,9 +77,15 @@ def test_host_error_paths():
     assert rc == -4                                 # FP64 on the device is not built
     rc = lib.afm_model_create(None, None, 0, 1, C.byref(out))
     assert rc == -1
-    bad = afm.hparams_struct(dict(hp, l_max=3))
     nb, npar = C.c_int64(), C.c_int64()
-    assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == -4
+    for kw in (dict(l_max=4), dict(l_max=3),                       # l = 4; 8 channels at l = 3
+               dict(l_max=3, channels=16, n_layers=3)):            # three layers at l = 3
+        bad = afm.hparams_struct(dict(hp, **kw))
+        assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == -4, kw
+    ok = afm.hparams_struct(dict(hp, l_max=3, channels=16, n_layers=2))
+    assert lib.afm_param_layout_size(C.byref(ok), C.byref(nb), C.byref(npar)) == 0
+    assert npar.value == M.n_params(M.HParams.from_dict(dict(hp, l_max=3, channels=16, n_layers=2,
+                                                              avg_num_neighbors=1.0, energy_scale=1.0)))
     bad = afm.hparams_struct(dict(hp, twobody=[16, 48]))
     assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == -1
     ws = _abi.Workspace()
