@@ -15,7 +15,11 @@
 // The _mfma variants (second-order path) stage the same LDS tiles and
 // multiply them on the matrix cores in FP32 (v_mfma_f32_16x16x4f32, FP32
 // products and accumulation): each of the 4 wavefronts owns a 32 x 32
-// quarter of the tile as 2 x 2 blocks of 16 x 16.
+// quarter of the tile as 2 x 2 blocks of 16 x 16.  The _bf16 variants (the
+// second-order path of BF16 models) round both operands to bf16 when they
+// are staged and multiply on v_mfma_f32_16x16x32_bf16 (FP32 accumulation):
+// a stage covers 32 of the reduction index, held as rows of 8 consecutive
+// values per lane group.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -312,6 +316,182 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(RowRange rr, int stack, int 
         if (k < K) P[(int64_t)n * K + k] = acc[i][j][q];
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA variants
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// LDS tile of 64 rows x 32 reduction values in bf16, rows padded to 40
+// values (80 bytes) so a lane's 8 values are one aligned 16-byte read.
+constexpr int kBfRow = 40;
+
+// 8 bf16 values [8 g, 8 g + 8) of row r
+__device__ __forceinline__ bf16x8_t lds_row8(const __bf16* T, int r, int g) {
+  return *reinterpret_cast<const bf16x8_t*>(T + r * kBfRow + 8 * g);
+}
+
+template <bool NT, class AL, class EP>
+__global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, const float* __restrict__ W, int ldw,
+                                                    AL al, EP ep, int stack) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int rows = stack ? 2 * stack : M;
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= rows) return;
+  if (stack && (m0 % stack) >= M) return;
+  const int n0 = blockIdx.y * 64;
+  constexpr int KS = 32;
+  __shared__ __attribute__((aligned(16))) __bf16 As[64 * kBfRow];   // [m][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64 * kBfRow];   // [n][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  // next stage fetched into registers while the current one is multiplied;
+  // A: element (r, kk) = (idx / 32, idx % 32), consecutive lanes along k
+  float ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx >> 5, kk = idx & 31;
+      const int m = m0 + r, k = k0 + kk;
+      ra[q] = (m < rows && row_live(m, M, stack) && k < K) ? al(m, k) : 0.0f;
+      int c, kb;
+      if (NT) { c = idx >> 5; kb = idx & 31; } else { kb = idx >> 6; c = idx & 63; }
+      const int k2 = k0 + kb, n = n0 + c;
+      float v = 0.0f;
+      if (k2 < K && n < N) v = NT ? W[(int64_t)n * ldw + k2] : W[(int64_t)k2 * ldw + n];
+      rb[q] = v;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      As[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)ra[q];
+      if (NT) Bs[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)rb[q];
+      else Bs[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)rb[q];
+    }
+    __syncthreads();
+    if (k0 + KS < K) fetch(k0 + KS);
+    bf16x8_t a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = lds_row8(As, 32 * wr + 16 * i + lr, lg);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = lds_row8(Bs, 32 * wc + 16 * j + lr, lg);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + 32 * wr + 16 * i + 4 * lg + q;
+      if (m >= rows || !row_live(m, M, stack)) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 32 * wc + 16 * j + lr;
+        if (n < N) ep(m, n, acc[i][j][q]);
+      }
+    }
+}
+
+template <class ALA, class ALB>
+__global__ void __launch_bounds__(256) k_wgrad_bf16(RowRange rr, int stack, int N, int K, int rows_per_slice,
+                                                    ALA A, ALB Bl, float* __restrict__ partial) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int rows = stack ? 2 * stack : M;
+  const int n0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+  const int slice = blockIdx.z;
+  const int r0 = slice * rows_per_slice;
+  const int r1 = min(rows, r0 + rows_per_slice);
+  constexpr int MS = 32;  // rows (the reduction index) per stage
+  __shared__ __attribute__((aligned(16))) __bf16 As[64 * kBfRow];   // [n][m]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64 * kBfRow];   // [k][m]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  float ra[8], rb[8];
+  auto fetch = [&](int m0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      const int mm = idx >> 6, c = idx & 63;
+      const int m = m0 + mm;
+      const bool live = m < r1 && row_live(m, M, stack);
+      ra[q] = (live && n0 + c < N) ? A(m, n0 + c) : 0.0f;
+      rb[q] = (live && k0 + c < K) ? Bl(m, k0 + c) : 0.0f;
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int m0 = r0; m0 < r1; m0 += MS) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q;
+      As[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)ra[q];
+      Bs[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)rb[q];
+    }
+    __syncthreads();
+    if (m0 + MS < r1) fetch(m0 + MS);
+    bf16x8_t a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = lds_row8(As, 32 * wr + 16 * i + lr, lg);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = lds_row8(Bs, 32 * wc + 16 * j + lr, lg);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+    __syncthreads();
+  }
+  float* P = partial + (int64_t)slice * N * K;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * wr + 16 * i + 4 * lg + q;
+      if (n >= N) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + 32 * wc + 16 * j + lr;
+        if (k < K) P[(int64_t)n * K + k] = acc[i][j][q];
+      }
+    }
+}
+
+// the second-order GEMM: BF16 MFMA for BF16 models, FP32 MFMA otherwise
+template <bool NT, class AL, class EP>
+inline void sgemm_so(bool bf16, hipStream_t st, RowRange rr, int64_t max_rows, int K, int N, const float* W, int ldw,
+                     AL al, EP ep, int stack) {
+  const int64_t rows = stack ? 2 * (int64_t)stack : max_rows;
+  dim3 grid((unsigned)((rows + 63) / 64 > 0 ? (rows + 63) / 64 : 1), (unsigned)((N + 63) / 64));
+  if (bf16)
+    hipLaunchKernelGGL((k_sgemm_bf16<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
+  else
+    hipLaunchKernelGGL((k_sgemm_mfma<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
 }
 
 }  // namespace afm

@@ -1022,7 +1022,7 @@ static int64_t block_offset(const afm_model* m, const char* name) {
 }
 
 template <class ALA, class ALB>
-static int wgrad(hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, ALB Bl, float* partial,
+static int wgrad(bool bf16, hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, ALB Bl, float* partial,
                  double* gacc, int64_t off, int env_c = 0, int env_l1 = 0) {
   const int rows = 2 * stack;
   const int tiles = ((N + 63) / 64) * ((K + 63) / 64);
@@ -1030,7 +1030,10 @@ static int wgrad(hipStream_t st, RowRange rr, int stack, int N, int K, ALA A, AL
   slices = slices < 1 ? 1 : (slices > kMaxSlices ? kMaxSlices : slices);
   const int rps = ((rows + slices - 1) / slices + 15) / 16 * 16;
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)slices);
-  hipLaunchKernelGGL((k_wgrad_mfma<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
+  if (bf16)
+    hipLaunchKernelGGL((k_wgrad_bf16<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
+  else
+    hipLaunchKernelGGL((k_wgrad_mfma<ALA, ALB>), grid, dim3(256), 0, st, rr, stack, N, K, rps, A, Bl, partial);
   hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for((int64_t)N * K, 256, 4096)), dim3(256), 0, st,
                      (const float*)partial, slices, N, K, gacc, off, env_c, env_l1);
   AFM_LAUNCH_CHECK();
@@ -1046,6 +1049,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   TraceScope tr(st, "second_order");
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
+  const bool so_bf16 = m->prec == AFM_BF16_MFMA;   // BF16 models: BF16 MFMA GEMMs, FP32 accumulation
   for (int layer = 1; layer <= d.NL; ++layer)   // refuse before launching anything
     if (!pick_tp2(d.lmax, d.NL, layer, d.c, false) || !pick_tp2(d.lmax, d.NL, layer, d.c, true)) {
       set_error("second-order tensor-product kernel not built for this shape");
@@ -1095,14 +1099,14 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                        m->W.tb[0], d.S, d.nb, d.tb[0], (float)d.r_cut, d.p, tbp0);
     AFM_LAUNCH_CHECK();
     for (int k = 1; k < d.ntb; ++k)
-      sgemm<true, true>(st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
+      sgemm_so<true>(so_bf16, st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
                   LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack},
                   EpSt{ws_ptr<float>(ws, L.so_tb_pre[k]), d.tb[k]}, stack);
     float* x0 = ws_ptr<float>(ws, L.so_x[0]);
     hipLaunchKernelGGL(k_tb2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack, d.w,
                        (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), (const float*)geo,
                        (const float*)geo2, x0);
-    sgemm<true, true>(st, rr, E2, d.w, env, m->W.env[0], d.w, LdPlain{x0, d.w}, EpSt{ws_ptr<float>(ws, L.so_omega[0]), env},
+    sgemm_so<true>(so_bf16, st, rr, E2, d.w, env, m->W.env[0], d.w, LdPlain{x0, d.w}, EpSt{ws_ptr<float>(ws, L.so_omega[0]), env},
                 stack);
     AFM_LAUNCH_CHECK();
     for (int layer = 1; layer <= d.NL; ++layer) {
@@ -1127,10 +1131,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       for (int k = 0; k < d.depth; ++k) {
         float* pre = ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k]);
         if (k == 0)
-          sgemm<true, true>(st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
+          sgemm_so<true>(so_bf16, st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
                       EpSt{pre, d.w}, stack);
         else
-          sgemm<true, true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
+          sgemm_so<true>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
                       LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, EpSt{pre, d.w}, stack);
       }
       float* xn = ws_ptr<float>(ws, L.so_x[layer]);
@@ -1138,7 +1142,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                          d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][d.depth - 1]), xp,
                          (const float*)geo, (const float*)geo2, xn);
       if (layer < d.NL)
-        sgemm<true, true>(st, rr, E2, d.w, env, m->W.env[layer], d.w, LdPlain{xn, d.w},
+        sgemm_so<true>(so_bf16, st, rr, E2, d.w, env, m->W.env[layer], d.w, LdPlain{xn, d.w},
                     EpSt{ws_ptr<float>(ws, L.so_omega[layer]), env}, stack);
       AFM_LAUNCH_CHECK();
     }
@@ -1151,7 +1155,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                        ws_ptr<double>(ws, L.so_amu));
     AFM_LAUNCH_CHECK();
     // q[f] = sum_m coef_m x[m][f]  (accumulated in the q slot of gacc's tail)
-    rc = wgrad(st, rr, stack, 1, d.w, LdCoef{coef}, LdPlain{xN, d.w}, partial, ws_ptr<double>(ws, L.so_q), 0);
+    rc = wgrad(so_bf16, st, rr, stack, 1, d.w, LdCoef{coef}, LdPlain{xN, d.w}, partial, ws_ptr<double>(ws, L.so_q), 0);
     if (rc) return rc;
     // ---- reverse ----
     char nm[32];
@@ -1160,9 +1164,9 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       const int ls = lp.n0e * d.c;
       const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
       if (layer < d.NL) {
-        sgemm<false, true>(st, rr, E2, env, d.w, m->W.env[layer], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+        sgemm_so<false>(so_bf16, st, rr, E2, env, d.w, m->W.env[layer], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
         snprintf(nm, sizeof nm, "layer%d.env", layer + 1);
-        rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{ws_ptr<float>(ws, L.so_x[layer]), d.w},
+        rc = wgrad(so_bf16, st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{ws_ptr<float>(ws, L.so_x[layer]), d.w},
                    partial, gacc, block_offset(m, nm), d.c, d.lmax + 1);
         if (rc) return rc;
       }
@@ -1178,19 +1182,19 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         snprintf(nm, sizeof nm, "layer%d.latent.%d", layer, k);
         const int64_t off = block_offset(m, nm);
         if (k > 0) {
-          rc = wgrad(st, rr, stack, d.w, d.w, LdPlain{ga, d.w},
+          rc = wgrad(so_bf16, st, rr, stack, d.w, d.w, LdPlain{ga, d.w},
                      LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false, true>(st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
+          sgemm_so<false>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
           hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr,
                              stack, d.w, (const float*)ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), gh, ga,
                              (const float*)geo, (const float*)geo2, 0, 1.0f, 0.0f);
           AFM_LAUNCH_CHECK();
         } else {
-          rc = wgrad(st, rr, stack, d.w, d.w + ls, LdPlain{ga, d.w},
+          rc = wgrad(so_bf16, st, rr, stack, d.w, d.w + ls, LdPlain{ga, d.w},
                      LdCat{xp, d.w, ws_ptr<float>(ws, L.so_s[layer - 1]), ls}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false, true>(st, rr, E2, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LdPlain{ga, d.w},
+          sgemm_so<false>(so_bf16, st, rr, E2, d.w, d.w + ls, m->W.lat[layer - 1][0], d.w + ls, LdPlain{ga, d.w},
                        EpSplit2{gx, d.w, gs2, ls}, stack);
           AFM_LAUNCH_CHECK();
         }
@@ -1219,8 +1223,8 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       // alpha shares are per atom (chunks do not overlap): reduced after the last chunk
     }
     // two-body reverse
-    sgemm<false, true>(st, rr, E2, env, d.w, m->W.env[0], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
-    rc = wgrad(st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{x0, d.w}, partial, gacc,
+    sgemm_so<false>(so_bf16, st, rr, E2, env, d.w, m->W.env[0], d.w, LdPlain{gom, env}, EpAd{gx, d.w}, stack);
+    rc = wgrad(so_bf16, st, rr, stack, env, d.w, LdPlain{gom, env}, LdPlain{x0, d.w}, partial, gacc,
                block_offset(m, "layer1.env"), d.c, d.lmax + 1);
     if (rc) return rc;
     {
@@ -1236,10 +1240,10 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         snprintf(nm, sizeof nm, "twobody.%d", k);
         const int64_t off = block_offset(m, nm);
         if (k > 0) {
-          rc = wgrad(st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+          rc = wgrad(so_bf16, st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
                      LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack}, partial, gacc, off);
           if (rc) return rc;
-          sgemm<false, true>(st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+          sgemm_so<false>(so_bf16, st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
                        EpSt{gh, d.tb[k - 1]}, stack);
           hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.tb[k - 1], 256, 65536)), dim3(256), 0, st,
                              rr, stack, d.tb[k - 1], (const float*)ws_ptr<float>(ws, L.so_tb_pre[k - 1]), gh, ga,
@@ -1247,7 +1251,7 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
           AFM_LAUNCH_CHECK();
         } else {
           LdZ lz{geo, geo2, eidx, nl.col, s.species, 0, rr, stack, d.S, d.nb, d.p, (float)d.r_cut};
-          rc = wgrad(st, rr, stack, d.tb[0], 2 * d.S + d.nb, LdPlain{ga, d.tb[0]}, lz, partial, gacc, off);
+          rc = wgrad(so_bf16, st, rr, stack, d.tb[0], 2 * d.S + d.nb, LdPlain{ga, d.tb[0]}, lz, partial, gacc, off);
           if (rc) return rc;
         }
       }
