@@ -86,3 +86,22 @@ def test_lmax3_second_order_is_refused():
     calc.energy_forces()
     with pytest.raises(afm.AfmError, match="second-order"):
         calc.forces_backward(torch.ones(s.n_struct, dtype=torch.float64, device="cuda"), None)
+
+
+def test_lmax3_tile_shapes_bitwise_equal():
+    """The l_max = 3 chains of every edge-tile shape give the same bits."""
+    import torch
+    import paper_2502_06073_amd as afm
+    hp, s, w, _ = _case("L2_w256_c64", "lattice_5cube")
+    model = afm.Model(hp, w, precision="bf16")
+    calc = afm.Calculator(model, afm.DeviceSystem.from_synth(s))
+    calc.build_neighbors()
+    res = []
+    for shape in ((64, 8), (128, 16), (128, 8)):
+        model.set_edge_tile(*shape)
+        out = calc.energy_forces()
+        torch.cuda.synchronize()
+        res.append({k: v.cpu().numpy() for k, v in out.items()})
+    for r in res[1:]:
+        for k in ("e_atom", "e_struct", "forces", "virial"):
+            np.testing.assert_array_equal(res[0][k], r[k], err_msg=k)
