@@ -81,10 +81,15 @@ def stage_roofline(costs, stats, n_edges, n_atoms, evals):
 FORCED_TILE = None   # (edges, waves) from --edge-tile, else the tuner decides
 
 
+FUSED_LAST = True    # --no-fused-last turns the fused last-layer kernel off
+
+
 def choose_tile(calc):
     """Edge-tile shape of the BF16 chains: the tuner's choice on this
     workload, or the shape given on the command line (profiler runs fix it,
     since counter collection slows kernels unevenly)."""
+    if not FUSED_LAST:
+        calc.model.set_fused_last(False)
     if FORCED_TILE is None or calc.model.precision not in ("bf16", "bf16_fast"):
         return calc.tune_edge_tile()
     calc.model.set_edge_tile(*FORCED_TILE)
@@ -539,6 +544,8 @@ def main(argv=None):
     ap.add_argument("--no-fast", action="store_true", help="skip timing the fast-adjoint variant")
     ap.add_argument("--max-gib", type=float, default=96.0,
                     help="workspace limit for the 1M-atom MD workload (row chunks beyond it)")
+    ap.add_argument("--no-fused-last", action="store_true",
+                    help="run the last latent layer's forward and adjoint as separate kernels")
     ap.add_argument("--edge-tile", default="", metavar="EDGESxWAVES",
                     help="fix the BF16 chains' edge-tile shape (64x8, 128x16, 128x8) instead of tuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -554,6 +561,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_probe_bytes=4 * n)), flush=True)
         return 0
+    if a.no_fused_last:
+        global FUSED_LAST
+        FUSED_LAST = False
     if a.edge_tile:
         global FORCED_TILE
         FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))

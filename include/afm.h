@@ -306,6 +306,14 @@ int afm_backward_forces_backward(const afm_model* model, const afm_system* sys,
  * models the shape has no effect (afm_get_edge_tile reports 0 x 0). */
 int afm_set_edge_tile(afm_model* model, int32_t edges, int32_t waves);
 int afm_get_edge_tile(const afm_model* model, int32_t* edges /*host*/, int32_t* waves /*host*/);
+/* Fused last layer: afm_energy_forces (and afm_md_step) run the last latent
+ * layer's forward and its adjoint as one kernel, since the adjoint's seed
+ * (sigma_Z escale w_eff) is known per edge before the layer runs; results are
+ * bit for bit those of the separate kernels.  Built for BF16 models with the
+ * 64 x 8 tile and latent widths up to 256; elsewhere, and with on = 0, the
+ * separate kernels run.  Default on.  *active (may be NULL) reports whether
+ * the model's current shape uses it. */
+int afm_set_fused_last(afm_model* model, int32_t on, int32_t* active /*host*/);
 /* Tuner: times afm_energy_forces on the caller's system, list and workspace
  * (1 warm-up + 3 timed evaluations per shape, HIP events on `stream`),
  * selects the fastest shape for the model and returns it in *edges, *waves

@@ -154,6 +154,13 @@ class Model:
     def set_edge_tile(self, edges: int, waves: int):
         check("afm_set_edge_tile", load().afm_set_edge_tile(self.handle, int(edges), int(waves)))
 
+    def set_fused_last(self, on: bool) -> bool:
+        """Fused last-layer forward + adjoint in energy_forces (default on);
+        returns whether the model's current shape uses it."""
+        active = C.c_int32()
+        check("afm_set_fused_last", load().afm_set_fused_last(self.handle, int(bool(on)), C.byref(active)))
+        return bool(active.value)
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             with torch.cuda.device(self.device):

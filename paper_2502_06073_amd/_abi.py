@@ -95,6 +95,7 @@ EXPORTS = {
                                      C.c_void_p],
     "afm_set_edge_tile": [C.c_void_p, C.c_int32, C.c_int32],
     "afm_get_edge_tile": [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    "afm_set_fused_last": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
     "afm_tune_edge_tile": [C.c_void_p, C.POINTER(System), C.POINTER(Nlist), C.POINTER(Workspace), C.c_char_p,
                            C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                            C.POINTER(C.c_int32), C.c_void_p],

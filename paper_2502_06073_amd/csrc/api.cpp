@@ -45,9 +45,10 @@ int api_energy_forces_dev(const afm_model* m, const SysDev& s, const NlDev& n, d
                           hipStream_t st) {
   int rc = launch_chunk_rows(s, n, ws, L, st);
   if (!rc) rc = check_chunks(s, n, ws, L, st);
+  const bool fused = m->fuse_last && mfma_fused_last_available(m);
   for (int c = 0; !rc && c < ws->n_chunks; ++c) {
-    rc = run_forward_chunk(m, s, n, ws, L, c, st);
-    if (!rc) rc = run_backward_chunk(m, s, n, ws, L, c, nullptr, st);
+    rc = run_forward_chunk(m, s, n, ws, L, c, st, fused);
+    if (!rc) rc = run_backward_chunk(m, s, n, ws, L, c, nullptr, st, fused);
   }
   if (!rc) rc = run_atom_energy(m, s, n, ws, L, e_atom, e_struct, st);
   if (!rc && (forces || virial)) rc = run_force_scatter(m, s, n, ws, L, forces, virial, st);

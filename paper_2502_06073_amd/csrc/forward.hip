@@ -30,6 +30,8 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
                     hipStream_t st);
 int mfma_twobody_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
                      const int32_t* species, hipStream_t st);
+int mfma_latent_fb(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
+                   const int32_t* species, const int64_t* seg, int64_t B, const double* grad_e_struct, hipStream_t st);
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
@@ -488,7 +490,7 @@ int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const 
 }
 
 int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
-                      const WsLayout& L, int chunk, hipStream_t st) {
+                      const WsLayout& L, int chunk, hipStream_t st, bool fused_last) {
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
   RowRange rr = row_range(nl, ws, L, chunk);
@@ -535,6 +537,17 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
       int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, m->prec == AFM_BF16_MFMA, ta, s.N, st);
       if (rc) return rc;
     }
+    if (fused_last && layer == d.NL) {
+      // forward and adjoint of the last layer; the adjoint's dE/dY
+      // accumulators start here instead of in the backward
+      int rc = zero_async(ws_ptr<float>(ws, L.gy), E * 64, st);
+      if (!rc && d.lmax == 3) rc = zero_async(ws_ptr<float>(ws, L.gy3), E * GEO3_STRIDE * 4, st);
+      if (rc) return rc;
+      TraceScope tr(st, "latent_fb", layer);
+      rc = mfma_latent_fb(m, ws, L, rr, s.species, s.seg, s.B, nullptr, st);
+      if (rc) return rc;
+      continue;
+    }
     TraceScope tr(st, "latent_fwd", layer);
     if (m->prec == AFM_BF16_MFMA) {
       int rc = mfma_latent_fwd(m, ws, L, rr, layer, st);
@@ -576,7 +589,7 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
 }
 
 int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws,
-                       const WsLayout& L, int chunk, const double* grad_e_struct, hipStream_t st) {
+                       const WsLayout& L, int chunk, const double* grad_e_struct, hipStream_t st, bool fused_last) {
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
   RowRange rr = row_range(nl, ws, L, chunk);
@@ -588,13 +601,16 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
   float* gt1 = ws_ptr<float>(ws, L.gt1);
   float* gy = ws_ptr<float>(ws, L.gy);
   const int cw = (d.lmax + 1) * d.c;
-  int rc = zero_async(gy, E * 64, st);
-  if (!rc && d.lmax == 3) rc = zero_async(ws_ptr<float>(ws, L.gy3), E * GEO3_STRIDE * 4, st);
+  int rc = AFM_OK;
+  if (!fused_last) {   // (the fused last layer zeroed them and added its share)
+    rc = zero_async(gy, E * 64, st);
+    if (!rc && d.lmax == 3) rc = zero_async(ws_ptr<float>(ws, L.gy3), E * GEO3_STRIDE * 4, st);
+  }
   if (rc) return rc;
   for (int layer = d.NL; layer >= 1; --layer) {
     const LayerPlan& lp = P.layer[layer - 1];
     const int ls = lp.n0e * d.c;
-    {
+    if (!(fused_last && layer == d.NL)) {
       TraceScope tr(st, "latent_bwd", layer);
       if (m->prec == AFM_BF16_MFMA) {
         rc = mfma_latent_bwd(m, ws, L, rr, layer, s.species, s.seg, s.B, grad_e_struct, st);

@@ -67,6 +67,7 @@ struct afm_model {
   afm_hparams hp;
   afm_precision prec;          // AFM_FP32_PLAIN or AFM_BF16_MFMA
   bool fast_adjoint = false;   // AFM_BF16_MFMA_FAST_ADJOINT was asked for
+  bool fuse_last = true;       // fused last-layer forward + adjoint where built
   int edge_tile = 64;          // edges per workgroup tile of the BF16 MFMA chains (64 or 128)
   int tile_waves = 8;          // wavefronts per workgroup (64: 8; 128: 16 or 8)
   afm::ModelDims dims;
@@ -185,12 +186,16 @@ int launch_chunk_rows(const SysDev& s, const NlDev& nl, const afm_workspace* ws,
                       const WsLayout& L, hipStream_t st);
 
 // forward/backward orchestration for one chunk (forward.hip)
+// fused_last: the forward runs the last latent layer together with its
+// adjoint (energy + forces call), and the backward then starts at that
+// layer's tensor-product adjoint
 int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl,
                       const afm_workspace* ws, const WsLayout& L, int chunk,
-                      hipStream_t st);
+                      hipStream_t st, bool fused_last = false);
 int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl,
                        const afm_workspace* ws, const WsLayout& L, int chunk,
-                       const double* grad_e_struct, hipStream_t st);
+                       const double* grad_e_struct, hipStream_t st, bool fused_last = false);
+bool mfma_fused_last_available(const afm_model* m);
 int run_atom_energy(const afm_model* m, const SysDev& s, const NlDev& nl,
                     const afm_workspace* ws, const WsLayout& L, double* e_atom,
                     double* e_struct, hipStream_t st);

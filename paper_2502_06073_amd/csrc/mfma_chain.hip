@@ -284,7 +284,9 @@ static const uint4* frag_ptr(const afm_model* m, int64_t off) {
 namespace t64 {
 constexpr int NCB = 4, NCBW = 4, WPE = 4;
 #define AFM_TILE_WIDE 1
+#define AFM_TILE_FUSED 1
 #include "mfma_chain_tile.h"
+#undef AFM_TILE_FUSED
 #undef AFM_TILE_WIDE
 }  // namespace t64
 namespace t128 {
@@ -358,6 +360,37 @@ int mfma_latent_bwd(const afm_model* m, const afm_workspace* ws, const WsLayout&
   for (int k = 0; k < d.depth; ++k) a.pre[k] = ws_ptr<uint2>(ws, L.lat_pre[layer - 1][k]);
   const bool last = layer == d.NL, fast = m->fast_adjoint;
   return checked(m, AFM_TILE_DISPATCH(m, launch_lat_bwd(d, last, fast, a, L, st)));
+}
+
+// The last latent layer's forward and adjoint fused (k_lat_fb): built for
+// the 64-edge tile and latent widths up to 256.
+bool mfma_fused_last_available(const afm_model* m) {
+  if (m->prec != AFM_BF16_MFMA || m->edge_tile != 64 || m->dims.w > 256) return false;
+#define X(w, c, l, dp, a0, a1, a2, n0) \
+  if (shape_is(m->dims, w, c, l, dp, a0, a1, a2, n0)) return true;
+  AFM_SHAPES(X)
+#undef X
+  return false;
+}
+
+int mfma_latent_fb(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr,
+                   const int32_t* species, const int64_t* seg, int64_t B, const double* grad_e_struct, hipStream_t st) {
+  const ModelDims& d = m->dims;
+  const int layer = d.NL;
+  const FragOffsets* fo = reinterpret_cast<const FragOffsets*>(m->W.frag_off);
+  ChainArgs a = base_args(m, ws, L, rr, species);
+  a.seg = seg;
+  a.B = B;
+  a.ges = grad_e_struct;
+  for (int k = 0; k < d.depth; ++k) {
+    a.latf[k] = frag_ptr(m, fo->latf[layer - 1][k]);
+    a.latb[k] = frag_ptr(m, fo->latb[layer - 1][k]);
+  }
+  a.xprev = ws_ptr<float>(ws, L.x[layer - 1]);
+  a.s16 = ws_ptr<uint16_t>(ws, L.s[layer - 1]);
+  a.eps = ws_ptr<float>(ws, L.eps);
+  a.gs = ws_ptr<uint16_t>(ws, L.gs[layer - 1]);
+  return checked(m, t64::launch_lat_fb(d, m->fast_adjoint, a, L, st));
 }
 
 }  // namespace afm

@@ -750,6 +750,177 @@ __global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(wpe_f
   });
 }
 
+#ifdef AFM_TILE_FUSED
+// ---------------------------------------------------------------------------
+// The last latent layer's forward and adjoint in one kernel.  Its adjoint
+// seed dE/dx^{N_L} = sigma_Z(i) escale gE_s w_eff is known per edge before
+// the layer runs, so the adjoint head is applied in the forward's last
+// epilogue on the same registers (to the bf16-rounded pre-activation, as
+// the separate adjoint reads it), and the inner layers' pre-activations
+// stay in LDS instead of going to HBM and back: the results are bitwise
+// those of k_lat_fwd + k_lat_bwd.  Needs 130 KB of LDS at w = 256, so one
+// workgroup per CU.
+template <int W, int KS, int DEPTH, int kSplitBwd>
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2))) k_lat_fb(ChainArgs a) {
+  AFM_TILE_PROLOGUE
+  static_assert(W <= 32 * NPS, "one output-row pair per wavefront");
+  constexpr int RBW = W / 16, KBX = W / 32, KB0 = cdiv(W + KS, 32), NPW = W / 32;
+  const float r2 = 0.70710678118654752f;
+  __shared__ ChainSmem<cmax(W, KS)> S;
+  __shared__ uint2 PRE[DEPTH > 1 ? DEPTH - 1 : 1][RBW * NCB * 64];
+  const bool mine = pslot < NPW;
+  const int pair = pslot;
+  // sigma_Z(i) escale gE_s of the edge in column block cb
+  float ce[NCBW], ep[NCBW], gu[NCBW];
+#pragma unroll
+  for (int cb = 0; cb < NCBW; ++cb) {
+    ep[cb] = 0.0f;
+    gu[cb] = 0.0f;
+    const int64_t t = col_t(cb);
+    ce[cb] = 0.0f;
+    if (t < M) {
+      const int64_t i = a.eidx[t];
+      ce[cb] = (float)(a.sp_scale[min(max(a.species[i], 0), a.S - 1)] * a.escale);
+      if (a.ges) {
+        int64_t lo = 0, hi = a.B;
+        while (hi - lo > 1) {
+          int64_t mid = (lo + hi) >> 1;
+          if (a.seg[mid] <= i) lo = mid; else hi = mid;
+        }
+        ce[cb] *= (float)a.ges[lo];
+      }
+    }
+  }
+  auto pre_idx = [&](int rb, int cb) { return (rb * NCB + cbA(cb)) * 64 + lane; };
+  f32x4 xpf[2][NCBW];
+  auto epi = [&](auto K) {
+    constexpr int k = decltype(K)::value;
+    return [&](int rb, int cb, f32x4& v) {
+      if constexpr (k < DEPTH - 1) {
+        bf16x4 h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = (__bf16)v[q];
+        PRE[k][pre_idx(rb, cb)] = __builtin_bit_cast(uint2, h);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = v[q] * sigm(v[q]);
+      } else {
+        const f32x4 xp = xpf[rb & 1][cb];
+        const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          // energy: x^{N_L} and its edge-energy product
+          const float xl = (xp[q] + u[cb] * v[q] * sigm(v[q])) * r2;
+          ep[cb] += we[q] * xl;
+          // adjoint head on the bf16 pre-activation
+          const float pa = (float)(__bf16)v[q];
+          const float gs_ = (ce[cb] * we[q]) * r2;
+          const float sg = sigm(pa);
+          gu[cb] += gs_ * pa * sg;
+          v[q] = gs_ * u[cb] * sg * (1.0f + pa * (1.0f - sg));
+        }
+      }
+    };
+  };
+  auto load_xpf = [&]() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int cb = 0; cb < NCBW; ++cb) {
+        const int64_t t = col_t(cb);
+        xpf[r][cb] = t < M ? ld4(a.xprev + t * W + 16 * (2 * pair + r) + 4 * g) : zero4();
+      }
+  };
+  // forward: layer 0 over [x | s]
+  f32x4 acc0[2][NCBW];
+  zero_acc(acc0);
+  {
+    Stager<W, true> sx;
+    Stager<KS, false> ss;
+    sx.load(a.xprev, tile, M, tid);
+    ss.load(a.s16, tile, M, tid);
+    sx.store(S.act[0], tid);
+    ss.store(S.act[1], tid);
+  }
+  __syncthreads();
+  if (mine) {
+    mma_pair<KB0, KBX>(a.latf[0], pair, 0, S.act[0], acc0, half, lane);
+    mma_pair<KB0, KB0 - KBX>(a.latf[0], pair, KBX, S.act[1], acc0, half, lane);
+  }
+  __syncthreads();
+  if (mine) {
+    if constexpr (DEPTH == 1) load_xpf();
+    finish_pair(pair, acc0, S.act[0], epi(std::integral_constant<int, 0>{}), half, lane);
+  }
+  __syncthreads();
+  int cur = 0;
+  static_for<1, DEPTH>([&](auto K) __attribute__((always_inline)) {
+    constexpr int k = decltype(K)::value;
+    if (mine) {
+      f32x4 acc[2][NCBW];
+      zero_acc(acc);
+      mma_pair<KBX, KBX>(a.latf[k], pair, 0, S.act[cur], acc, half, lane);
+      if constexpr (k == DEPTH - 1) load_xpf();
+      finish_pair(pair, acc, S.act[cur ^ 1], epi(K), half, lane);
+    }
+    __syncthreads();
+    cur ^= 1;
+  });
+  // edge energies and dE/du of the head (the barriers inside also publish
+  // the head's fragments)
+#pragma unroll
+  for (int cb = 0; cb < NCBW; ++cb) ep[cb] = sum_groups(ep[cb]);
+  wg_edge_sum(S.red, ep, tile, M, tid, [&](int64_t t, float v) { a.eps[e0 + t] = v; });
+#pragma unroll
+  for (int cb = 0; cb < NCBW; ++cb) gu[cb] = sum_groups(gu[cb]);
+  wg_edge_sum(S.red, gu, tile, M, tid, [&](int64_t t, float v) { a.gy[t * GEO_STRIDE + 9] += v; });
+  // adjoint: inner layers ga_{k-1} = (W_k^T ga_k) * silu'(a_{k-1})
+  static_for<1, DEPTH>([&](auto KK) __attribute__((always_inline)) {
+    constexpr int k = DEPTH - decltype(KK)::value;
+    if (mine) {
+      f32x4 acc[2][NCBW];
+      zero_acc(acc);
+      mma_pair<KBX, KBX, kSplitBwd>(a.latb[k], pair, 0, S.act[cur], acc, half, lane);
+      finish_pair(
+          pair, acc, S.act[cur ^ 1],
+          [&](int rb, int cb, f32x4& v) {
+            const bf16x4 h = __builtin_bit_cast(bf16x4, PRE[k - 1][pre_idx(rb, cb)]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] *= dsilu_of((float)h[q]);
+          },
+          half, lane);
+    }
+    __syncthreads();
+    cur ^= 1;
+  });
+  // dE/d[x | s] = W_1^T ga_1: x rows plus the residual share, s rows stored
+  int64_t tile_o = tile;
+  asm volatile("" : "+s"(tile_o));
+  auto out_epi = [&](int rb, int cb, f32x4& v) {
+    const int64_t t = tile_o * TILE + 16 * cbA(cb) + (lane & 15);
+    if (t >= M) return;
+    if (rb < RBW) {
+      const f32x4 we = ld4(a.w_eff + 16 * rb + 4 * g);
+      f32x4 res;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) res[q] = (ce[cb] * we[q]) * r2;
+      st4(a.gx + t * W + 16 * rb + 4 * g, res + v);
+    } else if (16 * (rb - RBW) < KS) {
+      st_bf16x4_plain(a.gs + t * KS + 16 * (rb - RBW) + 4 * g, v);
+    }
+  };
+  constexpr int NPO = cdiv(W + KS, 32);
+  static_for<0, cdiv(NPO, NPS)>([&](auto P) __attribute__((always_inline)) {
+    const int p = decltype(P)::value * NPS + pslot;
+    if (p < NPO) {
+      f32x4 acc[2][NCBW];
+      zero_acc(acc);
+      mma_pair<KBX, KBX, kSplitBwd>(a.latb[0], p, 0, S.act[cur], acc, half, lane);
+      finish_pair(p, acc, nullptr, out_epi, half, lane);
+    }
+  });
+}
+#endif
+
 // ---------------------------------------------------------------------------
 // adjoint of the two-body MLP: dE/dx^0 (+ W_env^1T dE/domega^1) -> dE/drho, dE/du
 
@@ -964,5 +1135,22 @@ static int launch_lat_bwd(const ModelDims& d, bool last, bool fast, const ChainA
 #undef X
   return AFM_E_UNSUPPORTED;
 }
+
+#ifdef AFM_TILE_FUSED
+static int launch_lat_fb(const ModelDims& d, bool fast, const ChainArgs& a, const WsLayout& L, hipStream_t st) {
+#define X(w, c, l, dp, a0, a1, a2, n0)                                                                  \
+  if (shape_is(d, w, c, l, dp, a0, a1, a2, n0)) {                                                       \
+    if (fast)                                                                                           \
+      hipLaunchKernelGGL((k_lat_fb<w, n0 * c, dp, 1>), chain_grid(L), dim3(NTHR), 0, st, a);            \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_lat_fb<w, n0 * c, dp, kSplit>), chain_grid(L), dim3(NTHR), 0, st, a);       \
+    AFM_LAUNCH_CHECK();                                                                                 \
+    return AFM_OK;                                                                                      \
+  }
+  AFM_SHAPES(X)
+#undef X
+  return AFM_E_UNSUPPORTED;
+}
+#endif
 
 #undef AFM_TILE_PROLOGUE

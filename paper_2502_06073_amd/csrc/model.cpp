@@ -487,9 +487,12 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
     // x^{L-1}, s^L (bf16), u in; x^L + omega^{L+1} (bf16) or eps out; pre-activations out
     add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),
         4 * W + 2 * s_out + 4 + (last ? 4 : 4 * W + 2 * ENV) + 2 * d.depth * W, 0);
-    // dE/domega^{L+1} (bf16), dE/dx^L, pre-activations in; dE/dx^{L-1}, dE/ds^L, dE/du out
+    // dE/domega^{L+1} (bf16), dE/dx^L, pre-activations in; dE/dx^{L-1}, dE/ds^L (bf16), dE/du out
     add("latent_bwd", L, 0, 2.0 * (lat + (last ? 0 : W * ENV)),
-        (last ? 0 : 2 * ENV) + 4 * W + 2 * d.depth * W + 4 * W + 4 * s_out + 4, 0);
+        (last ? 0 : 2 * ENV) + 4 * W + 2 * d.depth * W + 4 * W + 2 * s_out + 4, 0);
+    // the last layer's forward and adjoint fused: x^{L-1}, s^L (bf16), u in;
+    // eps, dE/dx^{L-1}, dE/ds^L (bf16), dE/du out
+    if (last) add("latent_fb", L, 0, 2.0 * (lat + W) + 2.0 * lat, 4 * W + 2 * s_out + 4 + 4 + 4 * W + 2 * s_out + 4, 0);
   }
   // rho and u adjoints in, dE/d delta out
   add("geometry_bwd", 0, 1, 40.0 + 4.0 * d.nb, 4.0 * (GEO_Y + 9) + 4 * (16 + 16) + 12, 0);

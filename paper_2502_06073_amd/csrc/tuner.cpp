@@ -50,6 +50,13 @@ int afm_set_edge_tile(afm_model* m, int32_t edges, int32_t waves) {
   return AFM_OK;
 }
 
+int afm_set_fused_last(afm_model* m, int32_t on, int32_t* active) {
+  if (!m) { set_error("null model"); return AFM_E_INVALID; }
+  m->fuse_last = on != 0;
+  if (active) *active = (m->fuse_last && mfma_fused_last_available(m)) ? 1 : 0;
+  return AFM_OK;
+}
+
 int afm_get_edge_tile(const afm_model* m, int32_t* edges, int32_t* waves) {
   if (!m || !edges || !waves) { set_error("null argument"); return AFM_E_INVALID; }
   const bool mfma = m->prec == AFM_BF16_MFMA;

@@ -111,7 +111,9 @@ def test_stage_costs_cover_traced_stages():
     names = {"geometry", "twobody_fwd", "twobody_bwd", "geometry_bwd", "energy", "force_scatter"}
     for L in (1, 2):
         names |= {f"tp_fwd{L}", f"tp_bwd{L}", f"latent_fwd{L}", f"latent_bwd{L}"}
+    names.add("latent_fb2")                  # the fused last layer: forward + adjoint
     assert set(c) == names
+    assert c["latent_fb2"]["flops_per_edge"] == c["latent_fwd2"]["flops_per_edge"] + c["latent_bwd2"]["flops_per_edge"]
     W, C, D = hp["latent"], hp["channels"], hp["latent_depth"]
     env = (hp["l_max"] + 1) * C
     lat1 = (W + 3 * C) * W + (D - 1) * W * W
