@@ -22,7 +22,10 @@ module follows the Allegro formulation with these readings:
                              * Gamma_i(e)[n, l2, m2]   (channelwise);
              s_e = T^pi_e[:, 0] over the 0e paths (path-major, channel-minor);
              x~ = u * MLP_lat([x^(L-1) | s_e]); x^L = (x^(L-1) + x~) / sqrt 2;
-             V^L[n, ir3] = sum_{pi -> ir3} alpha^L[pi, n] T^pi[n]  (L < N_L).
+             V^L[n, ir3] = sum_{pi -> ir3} alpha^L[pi, n] T^pi[n]  (L < N_L);
+             or, with mixing = "dense" (the alternative reading, a c x c
+             channel-mixing matrix per path after the products):
+             V^L[n, ir3] = sum_{pi -> ir3} sum_k A^L_pi[n, k] T^pi[k].
   energy     eps_e = W_E2 W_E1 x^(N_L);
              E_i = sigma_Z(i) * energy_scale * sum_{row i} eps_e + mu_Z(i);
              E_s = sum_{i in s} E_i.
@@ -36,7 +39,9 @@ backwards; order is lexicographic on (l1, p1 [+ first], l2, l3, p3 [+ first]).
 Weight layout (flat float64 vector, row-major out x in matrices, in order):
   twobody.k [h_k+1, h_k] (h_0 = 2S + n_b), fan-in init;
   per layer: layer{L}.env [c (l_max+1), w]; layer{L}.latent.k (first has
-  in = w + n0e c); layer{L}.alpha [n_paths, c] (ones; only L < N_L);
+  in = w + n0e c); layer{L}.alpha [n_paths, c] (ones; only L < N_L) or,
+  dense mixing, layer{L}.mix [n_paths c, c] (row pi c + n, column k:
+  A^L_pi[n, k]; fan-in c init; only L < N_L);
   edge.0 [h, w]; edge.1 [1, h]; species.scale [S] (ones);
   species.shift [S] (N(0, 1)).
 
@@ -44,7 +49,10 @@ Pins: invariances, finite differences, locality, the pair-potential special
 case (all W_env = 0), Table 1's parameter counts, and a value pin of the
 equivariant branch: per-atom energies of open clusters (l_max = 1, two and
 three layers, alpha, sigma_Z, nbar and energy_scale away from 1) evaluated
-independently with dot and cross products (tests/test_oracle_*).
+independently with dot and cross products (tests/test_oracle_*); the
+dense mixing reading by the same hand evaluation with explicit sums over
+channels, by its reduction to the per-path reading when every A is
+diagonal, and by invariance and finite differences with random A.
 The match to the trained Allegro-FM models themselves is parity unpinned (no
 weights or code exist).
 """
@@ -79,6 +87,7 @@ class HParams:
     r_cut: float
     avg_num_neighbors: float = 1.0
     energy_scale: float = 1.0
+    mixing: str = "path"        # "path" (alpha per path and channel) or "dense"
 
     @staticmethod
     def from_dict(d: Dict) -> "HParams":
@@ -164,8 +173,13 @@ def param_layout(hp: HParams) -> List[Dict]:
             mat(f"layer{L}.latent.{k}", w, ind if k == 0 else w)
         if L < hp.n_layers:
             np_ = len(paths[L - 1])
-            blocks.append(dict(name=f"layer{L}.alpha", shape=(np_, c),
-                               size=np_ * c, fan_in=1, init="ones"))
+            if hp.mixing == "dense":
+                mat(f"layer{L}.mix", np_ * c, c)
+            elif hp.mixing == "path":
+                blocks.append(dict(name=f"layer{L}.alpha", shape=(np_, c),
+                                   size=np_ * c, fan_in=1, init="ones"))
+            else:
+                raise ValueError(f"unknown mixing {hp.mixing!r}")
     mat("edge.0", hp.edge_hidden, w)
     mat("edge.1", 1, hp.edge_hidden)
     blocks.append(dict(name="species.scale", shape=(S,), size=S, fan_in=1,
@@ -289,10 +303,16 @@ def rows_energy(hp: HParams, P: Dict[str, torch.Tensor], delta: torch.Tensor,
                                     for k in range(hp.latent_depth)])
         x = (x + xt) / math.sqrt(2.0)
         if L < hp.n_layers:
-            alpha = P[f"layer{L}.alpha"]
+            if hp.mixing == "dense":
+                A = P[f"layer{L}.mix"].view(len(paths[L - 1]), c, c)
+            else:
+                alpha = P[f"layer{L}.alpha"]
             Vn = {}
             for k, (l1, p1, l2, l3, p3) in enumerate(paths[L - 1]):
-                term = alpha[k][None, :, None] * T[k]
+                if hp.mixing == "dense":
+                    term = torch.matmul(A[k], T[k])       # [c, c] @ [E, c, 2 l3 + 1]
+                else:
+                    term = alpha[k][None, :, None] * T[k]
                 key = (l3, p3)
                 Vn[key] = term if key not in Vn else Vn[key] + term
             V = Vn

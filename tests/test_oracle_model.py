@@ -453,3 +453,99 @@ def test_virial_term_of_the_double_backward_alone():
         return float(np.sum(gW * M.energy_forces(hp, wv, s)["virial"]))
     fd = (obj(w + h * v) - obj(w - h * v)) / (2 * h)
     assert abs(fd - out["grad_weights"] @ v) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+# ------------------------------------------------------ dense channel mixing
+
+def _dense_from_alpha(hp_path, w_path, hp_dense):
+    """The dense reading's weight vector whose mixing matrices are diag(alpha)
+    of the path reading's vector (every other block copied)."""
+    src = {b["name"]: b for b in M.param_layout(hp_path)}
+    off, o = {}, 0
+    for b in M.param_layout(hp_path):
+        off[b["name"]] = o
+        o += b["size"]
+    out = []
+    c = hp_dense.channels
+    for b in M.param_layout(hp_dense):
+        if b["name"].endswith(".mix"):
+            a = src[b["name"][:-4] + ".alpha"]
+            al = w_path[off[a["name"]]:off[a["name"]] + a["size"]].reshape(a["shape"])
+            A = np.zeros((al.shape[0], c, c))
+            for k in range(al.shape[0]):
+                A[k] = np.diag(al[k])
+            out.append(A.reshape(-1))
+        else:
+            out.append(w_path[off[b["name"]]:off[b["name"]] + b["size"]])
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("lmax,nl", [(1, 3), (2, 2), (2, 3)])
+def test_dense_mixing_with_diagonal_matrices_is_the_path_reading(lmax, nl):
+    """A_pi = diag(alpha_pi) turns the dense reading into the per-path one:
+    energies, forces and virial agree to rounding."""
+    hp_p = small_hp(l_max=lmax, n_layers=nl)
+    hp_d = small_hp(l_max=lmax, n_layers=nl, mixing="dense")
+    w = weights(hp_p, 9)
+    # alpha away from 1 so the diagonal carries information
+    rng = np.random.default_rng(3)
+    o = 0
+    for b in M.param_layout(hp_p):
+        if b["name"].endswith(".alpha"):
+            w[o:o + b["size"]] = rng.uniform(0.4, 1.6, b["size"]) * rng.choice([-1, 1], b["size"])
+        o += b["size"]
+    wd = _dense_from_alpha(hp_p, w, hp_d)
+    assert wd.shape[0] == M.n_params(hp_d)
+    s = synth.config_a()
+    s = dataclasses.replace(s, n_species=3)
+    rp = M.energy_forces(hp_p, w, s)
+    rd = M.energy_forces(hp_d, wd, s)
+    np.testing.assert_allclose(rd["e_atom"], rp["e_atom"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(rd["forces"], rp["forces"], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(rd["virial"], rp["virial"], rtol=1e-11, atol=1e-10)
+
+
+def test_dense_mixing_parameter_count():
+    """The dense reading replaces each alpha [n_paths, c] by n_paths c x c
+    matrices: Table 1's FM64 / FM256 / FM512 shapes then have
+    49.6K / 720.8K / 2.79M weights, further from the paper's 44.4K / 690K /
+    2.6M than the per-path reading (the reason it is not the default)."""
+    want = {64: (16, 64, 49554), 256: (64, 128, 720818), 512: (128, 128, 2793010)}
+    for w_, (c, h, n) in want.items():
+        d = dict(n_species=89, l_max=2, n_layers=2, latent=w_, channels=c, n_bessel=8, poly_p=6,
+                 twobody=[w_ // 4, w_ // 2, w_], latent_depth=3, edge_hidden=h, r_cut=5.2)
+        npd = M.n_params(M.HParams.from_dict(dict(d, mixing="dense")))
+        npp = M.n_params(M.HParams.from_dict(d))
+        paths, _, _ = M.path_sets(M.HParams.from_dict(d))
+        assert npd - npp == len(paths[0]) * c * (c - 1)
+        assert npd == n, (w_, npd)
+
+
+def test_dense_mixing_invariances_and_force_differences():
+    """Random dense mixing keeps O(3), translation and permutation invariance,
+    and the forces are the energy's central differences."""
+    hp = small_hp(n_layers=3, mixing="dense")
+    w = weights(hp, 13)
+    s = cluster(12, 6)
+    base = _energy(hp, w, s)
+    rng = np.random.default_rng(14)
+    Q = so3.random_rotation(rng)
+    for R in (Q, -Q):
+        s2 = dataclasses.replace(s, pos=s.pos @ R.T + rng.standard_normal(3))
+        r2 = _energy(hp, w, s2)
+        np.testing.assert_allclose(r2["e_atom"], base["e_atom"], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(r2["forces"], base["forces"] @ R.T, atol=1e-11)
+    perm = rng.permutation(s.n_atoms)
+    r3 = _energy(hp, w, dataclasses.replace(s, pos=s.pos[perm], species=s.species[perm]))
+    np.testing.assert_allclose(r3["e_atom"], base["e_atom"][perm], rtol=1e-12)
+    np.testing.assert_allclose(base["forces"].sum(0), 0, atol=1e-12)
+    h = 1e-5
+    for a in rng.choice(s.n_atoms, 4, replace=False):
+        for k in range(3):
+            p = s.pos.copy()
+            p[a, k] += h
+            ep = M.energy_forces(hp, w, dataclasses.replace(s, pos=p), want_forces=False)["e_struct"][0]
+            p[a, k] -= 2 * h
+            em = M.energy_forces(hp, w, dataclasses.replace(s, pos=p), want_forces=False)["e_struct"][0]
+            fd = -(ep - em) / (2 * h)
+            assert abs(fd - base["forces"][a, k]) <= 1e-7 * max(1.0, np.abs(base["forces"]).max())

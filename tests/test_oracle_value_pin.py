@@ -20,7 +20,9 @@ Training, l_max = 1 in full O(3)):
   vector x vector / sqrt(2) (1 x 1 -> 1);
 * path sets after backward pruning and their order, typed out below;
 * s = the 0e paths' outputs, path-major and channel-minor;
-* V^L = sum over the paths into an irrep of alpha[path, n] T;
+* V^L = sum over the paths into an irrep of alpha[path, n] T, or in the
+  dense reading of the mixing sum over the paths into an irrep and over
+  the input channels k of A_path[n, k] T[k];
 * latent MLP on [x | s] with SiLU after every layer, times the envelope,
   residual (x + x~) / sqrt 2;
 * eps = W_E2 W_E1 x; E_i = sigma_Z escale sum_row eps + mu_Z.
@@ -51,11 +53,11 @@ SQ2 = math.sqrt(2.0)
 # --------------------------------------------------------------------------
 # inputs
 
-def hparams(n_layers):
+def hparams(n_layers, mixing="path"):
     return dict(n_species=3, l_max=1, n_layers=n_layers, latent=8, channels=4,
                 n_bessel=5, poly_p=6, twobody=[6, 8], latent_depth=2,
                 edge_hidden=5, r_cut=3.6, avg_num_neighbors=2.7,
-                energy_scale=1.3)
+                energy_scale=1.3, mixing=mixing)
 
 
 # Path lists after backward pruning, typed out by hand as (l1, p1, l2, l3, p3),
@@ -92,7 +94,10 @@ def layout(hp, paths):
         out.append((f"layer{L}.latent.0", (w, w + n0 * c)))
         out.append((f"layer{L}.latent.1", (w, w)))
         if L < NL:
-            out.append((f"layer{L}.alpha", (len(paths[L - 1]), c)))
+            if hp["mixing"] == "dense":
+                out.append((f"layer{L}.mix", (len(paths[L - 1]) * c, c)))
+            else:
+                out.append((f"layer{L}.alpha", (len(paths[L - 1]), c)))
     out += [("edge.0", (hp["edge_hidden"], w)), ("edge.1", (1, hp["edge_hidden"])),
             ("species.scale", (S,)), ("species.shift", (S,))]
     return out
@@ -207,7 +212,18 @@ def hand_energies(hp, paths, P, sysd):
             h = np.concatenate([x[e], np.array(s)])
             h = silu(P[f"layer{L}.latent.1"] @ silu(P[f"layer{L}.latent.0"] @ h))
             newx.append((x[e] + u * h) / SQ2)
-            if L < NL:
+            if L < NL and hp["mixing"] == "dense":
+                A = P[f"layer{L}.mix"]          # row k c + n, column m
+                feats = []
+                for n in range(c):
+                    f = {}
+                    for k, pi in enumerate(paths[L - 1]):
+                        key = (pi[3], pi[4])
+                        for m in range(c):
+                            f[key] = f.get(key, 0.0) + A[k * c + n, m] * T[k][m]
+                    feats.append(f)
+                newV.append(feats)
+            elif L < NL:
                 al = P[f"layer{L}.alpha"]
                 feats = []
                 for n in range(c):
@@ -235,11 +251,12 @@ def test_path_lists_typed_by_hand(n_layers, paths):
     assert ps == paths
 
 
+@pytest.mark.parametrize("mixing", ["path", "dense"])
 @pytest.mark.parametrize("n_layers,paths", [(2, PATHS_2), (3, PATHS_3)])
 @pytest.mark.parametrize("seed", [11, 12])
-def test_energies_equal_hand_evaluation(n_layers, paths, seed):
+def test_energies_equal_hand_evaluation(n_layers, paths, seed, mixing):
     from oracle import model as M
-    hp = hparams(n_layers)
+    hp = hparams(n_layers, mixing)
     w, P = draw(hp, paths, 700 + seed)
     assert w.shape[0] == M.n_params(M.HParams.from_dict(hp))
     s = open_cluster(seed)
@@ -266,3 +283,20 @@ def test_hand_evaluation_sees_the_tensor_branch():
         Q[f"layer{L}.latent.0"] = W0
     e_cut = hand_energies(hp, PATHS_2, Q, s)
     assert np.max(np.abs(e_full - e_cut)) > 1e-4
+
+
+def test_dense_mixing_is_seen():
+    """The dense reading's pin is only a pin if the mixing matrices matter:
+    transposing every A (a plausible index mistake) moves the energies far
+    beyond the 1e-12 tolerance."""
+    hp = hparams(3, "dense")
+    _, P = draw(hp, PATHS_3, 733)
+    s = open_cluster(12)
+    e_ref = hand_energies(hp, PATHS_3, P, s)
+    Q = dict(P)
+    c = hp["channels"]
+    for L in (1, 2):
+        A = P[f"layer{L}.mix"].reshape(-1, c, c)
+        Q[f"layer{L}.mix"] = np.ascontiguousarray(A.transpose(0, 2, 1)).reshape(-1, c)
+    e_t = hand_energies(hp, PATHS_3, Q, s)
+    assert np.max(np.abs(e_ref - e_t)) > 1e-4
