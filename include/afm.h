@@ -102,6 +102,14 @@ typedef struct {
   double r_cut;
   double avg_num_neighbors;
   double energy_scale;
+  /* Mixing of the tensor-product outputs into the next layer's features
+   * (Methodology / Model Training gives no equation for it):
+   *   0 = one weight per (path, channel), alpha (default; the reading whose
+   *       parameter counts are closest to Table 1);
+   *   1 = dense: a channels x channels matrix per path (the alternative
+   *       reading), built for l_max <= 2 and channels <= 64; the double
+   *       backward refuses it. */
+  int32_t mixing;
 } afm_hparams;
 
 /* ---- weight layout ------------------------------------------------------
@@ -110,7 +118,12 @@ typedef struct {
  *   twobody.k           [twobody[k], k ? twobody[k-1] : 2 S + n_bessel]
  *   layerL.env          [channels * (l_max + 1), latent]   (row n*(l_max+1)+l)
  *   layerL.latent.k     [latent, k ? latent : latent + n0e_L * channels]
- *   layerL.alpha        [n_paths_L, channels]      (only for L < n_layers)
+ *   layerL.alpha        [n_paths_L, channels]      (only for L < n_layers,
+ *                                                    mixing = 0)
+ *   layerL.mix          [n_paths_L * channels, channels]  (only for
+ *                       L < n_layers, mixing = 1; row k*channels + n, column
+ *                       m: output channel n of path k takes A_k[n][m] times
+ *                       the path's input channel m)
  *   edge.0              [edge_hidden, latent]
  *   edge.1              [1, edge_hidden]
  *   species.scale       [S]       species.shift [S]

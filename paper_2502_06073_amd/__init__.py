@@ -73,6 +73,11 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return t.data_ptr()
 
 
+# tensor-product output mixing: one weight per (path, channel), or a dense
+# channel-mixing matrix per path
+MIXING = {"path": 0, "dense": 1}
+
+
 def hparams_struct(hp: Dict) -> _abi.Hparams:
     tb = list(hp["twobody"])
     h = _abi.Hparams()
@@ -91,6 +96,10 @@ def hparams_struct(hp: Dict) -> _abi.Hparams:
     h.r_cut = float(hp["r_cut"])
     h.avg_num_neighbors = float(hp.get("avg_num_neighbors", 1.0))
     h.energy_scale = float(hp.get("energy_scale", 1.0))
+    mixing = hp.get("mixing", "path")
+    if mixing not in MIXING:
+        raise ValueError(f"mixing must be one of {sorted(MIXING)}, not {mixing!r}")
+    h.mixing = MIXING[mixing]
     return h
 
 

@@ -22,7 +22,8 @@ class Hparams(C.Structure):
                 ("latent", C.c_int32), ("channels", C.c_int32), ("n_bessel", C.c_int32),
                 ("poly_p", C.c_int32), ("n_twobody", C.c_int32), ("twobody", C.c_int32 * 4),
                 ("latent_depth", C.c_int32), ("edge_hidden", C.c_int32), ("r_cut", C.c_double),
-                ("avg_num_neighbors", C.c_double), ("energy_scale", C.c_double)]
+                ("avg_num_neighbors", C.c_double), ("energy_scale", C.c_double),
+                ("mixing", C.c_int32)]
 
 
 class ParamBlock(C.Structure):

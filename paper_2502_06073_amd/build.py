@@ -24,7 +24,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["model.cpp", "weights.cpp", "api.cpp", "trace.cpp", "neighbors.hip", "forward.hip",
-           "tp_kernels.hip", "mfma_chain.hip", "md.hip", "second_order.hip", "train.hip",
+           "tp_kernels.hip", "dense_mix.hip", "mfma_chain.hip", "md.hip", "second_order.hip", "train.hip",
            "static_scratch.hip", "tuner.cpp"]
 
 FLAGS = ["-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}",

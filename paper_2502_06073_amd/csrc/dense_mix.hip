@@ -1,0 +1,321 @@
+// Dense channel mixing after the tensor products: the alternative reading of
+// the post-product mixing (Methodology / Model Training prints no equation),
+// in which each path's outputs go through a c x c matrix,
+//   V^L[ir3][n] = sum_{pi -> ir3} sum_k A^L_pi[n][k] T^pi[k]      (L < N_L),
+// instead of one weight per (path, channel).  The matrices couple the
+// channels, so an edge's tensor track is no longer a per-channel linear map
+// of V^0 (the structure the per-path kernels are built on): here the
+// per-edge features V^L, the products T^L and their adjoints are stored, the
+// channelwise products and their adjoints run per atom (one group of C lanes
+// per central atom, lane = channel), and the mixing is a GEMM over the edges
+// of a chunk on the FP32 matrix cores, one per output component:
+//   forward   V^L[t][ir3, m3][:] = A_ir3 [T^pi[t][m3][:] over pi -> ir3]
+//   adjoint   dE/dT^pi[t][m3][:] = A_ir3^T dE/dV^L[t][ir3, m3][:]
+// with A_ir3 = [A_pi1 | A_pi2 | ...] the path matrices side by side.
+#include <hip/hip_runtime.h>
+
+#include "cg_ct.h"
+#include "device_util.h"
+#include "gemm_f32.h"
+#include "internal.h"
+
+namespace afm {
+namespace {
+
+template <int LMAX, int NL, int L>
+struct DenseCT {
+  static constexpr LayerPlan lp = PlanCT<LMAX, NL>::plan.layer[L - 1];
+};
+
+template <bool B16>
+__device__ __forceinline__ float ldx(const void* p, int64_t i) {
+  if constexpr (B16) return __builtin_bit_cast(float, (uint32_t)static_cast<const uint16_t*>(p)[i] << 16);
+  else return static_cast<const float*>(p)[i];
+}
+template <bool B16>
+__device__ __forceinline__ void stx(void* p, int64_t i, float v) {
+  if constexpr (B16) static_cast<uint16_t*>(p)[i] = __builtin_bit_cast(uint16_t, (__bf16)v);
+  else static_cast<float*>(p)[i] = v;
+}
+
+// V^{L-1} of edge t, channel n: V^0 = omega^1 (x) Y for L = 1 (component
+// l*l + m), else the stored features
+template <int LMAX, int NL, int L, int C, bool B16>
+__device__ __forceinline__ void load_vin(const DenseArgs& a, int64_t t, int n, const float* Y, float* V) {
+  constexpr int NIN = DenseCT<LMAX, NL, L>::lp.n_in_comps;
+  if constexpr (L == 1) {
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      const float w = ldx<B16>(a.omega1, (t * (LMAX + 1) + l) * C + n);
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) V[l * l + m] = w * Y[l * l + m];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) V[q] = a.vin[(t * NIN + q) * C + n];
+  }
+}
+
+// Forward of layer L: Gamma^L of each atom (stored for the adjoint), then per
+// edge every path's product, the 0e outputs to s^L and, below the last
+// layer, all products to the T buffer for the mixing GEMMs.
+template <int LMAX, int NL, int L, int C, bool B16>
+__global__ void __launch_bounds__(256) k_dtp_fwd(DenseArgs a) {
+  constexpr LayerPlan LP = DenseCT<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NIN = LP.n_in_comps, NT = dense_t_comps(LP), NS0 = LP.n0e;
+  static_assert(L > 1 || NIN == NLM, "layer-1 inputs are omega^1 (x) Y");
+  constexpr int NA = 256 / C;
+  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    float G[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) G[q] = 0.0f;
+    for (int64_t e = eb; e < ee; ++e) {
+      const int64_t t = e - e0;
+      const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = ldx<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) G[l * l + m] += w * Y[l * l + m];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      G[q] *= a.inv_sqrt_nbar;
+      a.gamma[(i * NLM + q) * C + n] = G[q];
+    }
+    for (int64_t e = eb; e < ee; ++e) {
+      const int64_t t = e - e0;
+      float Y[NLM];
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) Y[q] = a.geo[t * GEO_STRIDE + GEO_Y + q];
+      float V[NIN];
+      load_vin<LMAX, NL, L, C, B16>(a, t, n, Y, V);
+      static_for<0, LP.n_paths>([&](auto P) {
+        constexpr int k = decltype(P)::value;
+        constexpr PathT pt = LP.p[k];
+        static_assert(L > 1 || pt.in_off == pt.l1 * pt.l1, "layer-1 input offsets");
+        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+        float T[2 * pt.l3 + 1];
+#pragma unroll
+        for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) T[m3] = 0.0f;
+        static_for<0, nz.n>([&](auto Q) {
+          constexpr int q = decltype(Q)::value;
+          T[nz.m3[q]] += nz.c[q] * V[pt.in_off + nz.m1[q]] * G[pt.l2 * pt.l2 + nz.m2[q]];
+        });
+        if constexpr (pt.s_idx >= 0) stx<B16>(a.s, (t * NS0 + pt.s_idx) * C + n, T[0]);
+        if constexpr (L < NL && pt.out_off >= 0) {
+          constexpr int to = dense_t_off(LP, k);
+#pragma unroll
+          for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) a.tbuf[(t * NT + to + m3) * C + n] = T[m3];
+        }
+      });
+    }
+  }
+}
+
+// Adjoint of layer L: dE/dT^pi = dE/ds (0e paths) + the mixing adjoint
+// (T buffer, L < N_L); per edge dE/dV^{L-1} = sum C Gamma dE/dT (stored),
+// per atom dE/dGamma = sum over the row of C V^{L-1} dE/dT; then per edge
+// dE/domega^L (written) and the channel sums of dE/dY (added), with layer 1
+// adding its inputs' adjoint dE/dV^0 through V^0 = omega^1 (x) Y.
+template <int LMAX, int NL, int L, int C, bool B16>
+__global__ void __launch_bounds__(256) k_dtp_bwd(DenseArgs a) {
+  constexpr LayerPlan LP = DenseCT<LMAX, NL, L>::lp;
+  constexpr int NLM = (LMAX + 1) * (LMAX + 1);
+  constexpr int NIN = LP.n_in_comps, NT = dense_t_comps(LP), NS0 = LP.n0e;
+  static_assert(L > 1 || NIN == NLM, "layer-1 inputs are omega^1 (x) Y");
+  constexpr int NA = 256 / C;
+  const int n = threadIdx.x % C, grp = threadIdx.x / C;
+  const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
+  const int64_t e0 = a.rr.row_ptr[a0];
+  for (int64_t i = a0 + (int64_t)blockIdx.x * NA + grp; i < a1; i += (int64_t)gridDim.x * NA) {
+    const int64_t eb = a.rr.row_ptr[i], ee = a.rr.row_ptr[i + 1];
+    float G[NLM], GG[NLM];
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) {
+      G[q] = a.gamma[(i * NLM + q) * C + n];
+      GG[q] = 0.0f;
+    }
+    for (int64_t e = eb; e < ee; ++e) {
+      const int64_t t = e - e0;
+      float Y[NLM];
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) Y[q] = a.geo[t * GEO_STRIDE + GEO_Y + q];
+      float V[NIN], dV[NIN];
+      load_vin<LMAX, NL, L, C, B16>(a, t, n, Y, V);
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) dV[q] = 0.0f;
+      static_for<0, LP.n_paths>([&](auto P) {
+        constexpr int k = decltype(P)::value;
+        constexpr PathT pt = LP.p[k];
+        constexpr ct::Nz nz = ct::NzCT<pt.l1, pt.l2, pt.l3>::nz;
+        float dT[2 * pt.l3 + 1];
+#pragma unroll
+        for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) dT[m3] = 0.0f;
+        if constexpr (pt.s_idx >= 0) dT[0] = ldx<B16>(a.gs, (t * NS0 + pt.s_idx) * C + n);
+        if constexpr (L < NL && pt.out_off >= 0) {
+          constexpr int to = dense_t_off(LP, k);
+#pragma unroll
+          for (int m3 = 0; m3 < 2 * pt.l3 + 1; ++m3) dT[m3] += a.tbuf[(t * NT + to + m3) * C + n];
+        }
+        static_for<0, nz.n>([&](auto Q) {
+          constexpr int q = decltype(Q)::value;
+          const float cg = nz.c[q] * dT[nz.m3[q]];
+          GG[pt.l2 * pt.l2 + nz.m2[q]] += cg * V[pt.in_off + nz.m1[q]];
+          dV[pt.in_off + nz.m1[q]] += cg * G[pt.l2 * pt.l2 + nz.m2[q]];
+        });
+      });
+      // L >= 2: input of the layer below's mixing adjoint; L = 1: dE/dV^0,
+      // read back by the pass below
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) a.dvbuf[(t * NIN + q) * C + n] = dV[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NLM; ++q) GG[q] *= a.inv_sqrt_nbar;
+    for (int64_t e = eb; e < ee; ++e) {
+      const int64_t t = e - e0;
+      float tot[NLM];
+#pragma unroll
+      for (int q = 0; q < NLM; ++q) {
+        tot[q] = GG[q];
+        if constexpr (L == 1) tot[q] += a.dvbuf[(t * NLM + q) * C + n];
+      }
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        const float w = ldx<B16>(a.omega, (t * (LMAX + 1) + l) * C + n);
+        float go = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          const int q = l * l + m;
+          go += tot[q] * a.geo[t * GEO_STRIDE + GEO_Y + q];
+          const float y = group_sum<C>(tot[q] * w);
+          if (n == 0) a.gy[t * GEO_STRIDE + q] += y;
+        }
+        stx<B16>(a.gomega, (t * (LMAX + 1) + l) * C + n, go);
+      }
+    }
+  }
+}
+
+typedef void (*dense_kernel_t)(DenseArgs);
+
+template <int LMAX, int NL, int C, bool B16>
+dense_kernel_t pick_dense(int L, bool bwd) {
+  if (L == 1) return bwd ? k_dtp_bwd<LMAX, NL, 1, C, B16> : k_dtp_fwd<LMAX, NL, 1, C, B16>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_dtp_bwd<LMAX, NL, 2, C, B16> : k_dtp_fwd<LMAX, NL, 2, C, B16>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_dtp_bwd<LMAX, NL, 3, C, B16> : k_dtp_fwd<LMAX, NL, 3, C, B16>;
+  return nullptr;
+}
+
+template <int LMAX, int C, bool B16>
+dense_kernel_t pick_dense_nl(int NL, int L, bool bwd) {
+  switch (NL) {
+    case 2: return pick_dense<LMAX, 2, C, B16>(L, bwd);
+    case 3: return pick_dense<LMAX, 3, C, B16>(L, bwd);
+  }
+  return nullptr;
+}
+
+template <int LMAX, bool B16>
+dense_kernel_t pick_dense_c(int C, int NL, int L, bool bwd) {
+  switch (C) {
+    case 8: return pick_dense_nl<LMAX, 8, B16>(NL, L, bwd);
+    case 16: return pick_dense_nl<LMAX, 16, B16>(NL, L, bwd);
+    case 32: return pick_dense_nl<LMAX, 32, B16>(NL, L, bwd);
+    case 64: return pick_dense_nl<LMAX, 64, B16>(NL, L, bwd);
+  }
+  return nullptr;
+}
+
+template <bool B16>
+dense_kernel_t pick_dense_l(int lmax, int C, int NL, int L, bool bwd) {
+  switch (lmax) {
+    case 0: return pick_dense_c<0, B16>(C, NL, L, bwd);
+    case 1: return pick_dense_c<1, B16>(C, NL, L, bwd);
+    case 2: return pick_dense_c<2, B16>(C, NL, L, bwd);
+  }
+  return nullptr;
+}
+
+// mixing GEMM operands: the products of the paths into one output irrep at
+// component m3 (columns (j, k): path j's channel k), and one component of the
+// features
+struct LoadT {
+  const float* T;
+  int nt, C, m3;
+  int toff[kMaxPaths];
+  __device__ float operator()(int m, int k) const {
+    const int j = k / C;
+    return T[((int64_t)m * nt + toff[j] + m3) * C + (k - j * C)];
+  }
+};
+struct StoreT {
+  float* T;
+  int nt, C, m3;
+  int toff[kMaxPaths];
+  __device__ void operator()(int m, int k, float v) const {
+    const int j = k / C;
+    T[((int64_t)m * nt + toff[j] + m3) * C + (k - j * C)] = v;
+  }
+};
+struct LoadV {
+  const float* V;
+  int nv, C, off;
+  __device__ float operator()(int m, int k) const { return V[((int64_t)m * nv + off) * C + k]; }
+};
+struct StoreV {
+  float* V;
+  int nv, C, off;
+  __device__ void operator()(int m, int k, float v) const { V[((int64_t)m * nv + off) * C + k] = v; }
+};
+
+}  // namespace
+
+int launch_dense_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const DenseArgs& a,
+                    int64_t n_atoms_max, hipStream_t st) {
+  dense_kernel_t k = bf16 ? pick_dense_l<true>(lmax, C, NL, L, bwd) : pick_dense_l<false>(lmax, C, NL, L, bwd);
+  if (!k) { set_error("dense-mixing tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
+  hipLaunchKernelGGL(k, dim3(grid_for(n_atoms_max, 256 / C, 65536)), dim3(256), 0, st, a);
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
+}
+
+// Mixing of layer L (< N_L) over the edges of a chunk (at most E rows).
+// Forward: T (tbuf) -> V^L (feat).  Adjoint: dE/dV^L (feat) -> dE/dT (tbuf),
+// every component of the paths with an output written.
+int launch_dense_mix(const afm_model* m, int L, bool bwd, RowRange rr, int64_t E, float* feat, float* tbuf,
+                     hipStream_t st) {
+  const ModelDims& d = m->dims;
+  const LayerPlan& lp = m->plan.layer[L - 1];
+  const int nt = dense_t_comps(lp), nv = lp.n_out_comps;
+  for (int r = 0; r < lp.n_out; ++r) {
+    int toff[kMaxPaths] = {}, np = 0;
+    for (int k = 0; k < lp.n_paths; ++k)
+      if (lp.p[k].out_off == lp.out_off[r]) toff[np++] = dense_t_off(lp, k);
+    if (np == 0) continue;
+    const float* A = m->W.mix[L - 1] + m->W.mix_off[L - 1][r];
+    const int K = np * d.c;
+    for (int m3 = 0; m3 < 2 * lp.out[r].l + 1; ++m3) {
+      const int off = lp.out_off[r] + m3;
+      if (!bwd) {
+        LoadT al{tbuf, nt, d.c, m3, {}};
+        for (int j = 0; j < np; ++j) al.toff[j] = toff[j];
+        sgemm<true, true>(st, rr, E, K, d.c, A, K, al, StoreV{feat, nv, d.c, off});
+      } else {
+        StoreT ep{tbuf, nt, d.c, m3, {}};
+        for (int j = 0; j < np; ++j) ep.toff[j] = toff[j];
+        sgemm<false, true>(st, rr, E, d.c, K, A, K, LoadV{feat, nv, d.c, off}, ep);
+      }
+      AFM_LAUNCH_CHECK();
+    }
+  }
+  return AFM_OK;
+}
+
+}  // namespace afm

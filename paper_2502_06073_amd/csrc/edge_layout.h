@@ -56,4 +56,32 @@ struct TPArgs {
 int launch_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const TPArgs& a, int64_t n_atoms_max,
               hipStream_t st);
 
+// Operands of the dense-mixing tensor-product kernels of layer L (per-edge
+// features stored; arrays of C = channels).
+struct DenseArgs {
+  RowRange rr;
+  const float* geo;
+  const void* omega;     // omega^L  [t][lmax+1][C]  (float or bf16 bits, as in TPArgs)
+  const void* omega1;    // omega^1
+  void* s;               // s^L      [t][n0e][C]     (float or bf16 bits)
+  float* gamma;          // Gamma^L  [N][(lmax+1)^2][C]
+  const float* vin;      // V^{L-1}  [t][n_in_comps][C]  (L >= 2)
+  float* tbuf;           // forward: T^L written; adjoint: dE/dT^L read  [t][T comps][C]
+  float* dvbuf;          // adjoint: dE/dV^{L-1} written  [t][n_in_comps][C]
+  const void* gs;        // dE/ds^L  [t][n0e][C]     (float or bf16 bits)
+  void* gomega;          // dE/domega^L [t][lmax+1][C] (float or bf16 bits)
+  float* gy;             // dE/dY [t][16]  (+=)
+  float inv_sqrt_nbar;
+};
+
+int launch_dense_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const DenseArgs& a,
+                    int64_t n_atoms_max, hipStream_t st);
+}  // namespace afm
+struct afm_model;
+namespace afm {
+// the mixing GEMMs of layer L < N_L over a chunk of at most E edges:
+// forward T (tbuf) -> V^L (feat), adjoint dE/dV^L (feat) -> dE/dT (tbuf)
+int launch_dense_mix(const afm_model* m, int L, bool bwd, RowRange rr, int64_t E, float* feat, float* tbuf,
+                     hipStream_t st);
+
 }  // namespace afm

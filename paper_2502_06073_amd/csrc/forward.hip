@@ -479,6 +479,53 @@ static TPArgs tp_args(const afm_model* m, const afm_workspace* ws, const WsLayou
   return a;
 }
 
+static DenseArgs dense_args(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer) {
+  DenseArgs a{};
+  a.rr = rr;
+  a.geo = ws_ptr<float>(ws, L.geo);
+  a.omega = ws_ptr<float>(ws, L.omega[layer - 1]);
+  a.omega1 = ws_ptr<float>(ws, L.omega[0]);
+  a.s = ws_ptr<float>(ws, L.s[layer - 1]);
+  a.gamma = ws_ptr<float>(ws, L.gamma[layer - 1]);
+  a.vin = layer >= 2 ? ws_ptr<float>(ws, L.dense_v[layer - 2]) : nullptr;
+  a.tbuf = ws_ptr<float>(ws, L.dense_t);
+  a.dvbuf = ws_ptr<float>(ws, L.dense_dv);
+  a.gs = ws_ptr<float>(ws, L.gs[layer - 1]);
+  a.gomega = ws_ptr<float>(ws, L.gomega);
+  a.gy = ws_ptr<float>(ws, L.gy);
+  a.inv_sqrt_nbar = (float)(1.0 / sqrt(m->dims.nbar));
+  return a;
+}
+
+// tensor products of one layer: the per-path kernels, or with dense mixing
+// the stored-feature kernels and (below the last layer) the mixing GEMMs
+static int tensor_products(const afm_model* m, const afm_workspace* ws, const WsLayout& L, RowRange rr, int layer,
+                           bool bwd, int64_t n_atoms, hipStream_t st) {
+  const ModelDims& d = m->dims;
+  const bool bf16 = m->prec == AFM_BF16_MFMA;
+  if (!(d.dense && d.NL > 1)) {
+    TraceScope tr(st, bwd ? "tp_bwd" : "tp_fwd", layer);
+    return launch_tp(d.lmax, d.NL, layer, d.c, bwd, bf16, tp_args(m, ws, L, rr, layer), n_atoms, st);
+  }
+  const DenseArgs a = dense_args(m, ws, L, rr, layer);
+  int rc = AFM_OK;
+  if (bwd && layer < d.NL) {   // dE/dT^L from dE/dV^L (left in dvbuf by layer L + 1)
+    TraceScope tr(st, "mix_bwd", layer);
+    rc = launch_dense_mix(m, layer, true, rr, L.cex, a.dvbuf, a.tbuf, st);
+    if (rc) return rc;
+  }
+  {
+    TraceScope tr(st, bwd ? "tp_bwd" : "tp_fwd", layer);
+    rc = launch_dense_tp(d.lmax, d.NL, layer, d.c, bwd, bf16, a, n_atoms, st);
+    if (rc) return rc;
+  }
+  if (!bwd && layer < d.NL) {
+    TraceScope tr(st, "mix_fwd", layer);
+    rc = launch_dense_mix(m, layer, false, rr, L.cex, ws_ptr<float>(ws, L.dense_v[layer - 1]), a.tbuf, st);
+  }
+  return rc;
+}
+
 int launch_geometry(const afm_model* m, const SysDev& s, const NlDev& nl, const afm_workspace* ws, const WsLayout& L,
                     RowRange rr, hipStream_t st) {
   hipLaunchKernelGGL(k_geometry, dim3(grid_for(L.cex, 256, 65536)), dim3(256), 0, st, rr, s.pos, s.cell, s.pbc,
@@ -532,9 +579,7 @@ int run_forward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, cons
   }
   for (int layer = 1; layer <= d.NL; ++layer) {
     {
-      TraceScope tr(st, "tp_fwd", layer);
-      TPArgs ta = tp_args(m, ws, L, rr, layer);
-      int rc = launch_tp(d.lmax, d.NL, layer, d.c, false, m->prec == AFM_BF16_MFMA, ta, s.N, st);
+      int rc = tensor_products(m, ws, L, rr, layer, false, s.N, st);
       if (rc) return rc;
     }
     if (fused_last && layer == d.NL) {
@@ -644,9 +689,7 @@ int run_backward_chunk(const afm_model* m, const SysDev& s, const NlDev& nl, con
         AFM_LAUNCH_CHECK();
       }
     }
-    TraceScope tr(st, "tp_bwd", layer);
-    TPArgs ta = tp_args(m, ws, L, rr, layer);
-    rc = launch_tp(d.lmax, d.NL, layer, d.c, true, m->prec == AFM_BF16_MFMA, ta, s.N, st);
+    rc = tensor_products(m, ws, L, rr, layer, true, s.N, st);
     if (rc) return rc;
   }
   // two-body: dE/dx^0 += dE/domega^1 W_env^1, then the MLP adjoint

@@ -43,6 +43,10 @@ struct DevWeights {
   const float* env[kMaxLayers] = {};           // [(lmax+1)*c][w], l-major rows
   const float* lat[kMaxLayers][kMaxDepth] = {};// [out][in]
   const float* alpha[kMaxLayers] = {};         // [n_paths][c]
+  // dense mixing: per output irrep r of layer L, A_r [c][np_r c] (column
+  // block j: the j-th path into r, in path order) at mix[L-1] + mix_off[L-1][r]
+  const float* mix[kMaxLayers] = {};
+  int64_t mix_off[kMaxLayers][kMaxIrreps] = {};
   const float* w_eff = nullptr;                // [w] = W_E1^T W_E2^T
   const float* e0 = nullptr;                   // [h][w]
   const float* e1 = nullptr;                   // [h]
@@ -57,6 +61,7 @@ struct ModelDims {
   int S, lmax, NL, w, c, nb, p, ntb, depth, h;
   int tb[kMaxTwobody];
   int n_lm;             // (lmax+1)^2 spherical-harmonic components
+  bool dense;           // dense channel-mixing matrices after the products
   double r_cut, nbar, escale;
 };
 
@@ -120,6 +125,10 @@ struct WsLayout {
   int64_t gomega = 0;                        // float [CEX][(lmax+1)c]
   int64_t grho = 0;                          // float [CEX][16]
   int64_t geo3 = 0, gy3 = 0;                 // float [CEX][8] Y^3 and dE/dY^3 (l_max = 3 only)
+  // dense mixing only: V^L [CEX][n_out_comps][c] (L < NL), the products T
+  // (forward) or their adjoints (backward) [CEX][t comps][c], and dE/dV^{L-1}
+  // [CEX][n_in_comps][c]
+  int64_t dense_v[kMaxLayers] = {}, dense_t = 0, dense_dv = 0;
   // second order (stacked rows: primal [0, CEX), tangent [CEX, 2 CEX))
   int64_t so_geo2 = 0;                                   // float [CEX][16]
   int64_t so_tb_pre[kMaxTwobody] = {};                   // float [2CEX][tb_k]

@@ -38,6 +38,10 @@ static int dims_of(const afm_hparams* hp, ModelDims* d) {
   if (hp->l_max == 3 && (hp->n_layers > 2 || (hp->channels != 16 && hp->channels != 64))) {
     set_error("l_max = 3 is built for 1 or 2 layers and 16 or 64 channels"); return AFM_E_UNSUPPORTED;
   }
+  if (hp->mixing != 0 && hp->mixing != 1) { set_error("mixing must be 0 (per path) or 1 (dense)"); return AFM_E_INVALID; }
+  if (hp->mixing == 1 && (hp->l_max > 2 || hp->channels > 64)) {
+    set_error("dense mixing is built for l_max <= 2 and channels <= 64"); return AFM_E_UNSUPPORTED;
+  }
   if (hp->n_bessel < 1 || hp->n_bessel > 16) { set_error("n_bessel must be 1..16"); return AFM_E_INVALID; }
   if (hp->poly_p < 2) { set_error("poly_p must be >= 2"); return AFM_E_INVALID; }
   if (hp->edge_hidden < 1) { set_error("edge_hidden must be >= 1"); return AFM_E_INVALID; }
@@ -50,6 +54,7 @@ static int dims_of(const afm_hparams* hp, ModelDims* d) {
   for (int k = 0; k < kMaxTwobody; ++k) d->tb[k] = k < hp->n_twobody ? hp->twobody[k] : 0;
   d->n_lm = (hp->l_max + 1) * (hp->l_max + 1);
   d->r_cut = hp->r_cut; d->nbar = hp->avg_num_neighbors; d->escale = hp->energy_scale;
+  d->dense = hp->mixing == 1;
   return AFM_OK;
 }
 
@@ -86,7 +91,10 @@ static int build_layout(const afm_hparams* hp, std::vector<afm_param_block>& out
       snprintf(nm, sizeof nm, "layer%d.latent.%d", L, k);
       push_block(out, nm, d.w, k ? d.w : lin, k ? d.w : lin, 0, off);
     }
-    if (L < d.NL) {
+    if (L < d.NL && d.dense) {
+      snprintf(nm, sizeof nm, "layer%d.mix", L);
+      push_block(out, nm, (int64_t)lp.n_paths * d.c, d.c, d.c, 0, off);
+    } else if (L < d.NL) {
       snprintf(nm, sizeof nm, "layer%d.alpha", L);
       push_block(out, nm, lp.n_paths, d.c, 1, 2, off);
     }
@@ -279,6 +287,16 @@ WsLayout workspace_layout(const afm_model* m, const afm_workspace* ws) {
     L.geo3 = take(E * GEO3_STRIDE * 4);
     L.gy3 = take(E * GEO3_STRIDE * 4);
   }
+  if (d.dense && d.NL > 1) {
+    int nt = 1, nin = 1;
+    for (int l = 0; l < d.NL; ++l) {
+      nt = nt > dense_t_comps(P.layer[l]) ? nt : dense_t_comps(P.layer[l]);
+      nin = nin > P.layer[l].n_in_comps ? nin : P.layer[l].n_in_comps;
+    }
+    for (int l = 0; l + 1 < d.NL; ++l) L.dense_v[l] = take(E * (int64_t)P.layer[l].n_out_comps * d.c * 4);
+    L.dense_t = take(E * (int64_t)nt * d.c * 4);
+    L.dense_dv = take(E * (int64_t)nin * d.c * 4);
+  }
   if (ws->with_second_order) {
     const int64_t E2 = 2 * E;
     const int envw = (d.lmax + 1) * d.c;
@@ -398,6 +416,15 @@ int afm_model_create(const afm_hparams* hp, const double* weights, int64_t n_wei
   m->fast_adjoint = precision == AFM_BF16_MFMA_FAST_ADJOINT;
   m->prec = m->fast_adjoint ? AFM_BF16_MFMA : precision;
   m->plan = make_plan(m->dims.lmax, m->dims.NL);
+  // the dense kernels read V^{L-1} with layer L's input offsets from the
+  // buffer written with layer L-1's output offsets
+  for (int L = 2; L <= m->dims.NL && m->dims.dense; ++L) {
+    const LayerPlan &a = m->plan.layer[L - 2], &b = m->plan.layer[L - 1];
+    bool same = a.n_out == b.n_in && a.n_out_comps == b.n_in_comps;
+    for (int r = 0; same && r < a.n_out; ++r)
+      same = a.out[r].l == b.in[r].l && a.out[r].p == b.in[r].p && a.out_off[r] == b.in_off[r];
+    if (!same) { set_error("internal: layer irreps do not chain"); delete m; return AFM_E_INVALID; }
+  }
   hipError_t e = hipGetDevice(&m->device);
   if (e != hipSuccess) { set_error(hipGetErrorString(e)); delete m; return AFM_E_HIP; }
   // library set-up on this device: the address of the no-allocation entry

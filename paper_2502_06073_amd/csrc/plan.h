@@ -162,6 +162,15 @@ constexpr Plan make_plan(int lmax, int n_layers) {
   return P;
 }
 
+// Dense mixing: per-edge products T of every path of a layer, path after
+// path (2 l3 + 1 components each); offset of path k and the total.
+constexpr int dense_t_off(const LayerPlan& lp, int k) {
+  int o = 0;
+  for (int q = 0; q < k; ++q) o += 2 * lp.p[q].l3 + 1;
+  return o;
+}
+constexpr int dense_t_comps(const LayerPlan& lp) { return dense_t_off(lp, lp.n_paths); }
+
 template <int LMAX, int NL>
 struct PlanCT {
   static constexpr Plan plan = make_plan(LMAX, NL);

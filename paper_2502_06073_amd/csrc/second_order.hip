@@ -1050,7 +1050,11 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   const ModelDims& d = m->dims;
   const Plan& P = m->plan;
   const bool so_bf16 = m->prec == AFM_BF16_MFMA;   // BF16 models: BF16 MFMA GEMMs, FP32 accumulation
-  for (int layer = 1; layer <= d.NL; ++layer)   // refuse before launching anything
+  if (d.dense && d.NL > 1) {   // refuse before launching anything
+    set_error("second-order pass not built for dense mixing");
+    return AFM_E_UNSUPPORTED;
+  }
+  for (int layer = 1; layer <= d.NL; ++layer)
     if (!pick_tp2(d.lmax, d.NL, layer, d.c, false) || !pick_tp2(d.lmax, d.NL, layer, d.c, true)) {
       set_error("second-order tensor-product kernel not built for this shape");
       return AFM_E_UNSUPPORTED;

@@ -63,7 +63,26 @@ int pack_weights(afm_model* m, const double* w) {
       b = find_block(m, nm);
       put_f32((const void**)&m->W.lat[L - 1][k], w + b->offset, b->rows * b->cols);
     }
-    if (L < d.NL) {
+    if (L < d.NL && d.dense) {
+      // regroup the per-path matrices by output irrep: A_r = [A_k1 | A_k2 | ...]
+      snprintf(nm, sizeof nm, "layer%d.mix", L);
+      b = find_block(m, nm);
+      const LayerPlan& lp = m->plan.layer[L - 1];
+      std::vector<double> rep;
+      for (int r = 0; r < lp.n_out; ++r) {
+        m->W.mix_off[L - 1][r] = (int64_t)rep.size();
+        std::vector<int> ks;
+        for (int k = 0; k < lp.n_paths; ++k)
+          if (lp.p[k].out_off == lp.out_off[r]) ks.push_back(k);
+        const size_t np = ks.size(), o = rep.size();
+        rep.resize(o + np * d.c * d.c);
+        for (int n = 0; n < d.c; ++n)
+          for (size_t j = 0; j < np; ++j)
+            memcpy(&rep[o + ((size_t)n * np + j) * d.c], w + b->offset + ((size_t)ks[j] * d.c + n) * d.c,
+                   sizeof(double) * d.c);
+      }
+      put_f32((const void**)&m->W.mix[L - 1], rep.data(), (int64_t)rep.size());
+    } else if (L < d.NL) {
       snprintf(nm, sizeof nm, "layer%d.alpha", L);
       b = find_block(m, nm);
       put_f32((const void**)&m->W.alpha[L - 1], w + b->offset, b->rows * b->cols);

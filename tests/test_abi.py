@@ -48,6 +48,35 @@ def test_param_layout_matches_oracle(name):
     assert sum(b["size"] for b in ours) == M.n_params(M.HParams.from_dict(hp))
 
 
+@pytest.mark.parametrize("lmax,nl,c", [(2, 2, 16), (2, 3, 8), (1, 3, 64), (0, 2, 32)])
+def test_dense_mixing_layout_matches_oracle(lmax, nl, c):
+    _lib()
+    hp = dict(synth.load_hparams("A"), l_max=lmax, n_layers=nl, channels=c, mixing="dense")
+    ours = afm.param_layout(hp)
+    ref = M.param_layout(M.HParams.from_dict(hp))
+    assert [b["name"] for b in ours] == [b["name"] for b in ref]
+    for a, b in zip(ours, ref):
+        assert tuple(a["shape"]) == tuple(b["shape"]), a["name"]
+        assert a["fan_in"] == b["fan_in"] and a["init"] == b["init"], a["name"]
+    assert any(b["name"].endswith(".mix") for b in ours)
+    assert not any(b["name"].endswith(".alpha") for b in ours)
+
+
+def test_dense_mixing_refusals():
+    lib = _lib()
+    hp = synth.load_hparams("A")
+    nb, npar = C.c_int64(), C.c_int64()
+    for kw, code in ((dict(mixing="dense", l_max=3, channels=16, n_layers=2), -4),
+                     (dict(mixing="dense", channels=128), -4)):
+        bad = afm.hparams_struct(dict(hp, **kw))
+        assert lib.afm_param_layout_size(C.byref(bad), C.byref(nb), C.byref(npar)) == code, kw
+    h = afm.hparams_struct(hp)
+    h.mixing = 2
+    assert lib.afm_param_layout_size(C.byref(h), C.byref(nb), C.byref(npar)) == -1
+    with pytest.raises(ValueError):
+        afm.hparams_struct(dict(hp, mixing="full"))
+
+
 def test_table1_counts_through_library():
     _lib()
     want = {64: 46914, 256: 676466, 512: 2614194}

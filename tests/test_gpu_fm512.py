@@ -80,9 +80,9 @@ def test_fm512_second_order_is_refused():
     import paper_2502_06073_amd as afm
     hp, s, w, _ = _case()
     model = afm.Model(hp, w, precision="fp32")
-    calc = afm.Calculator(model, afm.DeviceSystem.from_synth(s))
+    calc = afm.Calculator(model, afm.DeviceSystem.from_synth(s), second_order=True)
     calc.build_neighbors()
     calc.energy_forces()
     gE = torch.ones(s.n_struct, dtype=torch.float64, device="cuda")
-    with pytest.raises(afm.AfmError, match="second-order"):
+    with pytest.raises(afm.AfmError, match="second-order tensor-product kernel not built"):
         calc.forces_backward(gE, None)

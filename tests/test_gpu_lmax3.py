@@ -81,10 +81,10 @@ def test_lmax3_second_order_is_refused():
     import torch
     import paper_2502_06073_amd as afm
     hp, s, w, _ = _case("L2_w64_c16", "lattice_5cube")
-    calc = afm.Calculator(afm.Model(hp, w, precision="fp32"), afm.DeviceSystem.from_synth(s))
+    calc = afm.Calculator(afm.Model(hp, w, precision="fp32"), afm.DeviceSystem.from_synth(s), second_order=True)
     calc.build_neighbors()
     calc.energy_forces()
-    with pytest.raises(afm.AfmError, match="second-order"):
+    with pytest.raises(afm.AfmError, match="second-order tensor-product kernel not built"):
         calc.forces_backward(torch.ones(s.n_struct, dtype=torch.float64, device="cuda"), None)
 
 
