@@ -51,9 +51,9 @@ PEAK_HBM = 8.0e12       # HBM3E, B/s
 
 def stage_roofline(costs, stats, n_edges, n_atoms, evals):
     """Per traced stage: algorithmic work / average launch time against the
-    roofline that bounds it (MFMA stages: dense BF16 peak; vector stages:
-    whichever of FP32 ALU and HBM needs more time for the algorithmic
-    flops and bytes).  `evals` full evaluations were traced; with row
+    roofline that bounds it (MFMA stages: dense BF16 peak; vector stages
+    and the FP32-MFMA mixing GEMMs: whichever of the FP32 peak and HBM
+    needs more time for the algorithmic flops and bytes).  `evals` full evaluations were traced; with row
     chunks a stage launches once per chunk, so the work per launch is the
     evaluation's work divided by launches per evaluation."""
     out = {}
@@ -68,7 +68,9 @@ def stage_roofline(costs, stats, n_edges, n_atoms, evals):
         if c["kind"] == "mfma":
             bound, peak, work, unit = "mfma", PEAK_BF16, flops, "TFLOP/s"
         elif flops / PEAK_FP32 >= nbytes / PEAK_HBM:
-            bound, peak, work, unit = "alu", PEAK_FP32, flops, "TFLOP/s"
+            # FP32 matrix cores (dense-mixing GEMMs) peak at the FP32 vector rate
+            bound = "mfma" if c["kind"] == "mfma_f32" else "alu"
+            peak, work, unit = PEAK_FP32, flops, "TFLOP/s"
         else:
             bound, peak, work, unit = "hbm", PEAK_HBM, nbytes, "GB/s"
         ach = work / avg_s
@@ -96,11 +98,14 @@ def choose_tile(calc):
     return {"tile": FORCED_TILE, "from_cache": False, "ms": "fixed by --edge-tile"}
 
 
+MIXING = "path"      # --mixing dense: the dense post-product channel-mixing model
+
+
 def setup(config, precision):
     import torch
     import synth
     import paper_2502_06073_amd as afm
-    hp = synth.load_hparams(config)
+    hp = dict(synth.load_hparams(config), mixing=MIXING)
     s = synth.SYSTEMS[config]()
     w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS[config])
     model = afm.Model(hp, w, precision=precision)
@@ -548,6 +553,8 @@ def main(argv=None):
                     help="run the last latent layer's forward and adjoint as separate kernels")
     ap.add_argument("--edge-tile", default="", metavar="EDGESxWAVES",
                     help="fix the BF16 chains' edge-tile shape (64x8, 128x16, 128x8) instead of tuning")
+    ap.add_argument("--mixing", default="path", choices=["path", "dense"],
+                    help="config B: per-path mixing weights (default) or dense channel-mixing matrices")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -567,6 +574,12 @@ def main(argv=None):
     if a.edge_tile:
         global FORCED_TILE
         FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))
+    if a.mixing != "path":
+        if a.config != "B":
+            print("--mixing dense is measured on config B only", file=sys.stderr)
+            return 2
+        global MIXING
+        MIXING = a.mixing
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
@@ -595,7 +608,8 @@ def main(argv=None):
     dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom_name]
     roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"], frac=r["frac"],
-                traffic=load_traffic(dom_name, "configB"), kernel=dom_name, avg_ms=r["avg_ms"],
+                traffic=load_traffic(dom_name, "configB") if MIXING == "path" else None,
+                kernel=dom_name, avg_ms=r["avg_ms"],
                 per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]))
     mlp_flops = sum(roofs[k]["flops_per_launch"] for k in roofs if costs[k]["kind"] == "mfma")
     stage_ms = {k: round(v["total_ms"] / v["launches"], 4) for k, v in stats.items()}
@@ -605,7 +619,9 @@ def main(argv=None):
                data="synthetic (seeded jittered lattice, N(0,1/fan_in) weights)",
                config=dict(workload=f"{s.n_atoms}-atom periodic jittered SC lattice (24^3, a=2.2 A), 4 species, "
                                     f"r_c 5.5 A, l_max 2, 2 layers, latent 256, 3-layer MLPs, energy+forces+virial "
-                                    f"incl. edge-list build" if a.config == "B" else f"config {a.config}",
+                                    f"incl. edge-list build"
+                                    + (", dense post-product channel mixing" if MIXING == "dense" else "")
+                                    if a.config == "B" else f"config {a.config}",
                            n_atoms=s.n_atoms, n_edges=n_edges, edge_tile="%dx%d" % calc.tune["tile"],
                            parallelism="single GPU"),
                edge_tile_tuner_ms=calc.tune["ms"],

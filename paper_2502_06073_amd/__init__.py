@@ -54,7 +54,7 @@ def stage_costs(hp: Dict) -> Dict[str, Dict[str, float]]:
     check("afm_stage_costs", lib.afm_stage_costs(C.byref(h), None, 0, C.byref(n)))
     arr = (_abi.StageCost * max(1, n.value))()
     check("afm_stage_costs", lib.afm_stage_costs(C.byref(h), arr, n.value, C.byref(n)))
-    return {arr[k].name.decode(): dict(kind=("mfma" if arr[k].kind == 0 else "vector"),
+    return {arr[k].name.decode(): dict(kind={0: "mfma", 1: "vector", 2: "mfma_f32"}[arr[k].kind],
                                        flops_per_edge=arr[k].flops_per_edge,
                                        bytes_per_edge=arr[k].bytes_per_edge,
                                        bytes_per_atom=arr[k].bytes_per_atom)

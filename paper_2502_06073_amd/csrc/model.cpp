@@ -501,15 +501,36 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
       real_cg(t.l1, t.l2, t.l3, buf.data());
       for (int q = 0; q < (2 * t.l1 + 1) * (2 * t.l2 + 1) * (2 * t.l3 + 1); ++q) nz0 += std::fabs(buf[q]) > 1e-12;
     }
+    if (d.dense && d.NL > 1) {
+      // stored-feature kernels: V^{L-1} (or omega^1 (x) Y) in, T^L out below
+      // the last layer; the mixing GEMMs over the paths with an output
+      double tmix = 0;
+      for (int k = 0; k < lp.n_paths; ++k)
+        if (lp.p[k].out_off >= 0) tmix += 2 * lp.p[k].l3 + 1;
+      const double vin = L == 1 ? 2 * ENV : 4.0 * lp.n_in_comps * C;
+      const double tout = last ? 0 : 4 * tmix * C;
+      add("tp_fwd", L, 1, 2 * NLM * C + 3 * nz * C + NLM * C, 2 * ENV + vin + 4 * NLM + 2 * s_out + tout,
+          4 * NLM * C);
+      add("tp_bwd", L, 1, 2 * NLM * C * 2 + 6 * nz * C + 2 * NLM * C,
+          2 * ENV + vin + 4 * NLM + 2 * s_out + tout + 4.0 * lp.n_in_comps * C + (L == 1 ? 4 * NLM * C : 0) +
+              2 * ENV + 4 * NLM,
+          4 * NLM * C);
+      if (!last) {
+        add("mix_fwd", L, 2, 2.0 * C * C * tmix, 4 * tmix * C + 4.0 * lp.n_out_comps * C, 0);
+        add("mix_bwd", L, 2, 2.0 * C * C * tmix, 4 * tmix * C + 4.0 * lp.n_out_comps * C, 0);
+      }
+    }
     const double tpf = 2 * NLM * C + 3 * (last ? nz0 : nz) * C + (last ? 0 : 2 * outc * C) + NLM * C;
     // omega^L, omega^1 (bf16), Y in; s^L (bf16) out
-    add("tp_fwd", L, 1, tpf, 2 * ENV + 4 * NLM + 2 * prev + 2 * s_out, 4 * (NLM * C + gprev));
+    if (!(d.dense && d.NL > 1))
+      add("tp_fwd", L, 1, tpf, 2 * ENV + 4 * NLM + 2 * prev + 2 * s_out, 4 * (NLM * C + gprev));
     // adjoint: twice the products (dV and dGamma), the mixing, the environment-sum adjoint
     const double tpb = 2 * NLM * C * 2 + 6 * nz * C + (last ? 0 : 2 * outc * C) + 2 * NLM * C;
     // omega^L, omega^1, Y, dE/ds of this and the later layers in; dE/domega^L
     // (bf16) and dE/dY out
-    add("tp_bwd", L, 1, tpb, 2 * ENV + 4 * NLM + 2 * prev + 4 * (s_out + gs_later) + 2 * ENV + 4 * NLM,
-        4 * (NLM * C + gprev + gnext));
+    if (!(d.dense && d.NL > 1))
+      add("tp_bwd", L, 1, tpb, 2 * ENV + 4 * NLM + 2 * prev + 4 * (s_out + gs_later) + 2 * ENV + 4 * NLM,
+          4 * (NLM * C + gprev + gnext));
     const double lat = (W + lp.n0e * C) * W + (d.depth - 1) * W * W;
     // x^{L-1}, s^L (bf16), u in; x^L + omega^{L+1} (bf16) or eps out; pre-activations out
     add("latent_fwd", L, 0, 2.0 * (lat + (last ? W : W * ENV)),

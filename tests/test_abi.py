@@ -153,3 +153,19 @@ def test_stage_costs_cover_traced_stages():
     assert c["twobody_fwd"]["flops_per_edge"] == 2 * (hp["n_bessel"] * tb[0] + tb[0] * tb[1] + tb[1] * tb[2] + W * env)
     assert all(v["kind"] == ("mfma" if k.startswith(("latent", "twobody")) else "vector") for k, v in c.items())
     assert all(v["bytes_per_edge"] > 0 for v in c.values())
+
+
+def test_stage_costs_dense_mixing():
+    """With dense mixing the cost model names the mixing GEMMs of every layer
+    below the last (FP32 matrix-core stages) and their flops are 2 c^2 per
+    mixed product component."""
+    import paper_2502_06073_amd as afm
+    hp = dict(synth.load_hparams("B"), mixing="dense")
+    c = afm.stage_costs(hp)
+    assert {"mix_fwd1", "mix_bwd1"} <= set(c) and "mix_fwd2" not in c
+    assert c["mix_fwd1"]["kind"] == "mfma_f32" and c["tp_fwd1"]["kind"] == "vector"
+    paths, _, outs = M.path_sets(M.HParams.from_dict(hp))
+    used = set(outs[0])
+    comps = sum(2 * p[3] + 1 for p in paths[0] if (p[3], p[4]) in used)
+    C_ = hp["channels"]
+    assert c["mix_fwd1"]["flops_per_edge"] == 2 * C_ * C_ * comps == c["mix_bwd1"]["flops_per_edge"]
