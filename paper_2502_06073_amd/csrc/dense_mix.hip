@@ -8,7 +8,7 @@
 // per-edge features V^L, the products T^L and their adjoints are stored, the
 // channelwise products and their adjoints run per atom (one group of C lanes
 // per central atom, lane = channel), and the mixing is a GEMM over the edges
-// of a chunk on the FP32 matrix cores, one per output component:
+// of a chunk on the FP32 matrix cores (k_mix), one per output component:
 //   forward   V^L[t][ir3, m3][:] = A_ir3 [T^pi[t][m3][:] over pi -> ir3]
 //   adjoint   dE/dT^pi[t][m3][:] = A_ir3^T dE/dV^L[t][ir3, m3][:]
 // with A_ir3 = [A_pi1 | A_pi2 | ...] the path matrices side by side.
@@ -243,37 +243,190 @@ dense_kernel_t pick_dense_l(int lmax, int C, int NL, int L, bool bwd) {
   return nullptr;
 }
 
-// mixing GEMM operands: the products of the paths into one output irrep at
-// component m3 (columns (j, k): path j's channel k), and one component of the
-// features
-struct LoadT {
-  const float* T;
-  int nt, C, m3;
+// One mixing GEMM: output irrep r at component m3 over the chunk's edges.
+// Forward  V[t][off][n] = sum_k T(t, k) W[n][k],  k = (path j, channel c),
+//          T(t, k) = T[t][toff[j] + m3][c];
+// adjoint  dT(t, k) = sum_n dV[t][off][n] W[n][k]   (W = A_r, [C][np C]).
+struct MixOps {
+  const float* x;    // forward: T buffer; adjoint: dE/dV
+  float* y;          // forward: V^L; adjoint: dE/dT
+  const float* W;    // A_r, row-major [C][np C]
+  int C, np, nt, nv, off, m3;
   int toff[kMaxPaths];
-  __device__ float operator()(int m, int k) const {
-    const int j = k / C;
-    return T[((int64_t)m * nt + toff[j] + m3) * C + (k - j * C)];
+};
+
+// Forward GEMM: 64 edges x the C <= 64 output channels per workgroup (4
+// wavefronts of 32 x 32 on v_mfma_f32_16x16x4f32: FP32 products and sums),
+// the np C reduction staged 32 at a time through LDS with 16-byte loads; a
+// reduction run of 4 never crosses a path (C is a multiple of 4), so every
+// load is one aligned float4.
+__global__ void __launch_bounds__(256) k_mix(RowRange rr, MixOps o) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= M) return;
+  const int K = o.np * o.C, N = o.C;
+  constexpr int KS = 32;
+  __shared__ __attribute__((aligned(16))) float As[KS][68];   // [k][row]
+  __shared__ __attribute__((aligned(16))) float Bs[KS][68];   // [k][column]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float4 ra[2], rb[2];
+  // stage k0: T rows r = idx / 8 and W rows (output channels) r, reduction
+  // k0 + 4 (idx % 8)
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx >> 3, k = k0 + 4 * (idx & 7);
+      const int m = m0 + r;
+      ra[q] = z4;
+      if (m < M && k < K) {
+        const int j = k / o.C;
+        ra[q] = *reinterpret_cast<const float4*>(o.x + ((int64_t)m * o.nt + o.toff[j] + o.m3) * o.C + (k - j * o.C));
+      }
+      rb[q] = (r < N && k < K) ? *reinterpret_cast<const float4*>(o.W + (int64_t)r * K + k) : z4;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx >> 3, kk = 4 * (idx & 7);
+      As[kk + 0][r] = ra[q].x;
+      As[kk + 1][r] = ra[q].y;
+      As[kk + 2][r] = ra[q].z;
+      As[kk + 3][r] = ra[q].w;
+      Bs[kk + 0][r] = rb[q].x;
+      Bs[kk + 1][r] = rb[q].y;
+      Bs[kk + 2][r] = rb[q].z;
+      Bs[kk + 3][r] = rb[q].w;
+    }
+    __syncthreads();
+    if (k0 + KS < K) fetch(k0 + KS);
+#pragma unroll
+    for (int s4 = 0; s4 < KS / 4; ++s4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[4 * s4 + lk][32 * wr + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[4 * s4 + lk][32 * wc + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
   }
-};
-struct StoreT {
-  float* T;
-  int nt, C, m3;
-  int toff[kMaxPaths];
-  __device__ void operator()(int m, int k, float v) const {
-    const int j = k / C;
-    T[((int64_t)m * nt + toff[j] + m3) * C + (k - j * C)] = v;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + 32 * wr + 16 * i + 4 * lk + q;
+      if (m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = 32 * wc + 16 * j + lr;
+        if (n < N) o.y[((int64_t)m * o.nv + o.off) * o.C + n] = acc[i][j][q];
+      }
+    }
+}
+
+// Adjoint GEMM: the reduction runs over the C <= 64 output channels only,
+// so a workgroup stages its 64 rows of dE/dV once ([k][row] in LDS) and
+// sweeps up to kMixBwdTiles tiles of 64 of the np C output columns (all of
+// them for every built model), the next W tile fetched into registers while
+// the current one is multiplied (one tile per workgroup instead measured
+// 1.4x slower: the rows were staged once per tile).
+constexpr int kMixBwdTiles = 16;
+__global__ void __launch_bounds__(256) k_mix_bwd(RowRange rr, MixOps o) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= M) return;
+  const int K = o.C, N = o.np * o.C;
+  const int nb = blockIdx.y * 64 * kMixBwdTiles, ne = nb + 64 * kMixBwdTiles < N ? nb + 64 * kMixBwdTiles : N;
+  __shared__ __attribute__((aligned(16))) float As[64][68];   // [k][row]
+  __shared__ __attribute__((aligned(16))) float Bs[64][68];   // [k][column]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  // dE/dV rows: row r = idx / 16, channels 4 (idx % 16)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx >> 4, k = 4 * (idx & 15);
+    const int m = m0 + r;
+    float4 v = z4;
+    if (m < M && k < K) v = *reinterpret_cast<const float4*>(o.x + ((int64_t)m * o.nv + o.off) * o.C + k);
+    As[k + 0][r] = v.x;
+    As[k + 1][r] = v.y;
+    As[k + 2][r] = v.z;
+    As[k + 3][r] = v.w;
   }
-};
-struct LoadV {
-  const float* V;
-  int nv, C, off;
-  __device__ float operator()(int m, int k) const { return V[((int64_t)m * nv + off) * C + k]; }
-};
-struct StoreV {
-  float* V;
-  int nv, C, off;
-  __device__ void operator()(int m, int k, float v) const { V[((int64_t)m * nv + off) * C + k] = v; }
-};
+  // W tile of columns [n0, n0 + 64): row k = idx / 16, columns 4 (idx % 16)
+  float4 rb[4];
+  auto fetch = [&](int n0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx >> 4, n = n0 + 4 * (idx & 15);
+      rb[q] = (k < K && n < N) ? *reinterpret_cast<const float4*>(o.W + (int64_t)k * N + n) : z4;
+    }
+  };
+  fetch(nb);
+  for (int n0 = nb; n0 < ne; n0 += 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      *reinterpret_cast<float4*>(&Bs[idx >> 4][4 * (idx & 15)]) = rb[q];
+    }
+    __syncthreads();
+    if (n0 + 64 < ne) fetch(n0 + 64);
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s4 = 0; s4 < K / 4; ++s4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[4 * s4 + lk][32 * wr + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[4 * s4 + lk][32 * wc + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 32 * wr + 16 * i + 4 * lk + q;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int n = n0 + 32 * wc + 16 * j + lr;
+          if (n >= N) continue;
+          const int jp = n / o.C;
+          o.y[((int64_t)m * o.nt + o.toff[jp] + o.m3) * o.C + (n - jp * o.C)] = acc[i][j][q];
+        }
+      }
+  }
+}
 
 }  // namespace
 
@@ -299,19 +452,19 @@ int launch_dense_mix(const afm_model* m, int L, bool bwd, RowRange rr, int64_t E
     for (int k = 0; k < lp.n_paths; ++k)
       if (lp.p[k].out_off == lp.out_off[r]) toff[np++] = dense_t_off(lp, k);
     if (np == 0) continue;
-    const float* A = m->W.mix[L - 1] + m->W.mix_off[L - 1][r];
-    const int K = np * d.c;
+    MixOps o{};
+    o.x = bwd ? feat : tbuf;
+    o.y = bwd ? tbuf : feat;
+    o.W = m->W.mix[L - 1] + m->W.mix_off[L - 1][r];
+    o.C = d.c; o.np = np; o.nt = nt; o.nv = nv;
+    for (int j = 0; j < np; ++j) o.toff[j] = toff[j];
+    const unsigned gx = (unsigned)((E + 63) / 64 > 0 ? (E + 63) / 64 : 1);
+    const int ntile = (np * d.c + 64 * kMixBwdTiles - 1) / (64 * kMixBwdTiles);
     for (int m3 = 0; m3 < 2 * lp.out[r].l + 1; ++m3) {
-      const int off = lp.out_off[r] + m3;
-      if (!bwd) {
-        LoadT al{tbuf, nt, d.c, m3, {}};
-        for (int j = 0; j < np; ++j) al.toff[j] = toff[j];
-        sgemm<true, true>(st, rr, E, K, d.c, A, K, al, StoreV{feat, nv, d.c, off});
-      } else {
-        StoreT ep{tbuf, nt, d.c, m3, {}};
-        for (int j = 0; j < np; ++j) ep.toff[j] = toff[j];
-        sgemm<false, true>(st, rr, E, d.c, K, A, K, LoadV{feat, nv, d.c, off}, ep);
-      }
+      o.m3 = m3;
+      o.off = lp.out_off[r] + m3;
+      if (bwd) hipLaunchKernelGGL(k_mix_bwd, dim3(gx, (unsigned)ntile), dim3(256), 0, st, rr, o);
+      else hipLaunchKernelGGL(k_mix, dim3(gx), dim3(256), 0, st, rr, o);
       AFM_LAUNCH_CHECK();
     }
   }
