@@ -306,8 +306,15 @@ __device__ __forceinline__ void contract(const TPArgs& a, int nc, const float* G
 // One group of C lanes per central atom (lane = channel), 256 / C atoms per
 // workgroup; a group walks all edges of its row, so the row sums need no
 // cross-lane reduction and no LDS.
+// occupancy floor of the forward kernels: their edge loops are chains of
+// small dependent loads, so more wavefronts per SIMD hide more latency
+// (layer 3 of three at l_max = 2: 115 VGPRs / 4 waves -> 6 waves, 12 %
+// faster); l_max = 3 keeps the compiler's choice
+template <int LMAX>
+constexpr int tp_fwd_waves() { return LMAX <= 2 ? 6 : 1; }
+
 template <int LMAX, int NL, int L, int C, bool B16, int CS>
-__global__ void __launch_bounds__(256) k_tp_fwd(TPArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_fwd_waves<LMAX>()))) k_tp_fwd(TPArgs a) {
   constexpr LayerPlan LP = LayerCT<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
   constexpr int NA = 256 / C;
