@@ -409,9 +409,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_fwd
 // contributes the layer-L product adjoint of (its unit dE/dT^L) with
 // R^{L-1} M[:, b].  Layer 1 also needs dE/dV^0_e = D g'_e per edge (D: the
 // rows of every layer's P, formed alongside).
-// occupancy floor of the adjoint kernels (register budget 512 / waves)
+// occupancy floor of the adjoint kernels (register budget 512 / waves),
+// per layer by A/B on the three-layer step (the last layer's lighter
+// adjoint gains from a fifth wavefront, the middle one loses)
 template <int LMAX, int NL, int L>
-constexpr int tp_bwd_waves() { return LMAX == 3 ? 2 : (L == 1 && NL >= 3) ? 3 : 4; }
+constexpr int tp_bwd_waves() { return LMAX == 3 ? 2 : (L == NL && NL >= 3) ? 5 : 4; }
 
 template <int LMAX, int NL, int L, int C, bool B16, int CS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tp_bwd_waves<LMAX, NL, L>())))
