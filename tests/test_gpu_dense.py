@@ -5,8 +5,10 @@ and three-layer models with 8 to 64 channels and l_max 1 and 2, on a
 periodic lattice spanning several edge tiles with a ragged tail and on a
 mixed batch of triclinic cells and open clusters; a run split into several
 row chunks; the split forward / adjoint calls with a random per-structure
-upstream weight; diagonal matrices against the per-path kernels; and the
-double backward's refusal before anything is launched."""
+upstream weight; diagonal matrices against the per-path kernels; MD steps
+and whole evaluations replayed from captured graphs and the no-allocation
+entry point against the eager calls (bitwise); and the double backward's
+refusal before anything is launched."""
 
 import sys
 
@@ -179,3 +181,63 @@ def test_dense_second_order_is_refused():
     calc.energy_forces()
     with pytest.raises(afm.AfmError, match="second-order pass not built for dense mixing"):
         calc.forces_backward(torch.ones(s.n_struct, dtype=torch.float64, device="cuda"), None)
+
+
+def test_dense_md_graph_replay_equals_eager():
+    """MD steps of a dense-mixing model (mixing GEMMs inside the captured
+    step, rebuilds every 10 steps) replayed from hipGraphs equal the eager
+    steps bit for bit, with eager work between the replays."""
+    import torch
+    import paper_2502_06073_amd as afm
+    hp, s, w, _ = _case("l2_L3_w128_c32", "lattice_5cube")
+    masses = synth.species_masses(hp["n_species"], 3005)
+    v0 = synth.maxwell_boltzmann(masses[s.species], 300.0, 3001)
+    mds = []
+    for use_graph in (False, True):
+        calc = afm.Calculator(afm.Model(hp, w, precision="fp32"), afm.DeviceSystem.from_synth(s),
+                              r_list=hp["r_cut"] + 0.5)
+        mds.append(afm.MD(calc, masses, v0, dt_fs=0.5, skin=0.5, rebuild_every=10, use_graph=use_graph))
+    eager, graph = mds
+    for rep in range(3):
+        le = eager.run(10).cpu().numpy()
+        lg = graph.run(10).cpu().numpy()
+        torch.cuda.synchronize()
+        _ = eager.calc.sysd.pos.sum().item()
+        np.testing.assert_array_equal(le, lg)
+        np.testing.assert_array_equal(eager.calc.sysd.pos.cpu().numpy(), graph.calc.sysd.pos.cpu().numpy())
+        np.testing.assert_array_equal(eager.vel.cpu().numpy(), graph.vel.cpu().numpy())
+    assert eager.calc.status() == 0 and graph.calc.status() == 0
+    _say("[dense md graph] 3 x 10 steps bitwise equal")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_dense_eval_graph_and_noalloc_equal_eager(prec):
+    """A captured evaluation of the mixed batch (edge lists, energies,
+    forces, virials) replayed after in-place position updates, and the
+    no-allocation entry point, both equal the eager workspace calls bit for
+    bit."""
+    import torch
+    import paper_2502_06073_amd as afm
+    hp, s, w, _ = _case("l2_L2_w64_c16", "mixed_6")
+    model = afm.Model(hp, w, precision=prec)
+    sysd = afm.DeviceSystem.from_synth(s)
+    cg = afm.Calculator(model, sysd)
+    ce = afm.Calculator(model, sysd)
+    cg.build_neighbors()
+    g = afm.EvalGraph(cg, rebuild=True, virial=True)
+    rng = np.random.default_rng(177)
+    for rep in range(3):
+        if rep:
+            sysd.pos.add_(torch.tensor(rng.uniform(-0.05, 0.05, size=(s.n_atoms, 3)), device="cuda"))
+            torch.cuda.synchronize()
+        out = g.replay()
+        ce.build_neighbors()
+        ref = ce.energy_forces()
+        na = ce.energy_forces_noalloc()
+        torch.cuda.synchronize()
+        for k in ("e_atom", "e_struct", "forces", "virial"):
+            r = ref[k].cpu().numpy()
+            np.testing.assert_array_equal(out[k].cpu().numpy(), r, err_msg=f"graph {k} rep {rep}")
+            np.testing.assert_array_equal(na[k].cpu().numpy(), r, err_msg=f"noalloc {k} rep {rep}")
+        assert cg.status() == 0 and ce.status() == 0
+    _say(f"[dense graph/noalloc {prec}] 3 replays and no-allocation calls bitwise equal to eager")
