@@ -49,11 +49,13 @@ PEAK_FP32 = 157.3e12    # FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12       # HBM3E, B/s
 
 
-def stage_roofline(costs, stats, n_edges, n_atoms, evals):
+def stage_roofline(costs, stats, n_edges, n_atoms, evals, bf16=True):
     """Per traced stage: algorithmic work / average launch time against the
-    roofline that bounds it (MFMA stages: dense BF16 peak; vector stages
-    and the FP32-MFMA mixing GEMMs: whichever of the FP32 peak and HBM
-    needs more time for the algorithmic flops and bytes).  `evals` full evaluations were traced; with row
+    roofline that bounds it (MFMA stages: dense BF16 peak; vector stages:
+    whichever of the FP32 peak and HBM needs more time for the algorithmic
+    flops and bytes; the dense-mixing GEMMs the same with the peak of the
+    matrix cores they run on: FP32 for FP32 models, BF16 (operand pairs)
+    for BF16 models).  `evals` full evaluations were traced; with row
     chunks a stage launches once per chunk, so the work per launch is the
     evaluation's work divided by launches per evaluation."""
     out = {}
@@ -65,12 +67,12 @@ def stage_roofline(costs, stats, n_edges, n_atoms, evals):
         share = evals / st["launches"]
         flops = c["flops_per_edge"] * n_edges * share
         nbytes = (c["bytes_per_edge"] * n_edges + c["bytes_per_atom"] * n_atoms) * share
+        cpeak = PEAK_BF16 if (c["kind"] == "mfma_f32" and bf16) else PEAK_FP32
         if c["kind"] == "mfma":
             bound, peak, work, unit = "mfma", PEAK_BF16, flops, "TFLOP/s"
-        elif flops / PEAK_FP32 >= nbytes / PEAK_HBM:
-            # FP32 matrix cores (dense-mixing GEMMs) peak at the FP32 vector rate
+        elif flops / cpeak >= nbytes / PEAK_HBM:
             bound = "mfma" if c["kind"] == "mfma_f32" else "alu"
-            peak, work, unit = PEAK_FP32, flops, "TFLOP/s"
+            peak, work, unit = cpeak, flops, "TFLOP/s"
         else:
             bound, peak, work, unit = "hbm", PEAK_HBM, nbytes, "GB/s"
         ach = work / avg_s

@@ -424,9 +424,10 @@ int afm_trace_read(afm_trace_stat* out /*host*/, int32_t max, int32_t* n /*host*
  * types (bf16 pre-activations, omega, s and dE/domega; float32 x, dE/dx,
  * dE/ds and geometry; per-atom tensors once per central atom).
  * kind: 0 = dense contraction (MFMA in the BF16 path), 1 = vector ALU /
- * memory stage, 2 = dense contraction on the FP32 matrix cores (the
- * dense-mixing GEMMs, mix_fwd / mix_bwd).  out: host, `max` entries; *n
- * receives the stage count.  */
+ * memory stage, 2 = the dense-mixing GEMMs (mix_fwd / mix_bwd) on the
+ * matrix cores: FP32 for FP32 models, bf16 operand pairs (three products
+ * per block) for BF16 models.  out: host, `max` entries; *n receives the
+ * stage count.  */
 typedef struct {
   char name[32];
   int32_t kind;

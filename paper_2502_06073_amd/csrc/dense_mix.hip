@@ -8,7 +8,8 @@
 // per-edge features V^L, the products T^L and their adjoints are stored, the
 // channelwise products and their adjoints run per atom (one group of C lanes
 // per central atom, lane = channel), and the mixing is a GEMM over the edges
-// of a chunk on the FP32 matrix cores (k_mix), one per output component:
+// of a chunk on the matrix cores (k_mix: FP32; k_mix_b16: BF16 operand pairs
+// for BF16 models), one per output component:
 //   forward   V^L[t][ir3, m3][:] = A_ir3 [T^pi[t][m3][:] over pi -> ir3]
 //   adjoint   dE/dT^pi[t][m3][:] = A_ir3^T dE/dV^L[t][ir3, m3][:]
 // with A_ir3 = [A_pi1 | A_pi2 | ...] the path matrices side by side.
@@ -428,6 +429,132 @@ __global__ void __launch_bounds__(256) k_mix_bwd(RowRange rr, MixOps o) {
   }
 }
 
+// BF16 models: the same GEMMs on v_mfma_f32_16x16x32_bf16 with both
+// operands as bf16 pairs (x = x_hi + x_lo, w = w_hi + w_lo; the pairs of W
+// made at model creation, those of the activations when a stage is staged)
+// and three products per block, x_hi w_hi + x_hi w_lo + x_lo w_hi (the
+// dropped x_lo w_lo is ~2^-16 of the product): FP32-like accuracy at a
+// fraction of the FP32 matrix-core time.  Rows: 64 edges; columns: 64 of
+// the N outputs per workgroup (grid.y); reduction staged 32 at a time.
+// Forward: X = T (K = np C), W rows = A_r ([C][K]); adjoint: X = dE/dV
+// (K = C), W rows = A_r^T ([np C][C]).
+template <bool BWD>
+__global__ void __launch_bounds__(256) k_mix_b16(RowRange rr, MixOps o, const __bf16* __restrict__ Wh,
+                                                 const __bf16* __restrict__ Wl) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= M) return;
+  const int n0 = blockIdx.y * 64;
+  const int K = BWD ? o.C : o.np * o.C, N = BWD ? o.np * o.C : o.C;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[64 * kBfRow], Al[64 * kBfRow];   // [row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * kBfRow], Bl[64 * kBfRow];   // [column][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const uint4 zu = make_uint4(0u, 0u, 0u, 0u);
+  // stage k0: X rows r = idx / 8, reduction k0 + 4 (idx % 8) (two float4 per
+  // thread); W rows (output columns) n0 + tid / 4, k0 + 8 (tid % 4) (one run
+  // of 8 bf16 per term)
+  float4 ra[2];
+  uint4 rh, rl;
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx >> 3, k = k0 + 4 * (idx & 7);
+      const int m = m0 + r;
+      ra[q] = z4;
+      if (m < M && k < K) {
+        const float* src;
+        if constexpr (BWD) {
+          src = o.x + ((int64_t)m * o.nv + o.off) * o.C + k;
+        } else {
+          const int j = k / o.C;
+          src = o.x + ((int64_t)m * o.nt + o.toff[j] + o.m3) * o.C + (k - j * o.C);
+        }
+        ra[q] = *reinterpret_cast<const float4*>(src);
+      }
+    }
+    const int n = n0 + (tid >> 2), k = k0 + 8 * (tid & 3);
+    rh = zu;
+    rl = zu;
+    if (n < N && k < K) {
+      rh = *reinterpret_cast<const uint4*>(Wh + (int64_t)n * K + k);
+      rl = *reinterpret_cast<const uint4*>(Wl + (int64_t)n * K + k);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx >> 3, kk = 4 * (idx & 7);
+      const float v[4] = {ra[q].x, ra[q].y, ra[q].z, ra[q].w};
+      __bf16 h[4], l[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        h[c] = (__bf16)v[c];
+        l[c] = (__bf16)(v[c] - (float)h[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Ah[r * kBfRow + kk + c] = h[c];
+        Al[r * kBfRow + kk + c] = l[c];
+      }
+    }
+    *reinterpret_cast<uint4*>(&Bh[(tid >> 2) * kBfRow + 8 * (tid & 3)]) = rh;
+    *reinterpret_cast<uint4*>(&Bl[(tid >> 2) * kBfRow + 8 * (tid & 3)]) = rl;
+    __syncthreads();
+    if (k0 + 32 < K) fetch(k0 + 32);
+    bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = lds_row8(Ah, 32 * wr + 16 * i + lr, lg);
+      al[i] = lds_row8(Al, 32 * wr + 16 * i + lr, lg);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      bh[j] = lds_row8(Bh, 32 * wc + 16 * j + lr, lg);
+      bl[j] = lds_row8(Bl, 32 * wc + 16 * j + lr, lg);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(al[i], bh[j], acc[i][j]);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + 32 * wr + 16 * i + 4 * lg + q;
+      if (m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 32 * wc + 16 * j + lr;
+        if (n >= N) continue;
+        if constexpr (BWD) {
+          const int jp = n / o.C;
+          o.y[((int64_t)m * o.nt + o.toff[jp] + o.m3) * o.C + (n - jp * o.C)] = acc[i][j][q];
+        } else {
+          o.y[((int64_t)m * o.nv + o.off) * o.C + n] = acc[i][j][q];
+        }
+      }
+    }
+}
+
 }  // namespace
 
 int launch_dense_tp(int lmax, int NL, int L, int C, bool bwd, bool bf16, const DenseArgs& a,
@@ -460,11 +587,22 @@ int launch_dense_mix(const afm_model* m, int L, bool bwd, RowRange rr, int64_t E
     for (int j = 0; j < np; ++j) o.toff[j] = toff[j];
     const unsigned gx = (unsigned)((E + 63) / 64 > 0 ? (E + 63) / 64 : 1);
     const int ntile = (np * d.c + 64 * kMixBwdTiles - 1) / (64 * kMixBwdTiles);
+    const bool b16 = m->prec == AFM_BF16_MFMA;
+    const int64_t T = m->W.mix_elems[L - 1], wo = m->W.mix_off[L - 1][r];
+    const __bf16* wb = reinterpret_cast<const __bf16*>(m->W.mix_b16[L - 1]);
+    if (b16 && !wb) { set_error("internal: bf16 mixing weights missing"); return AFM_E_INVALID; }
     for (int m3 = 0; m3 < 2 * lp.out[r].l + 1; ++m3) {
       o.m3 = m3;
       o.off = lp.out_off[r] + m3;
-      if (bwd) hipLaunchKernelGGL(k_mix_bwd, dim3(gx, (unsigned)ntile), dim3(256), 0, st, rr, o);
-      else hipLaunchKernelGGL(k_mix, dim3(gx), dim3(256), 0, st, rr, o);
+      if (b16 && bwd)
+        hipLaunchKernelGGL(k_mix_b16<true>, dim3(gx, (unsigned)((np * d.c + 63) / 64)), dim3(256), 0, st, rr, o,
+                           wb + 2 * T + wo, wb + 3 * T + wo);
+      else if (b16)
+        hipLaunchKernelGGL(k_mix_b16<false>, dim3(gx), dim3(256), 0, st, rr, o, wb + wo, wb + T + wo);
+      else if (bwd)
+        hipLaunchKernelGGL(k_mix_bwd, dim3(gx, (unsigned)ntile), dim3(256), 0, st, rr, o);
+      else
+        hipLaunchKernelGGL(k_mix, dim3(gx), dim3(256), 0, st, rr, o);
       AFM_LAUNCH_CHECK();
     }
   }

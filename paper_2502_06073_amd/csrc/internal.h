@@ -47,6 +47,11 @@ struct DevWeights {
   // block j: the j-th path into r, in path order) at mix[L-1] + mix_off[L-1][r]
   const float* mix[kMaxLayers] = {};
   int64_t mix_off[kMaxLayers][kMaxIrreps] = {};
+  // BF16 models: the same matrices as bf16 pairs w = hi + lo, four arrays
+  // of mix_elems[L] values each: [hi | lo] of A_r, then [hi | lo] of A_r^T
+  // ([np_r c][c]), every A_r at element offset mix_off[L-1][r]
+  const uint16_t* mix_b16[kMaxLayers] = {};
+  int64_t mix_elems[kMaxLayers] = {};
   const float* w_eff = nullptr;                // [w] = W_E1^T W_E2^T
   const float* e0 = nullptr;                   // [h][w]
   const float* e1 = nullptr;                   // [h]

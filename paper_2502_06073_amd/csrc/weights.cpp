@@ -15,6 +15,20 @@ int mfma_check_shape(const afm_model* m);                                       
 
 namespace afm {
 
+// float -> bf16 bits, rounding to nearest even (weights are finite)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
 static const afm_param_block* find_block(const afm_model* m, const char* name) {
   for (auto& b : m->blocks)
     if (strcmp(b.name, name) == 0) return &b;
@@ -82,6 +96,30 @@ int pack_weights(afm_model* m, const double* w) {
                    sizeof(double) * d.c);
       }
       put_f32((const void**)&m->W.mix[L - 1], rep.data(), (int64_t)rep.size());
+      if (m->prec == AFM_BF16_MFMA) {
+        // hi = bf16(f), lo = bf16(f - hi) of the FP32 value f, for A_r and A_r^T
+        const int64_t T = (int64_t)rep.size();
+        m->W.mix_elems[L - 1] = T;
+        int64_t o = reserve(4 * T * 2);
+        uint16_t* q = reinterpret_cast<uint16_t*>(host.data() + o);
+        auto split = [&](int64_t dst, double v) {
+          const float f = (float)v;
+          const uint16_t h = bf16_rne(f);
+          q[dst] = h;
+          q[T + dst] = bf16_rne(f - bf16_value(h));
+        };
+        for (int r = 0; r < lp.n_out; ++r) {
+          int np = 0;
+          for (int k = 0; k < lp.n_paths; ++k) np += lp.p[k].out_off == lp.out_off[r];
+          const int64_t base = m->W.mix_off[L - 1][r], K = (int64_t)np * d.c;
+          for (int64_t n = 0; n < d.c; ++n)
+            for (int64_t k = 0; k < K; ++k) {
+              split(base + n * K + k, rep[base + n * K + k]);
+              split(2 * T + base + k * d.c + n, rep[base + n * K + k]);
+            }
+        }
+        fix.push_back({(const void**)&m->W.mix_b16[L - 1], o});
+      }
     } else if (L < d.NL) {
       snprintf(nm, sizeof nm, "layer%d.alpha", L);
       b = find_block(m, nm);
