@@ -434,11 +434,9 @@ __global__ void __launch_bounds__(256) k_mix_bwd(RowRange rr, MixOps o) {
 // made at model creation, those of the activations when a stage is staged)
 // and three products per block, x_hi w_hi + x_hi w_lo + x_lo w_hi (the
 // dropped x_lo w_lo is ~2^-16 of the product): FP32-like accuracy at a
-// fraction of the FP32 matrix-core time.  Rows: 64 edges; columns: 64 of
-// the N outputs per workgroup (grid.y); reduction staged 32 at a time.
-// Forward: X = T (K = np C), W rows = A_r ([C][K]); adjoint: X = dE/dV
-// (K = C), W rows = A_r^T ([np C][C]).
-template <bool BWD>
+// fraction of the FP32 matrix-core time.  Forward: 64 edges x the C <= 64
+// output channels per workgroup, X = T (K = np C) staged 32 at a time,
+// W rows = A_r ([C][K]).
 __global__ void __launch_bounds__(256) k_mix_b16(RowRange rr, MixOps o, const __bf16* __restrict__ Wh,
                                                  const __bf16* __restrict__ Wl) {
   int64_t e0, e1;
@@ -446,8 +444,8 @@ __global__ void __launch_bounds__(256) k_mix_b16(RowRange rr, MixOps o, const __
   const int M = (int)(e1 - e0);
   const int m0 = blockIdx.x * 64;
   if (m0 >= M) return;
-  const int n0 = blockIdx.y * 64;
-  const int K = BWD ? o.C : o.np * o.C, N = BWD ? o.np * o.C : o.C;
+  const int n0 = 0;
+  const int K = o.np * o.C, N = o.C;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[64 * kBfRow], Al[64 * kBfRow];   // [row][k]
   __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * kBfRow], Bl[64 * kBfRow];   // [column][k]
   const int tid = threadIdx.x;
@@ -473,14 +471,8 @@ __global__ void __launch_bounds__(256) k_mix_b16(RowRange rr, MixOps o, const __
       const int m = m0 + r;
       ra[q] = z4;
       if (m < M && k < K) {
-        const float* src;
-        if constexpr (BWD) {
-          src = o.x + ((int64_t)m * o.nv + o.off) * o.C + k;
-        } else {
-          const int j = k / o.C;
-          src = o.x + ((int64_t)m * o.nt + o.toff[j] + o.m3) * o.C + (k - j * o.C);
-        }
-        ra[q] = *reinterpret_cast<const float4*>(src);
+        const int j = k / o.C;
+        ra[q] = *reinterpret_cast<const float4*>(o.x + ((int64_t)m * o.nt + o.toff[j] + o.m3) * o.C + (k - j * o.C));
       }
     }
     const int n = n0 + (tid >> 2), k = k0 + 8 * (tid & 3);
@@ -544,15 +536,119 @@ __global__ void __launch_bounds__(256) k_mix_b16(RowRange rr, MixOps o, const __
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int n = n0 + 32 * wc + 16 * j + lr;
-        if (n >= N) continue;
-        if constexpr (BWD) {
-          const int jp = n / o.C;
-          o.y[((int64_t)m * o.nt + o.toff[jp] + o.m3) * o.C + (n - jp * o.C)] = acc[i][j][q];
-        } else {
-          o.y[((int64_t)m * o.nv + o.off) * o.C + n] = acc[i][j][q];
-        }
+        if (n < N) o.y[((int64_t)m * o.nv + o.off) * o.C + n] = acc[i][j][q];
       }
     }
+}
+
+// Adjoint on bf16 pairs with the rows staged once: a workgroup splits its
+// 64 rows of dE/dV (K = C <= 64) into LDS, then sweeps the np C output
+// columns 64 at a time (W = A_r^T pairs, the next tile fetched into
+// registers while the current one is multiplied; one column tile per
+// workgroup, the rows staged once per tile, measured 1.2x slower).
+constexpr int kRowK = 72;   // bf16 per LDS row: 64 reduction values + 8 of padding (16-byte aligned rows)
+__device__ __forceinline__ bf16x8_t lds_row8k(const __bf16* T, int r, int k) {
+  return *reinterpret_cast<const bf16x8_t*>(T + r * kRowK + k);
+}
+__global__ void __launch_bounds__(256) k_mix_b16_bwd(RowRange rr, MixOps o, const __bf16* __restrict__ Wh,
+                                                     const __bf16* __restrict__ Wl) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int M = (int)(e1 - e0);
+  const int m0 = blockIdx.x * 64;
+  if (m0 >= M) return;
+  const int K = o.C, N = o.np * o.C;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[64 * kRowK], Al[64 * kRowK];   // [row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[64 * kRowK], Bl[64 * kRowK];   // [column][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  const uint4 zu = make_uint4(0u, 0u, 0u, 0u);
+  // rows r = idx / 16, channels 4 (idx % 16)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx >> 4, k = 4 * (idx & 15);
+    const int m = m0 + r;
+    float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (m < M && k < K) x = *reinterpret_cast<const float4*>(o.x + ((int64_t)m * o.nv + o.off) * o.C + k);
+    const float v[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const __bf16 h = (__bf16)v[c];
+      Ah[r * kRowK + k + c] = h;
+      Al[r * kRowK + k + c] = (__bf16)(v[c] - (float)h);
+    }
+  }
+  // W tile: columns n0 + idx / 8, reduction 8 (idx % 8)
+  uint4 rh[2], rl[2];
+  auto fetch = [&](int n0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int n = n0 + (idx >> 3), k = 8 * (idx & 7);
+      rh[q] = zu;
+      rl[q] = zu;
+      if (n < N && k < K) {
+        rh[q] = *reinterpret_cast<const uint4*>(Wh + (int64_t)n * K + k);
+        rl[q] = *reinterpret_cast<const uint4*>(Wl + (int64_t)n * K + k);
+      }
+    }
+  };
+  fetch(0);
+  const int ks = (K + 31) / 32;
+  for (int n0 = 0; n0 < N; n0 += 64) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      *reinterpret_cast<uint4*>(&Bh[(idx >> 3) * kRowK + 8 * (idx & 7)]) = rh[q];
+      *reinterpret_cast<uint4*>(&Bl[(idx >> 3) * kRowK + 8 * (idx & 7)]) = rl[q];
+    }
+    __syncthreads();
+    if (n0 + 64 < N) fetch(n0 + 64);
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int st = 0; st < ks; ++st) {
+      const int kb = 32 * st + 8 * lg;
+      bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ah[i] = lds_row8k(Ah, 32 * wr + 16 * i + lr, kb);
+        al[i] = lds_row8k(Al, 32 * wr + 16 * i + lr, kb);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        bh[j] = lds_row8k(Bh, 32 * wc + 16 * j + lr, kb);
+        bl[j] = lds_row8k(Bl, 32 * wc + 16 * j + lr, kb);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+          acc[i][j] = mfma_bf16(ah[i], bl[j], acc[i][j]);
+          acc[i][j] = mfma_bf16(al[i], bh[j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 32 * wr + 16 * i + 4 * lg + q;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int n = n0 + 32 * wc + 16 * j + lr;
+          if (n >= N) continue;
+          const int jp = n / o.C;
+          o.y[((int64_t)m * o.nt + o.toff[jp] + o.m3) * o.C + (n - jp * o.C)] = acc[i][j][q];
+        }
+      }
+  }
 }
 
 }  // namespace
@@ -595,10 +691,9 @@ int launch_dense_mix(const afm_model* m, int L, bool bwd, RowRange rr, int64_t E
       o.m3 = m3;
       o.off = lp.out_off[r] + m3;
       if (b16 && bwd)
-        hipLaunchKernelGGL(k_mix_b16<true>, dim3(gx, (unsigned)((np * d.c + 63) / 64)), dim3(256), 0, st, rr, o,
-                           wb + 2 * T + wo, wb + 3 * T + wo);
+        hipLaunchKernelGGL(k_mix_b16_bwd, dim3(gx), dim3(256), 0, st, rr, o, wb + 2 * T + wo, wb + 3 * T + wo);
       else if (b16)
-        hipLaunchKernelGGL(k_mix_b16<false>, dim3(gx), dim3(256), 0, st, rr, o, wb + wo, wb + T + wo);
+        hipLaunchKernelGGL(k_mix_b16, dim3(gx), dim3(256), 0, st, rr, o, wb + wo, wb + T + wo);
       else if (bwd)
         hipLaunchKernelGGL(k_mix_bwd, dim3(gx, (unsigned)ntile), dim3(256), 0, st, rr, o);
       else
