@@ -336,9 +336,18 @@ __device__ __forceinline__ bf16x8_t lds_row8(const __bf16* T, int r, int g) {
   return *reinterpret_cast<const bf16x8_t*>(T + r * kBfRow + 8 * g);
 }
 
-template <bool NT, class AL, class EP>
+// BN output columns per workgroup (64 or 128): with 128 a wavefront owns
+// 32 x 64 of the tile, so every A element (whose loader may apply SiLU or
+// gather a concatenation) is loaded once for up to 128 outputs, and each
+// staged k-step feeds twice the MFMAs; the sequence of products into every
+// output is the same for both widths.  (The weight-gradient kernel below
+// keeps 64 x 64 tiles: 128-wide ones halve its workgroups and measured
+// slower.)
+template <bool NT, int BN, class AL, class EP>
 __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, const float* __restrict__ W, int ldw,
                                                     AL al, EP ep, int stack) {
+  static_assert(BN == 64 || BN == 128, "BN");
+  constexpr int NJ = BN / 32;   // 16-column blocks per wavefront
   int64_t e0, e1;
   rr.get(e0, e1);
   const int M = (int)(e1 - e0);
@@ -346,21 +355,22 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
   const int m0 = blockIdx.x * 64;
   if (m0 >= rows) return;
   if (stack && (m0 % stack) >= M) return;
-  const int n0 = blockIdx.y * 64;
+  const int n0 = blockIdx.y * BN;
   constexpr int KS = 32;
   __shared__ __attribute__((aligned(16))) __bf16 As[64 * kBfRow];   // [m][k]
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[64 * kBfRow];   // [n][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN * kBfRow];   // [n][k]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
   const int lr = lane & 15, lg = lane >> 4;
-  f32x4_t acc[2][2];
+  f32x4_t acc[2][NJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
   // next stage fetched into registers while the current one is multiplied;
   // A: element (r, kk) = (idx / 32, idx % 32), consecutive lanes along k
-  float ra[8], rb[8];
+  constexpr int QB = BN / 8;   // W elements per thread per stage
+  float ra[8], rb[QB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -368,8 +378,12 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
       const int r = idx >> 5, kk = idx & 31;
       const int m = m0 + r, k = k0 + kk;
       ra[q] = (m < rows && row_live(m, M, stack) && k < K) ? al(m, k) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int idx = tid + 256 * q;
       int c, kb;
-      if (NT) { c = idx >> 5; kb = idx & 31; } else { kb = idx >> 6; c = idx & 63; }
+      if (NT) { c = idx >> 5; kb = idx & 31; } else { kb = idx / BN; c = idx % BN; }
       const int k2 = k0 + kb, n = n0 + c;
       float v = 0.0f;
       if (k2 < K && n < N) v = NT ? W[(int64_t)n * ldw + k2] : W[(int64_t)k2 * ldw + n];
@@ -382,20 +396,24 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + 256 * q;
       As[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int idx = tid + 256 * q;
       if (NT) Bs[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)rb[q];
-      else Bs[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)rb[q];
+      else Bs[(idx % BN) * kBfRow + idx / BN] = (__bf16)rb[q];
     }
     __syncthreads();
     if (k0 + KS < K) fetch(k0 + KS);
-    bf16x8_t a[2], b[2];
+    bf16x8_t a[2], b[NJ];
 #pragma unroll
     for (int i = 0; i < 2; ++i) a[i] = lds_row8(As, 32 * wr + 16 * i + lr, lg);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = lds_row8(Bs, 32 * wc + 16 * j + lr, lg);
+    for (int j = 0; j < NJ; ++j) b[j] = lds_row8(Bs, (BN / 2) * wc + 16 * j + lr, lg);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < NJ; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
     __syncthreads();
   }
 #pragma unroll
@@ -405,8 +423,8 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
       const int m = m0 + 32 * wr + 16 * i + 4 * lg + q;
       if (m >= rows || !row_live(m, M, stack)) continue;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 32 * wc + 16 * j + lr;
+      for (int j = 0; j < NJ; ++j) {
+        const int n = n0 + (BN / 2) * wc + 16 * j + lr;
         if (n < N) ep(m, n, acc[i][j][q]);
       }
     }
@@ -488,8 +506,11 @@ inline void sgemm_so(bool bf16, hipStream_t st, RowRange rr, int64_t max_rows, i
                      AL al, EP ep, int stack) {
   const int64_t rows = stack ? 2 * (int64_t)stack : max_rows;
   dim3 grid((unsigned)((rows + 63) / 64 > 0 ? (rows + 63) / 64 : 1), (unsigned)((N + 63) / 64));
-  if (bf16)
-    hipLaunchKernelGGL((k_sgemm_bf16<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
+  if (bf16 && N > 64) {
+    grid.y = (unsigned)((N + 127) / 128);
+    hipLaunchKernelGGL((k_sgemm_bf16<NT, 128, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
+  } else if (bf16)
+    hipLaunchKernelGGL((k_sgemm_bf16<NT, 64, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
   else
     hipLaunchKernelGGL((k_sgemm_mfma<NT, AL, EP>), grid, dim3(256), 0, st, rr, K, N, W, ldw, al, ep, stack);
 }
