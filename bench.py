@@ -611,7 +611,7 @@ def main(argv=None):
     dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom_name]
     roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"], frac=r["frac"],
-                traffic=load_traffic(dom_name, "configB") if MIXING == "path" else None,
+                traffic=load_traffic(dom_name, "configB" if MIXING == "path" else "configB_dense"),
                 kernel=dom_name, avg_ms=r["avg_ms"],
                 per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]))
     mlp_flops = sum(roofs[k]["flops_per_launch"] for k in roofs if costs[k]["kind"] == "mfma")
