@@ -8,8 +8,9 @@
 // per-edge features V^L, the products T^L and their adjoints are stored, the
 // channelwise products and their adjoints run per atom (one group of C lanes
 // per central atom, lane = channel), and the mixing is a GEMM over the edges
-// of a chunk on the matrix cores (k_mix: FP32; k_mix_b16: BF16 operand pairs
-// for BF16 models), one per output component:
+// of a chunk on the matrix cores (k_mix / k_mix_bwd in FP32 for FP32 models,
+// k_mix_b16 / k_mix_b16_bwd on bf16 operand pairs for BF16 models), one per
+// output component:
 //   forward   V^L[t][ir3, m3][:] = A_ir3 [T^pi[t][m3][:] over pi -> ir3]
 //   adjoint   dE/dT^pi[t][m3][:] = A_ir3^T dE/dV^L[t][ir3, m3][:]
 // with A_ir3 = [A_pi1 | A_pi2 | ...] the path matrices side by side.
