@@ -101,6 +101,7 @@ def choose_tile(calc):
 
 
 MIXING = "path"      # --mixing dense: the dense post-product channel-mixing model
+MODEL = "fm256"      # --model fm512: Table 1's 512-wide shape on the same workload
 
 
 def setup(config, precision):
@@ -108,6 +109,8 @@ def setup(config, precision):
     import synth
     import paper_2502_06073_amd as afm
     hp = dict(synth.load_hparams(config), mixing=MIXING)
+    if MODEL == "fm512":
+        hp.update(latent=512, channels=128, twobody=[128, 256, 512])
     s = synth.SYSTEMS[config]()
     w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS[config])
     model = afm.Model(hp, w, precision=precision)
@@ -558,6 +561,9 @@ def main(argv=None):
                     help="fix the BF16 chains' edge-tile shape (64x8, 128x16, 128x8) instead of tuning")
     ap.add_argument("--mixing", default="path", choices=["path", "dense"],
                     help="config B: per-path mixing weights (default) or dense channel-mixing matrices")
+    ap.add_argument("--model", default="fm256", choices=["fm256", "fm512"],
+                    help="config B: the FM256 shape (default) or Table 1's 512-wide FM512 shape "
+                         "(latent 512, 128 channels, two-body [128, 256, 512])")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -577,12 +583,15 @@ def main(argv=None):
     if a.edge_tile:
         global FORCED_TILE
         FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))
-    if a.mixing != "path":
+    if a.mixing != "path" or a.model != "fm256":
         if a.config != "B":
-            print("--mixing dense is measured on config B only", file=sys.stderr)
+            print("--mixing dense and --model fm512 are measured on config B only", file=sys.stderr)
             return 2
-        global MIXING
-        MIXING = a.mixing
+        if a.mixing != "path" and a.model != "fm256":
+            print("dense mixing is built for channels <= 64 (not the FM512 shape)", file=sys.stderr)
+            return 2
+        global MIXING, MODEL
+        MIXING, MODEL = a.mixing, a.model
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); "
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
@@ -611,7 +620,8 @@ def main(argv=None):
     dom_name = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
     r = roofs[dom_name]
     roof = dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"], frac=r["frac"],
-                traffic=load_traffic(dom_name, "configB" if MIXING == "path" else "configB_dense"),
+                traffic=(load_traffic(dom_name, "configB" if MIXING == "path" else "configB_dense")
+                         if MODEL == "fm256" else None),
                 kernel=dom_name, avg_ms=r["avg_ms"],
                 per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"]))
     mlp_flops = sum(roofs[k]["flops_per_launch"] for k in roofs if costs[k]["kind"] == "mfma")
@@ -621,9 +631,11 @@ def main(argv=None):
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="bf16",
                data="synthetic (seeded jittered lattice, N(0,1/fan_in) weights)",
                config=dict(workload=f"{s.n_atoms}-atom periodic jittered SC lattice (24^3, a=2.2 A), 4 species, "
-                                    f"r_c 5.5 A, l_max 2, 2 layers, latent 256, 3-layer MLPs, energy+forces+virial "
+                                    f"r_c 5.5 A, l_max 2, 2 layers, latent {hp['latent']}, 3-layer MLPs, energy+forces+virial "
                                     f"incl. edge-list build"
                                     + (", dense post-product channel mixing" if MIXING == "dense" else "")
+                                    + ("; FM512 shape: 128 channels, two-body [128, 256, 512]"
+                                       if MODEL == "fm512" else "")
                                     if a.config == "B" else f"config {a.config}",
                            n_atoms=s.n_atoms, n_edges=n_edges, edge_tile="%dx%d" % calc.tune["tile"],
                            parallelism="single GPU"),
