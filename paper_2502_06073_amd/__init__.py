@@ -16,6 +16,7 @@ a GPU the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -177,6 +178,11 @@ class Model:
             self.handle = C.c_void_p()
 
     def __del__(self):
+        # during interpreter shutdown torch's operator registry may already be
+        # gone, and the device context in close() would abort the process;
+        # the driver releases the device memory at exit anyway
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

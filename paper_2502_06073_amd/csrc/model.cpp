@@ -476,7 +476,8 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
     const LayerPlan& lp = P.layer[L - 1];
     const bool last = L == d.NL;
     double nz = 0, outc = 0;
-    std::vector<double> buf(125);
+    // one real CG tensor, (2 l + 1)^3 values for l up to l_max
+    std::vector<double> buf((2 * kMaxLmax + 1) * (2 * kMaxLmax + 1) * (2 * kMaxLmax + 1));
     for (int k = 0; k < lp.n_paths; ++k) {
       const PathT& t = lp.p[k];
       real_cg(t.l1, t.l2, t.l3, buf.data());

@@ -169,3 +169,17 @@ def test_stage_costs_dense_mixing():
     comps = sum(2 * p[3] + 1 for p in paths[0] if (p[3], p[4]) in used)
     C_ = hp["channels"]
     assert c["mix_fwd1"]["flops_per_edge"] == 2 * C_ * C_ * comps == c["mix_bwd1"]["flops_per_edge"]
+
+
+def test_stage_costs_lmax3():
+    """The cost model of an l_max = 3 model (its CG tensors have up to 7^3
+    entries) gives positive figures for every stage and more tensor-product
+    work than the l_max = 2 model of the same widths."""
+    import paper_2502_06073_amd as afm
+    hp2 = synth.load_hparams("B")
+    c2 = afm.stage_costs(hp2)
+    c3 = afm.stage_costs(dict(hp2, l_max=3))
+    assert set(c3) == set(c2)
+    assert all(v["flops_per_edge"] > 0 and v["bytes_per_edge"] > 0 for v in c3.values())
+    for k in ("tp_fwd1", "tp_bwd1", "tp_fwd2", "tp_bwd2"):
+        assert c3[k]["flops_per_edge"] > c2[k]["flops_per_edge"], k
