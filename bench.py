@@ -101,7 +101,7 @@ def choose_tile(calc):
 
 
 MIXING = "path"      # --mixing dense: the dense post-product channel-mixing model
-MODEL = "fm256"      # --model fm512: Table 1's 512-wide shape on the same workload
+MODEL = "fm256"      # --model fm512 / lmax3: Table 1's 512-wide shape, or l_max = 3, on the same workload
 
 
 def setup(config, precision):
@@ -111,6 +111,8 @@ def setup(config, precision):
     hp = dict(synth.load_hparams(config), mixing=MIXING)
     if MODEL == "fm512":
         hp.update(latent=512, channels=128, twobody=[128, 256, 512])
+    elif MODEL == "lmax3":
+        hp.update(l_max=3)
     s = synth.SYSTEMS[config]()
     w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS[config])
     model = afm.Model(hp, w, precision=precision)
@@ -561,9 +563,10 @@ def main(argv=None):
                     help="fix the BF16 chains' edge-tile shape (64x8, 128x16, 128x8) instead of tuning")
     ap.add_argument("--mixing", default="path", choices=["path", "dense"],
                     help="config B: per-path mixing weights (default) or dense channel-mixing matrices")
-    ap.add_argument("--model", default="fm256", choices=["fm256", "fm512"],
-                    help="config B: the FM256 shape (default) or Table 1's 512-wide FM512 shape "
-                         "(latent 512, 128 channels, two-body [128, 256, 512])")
+    ap.add_argument("--model", default="fm256", choices=["fm256", "fm512", "lmax3"],
+                    help="config B: the FM256 shape (default), Table 1's 512-wide FM512 shape "
+                         "(latent 512, 128 channels, two-body [128, 256, 512]) or the FM256 shape "
+                         "with l_max = 3")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
@@ -585,10 +588,10 @@ def main(argv=None):
         FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))
     if a.mixing != "path" or a.model != "fm256":
         if a.config != "B":
-            print("--mixing dense and --model fm512 are measured on config B only", file=sys.stderr)
+            print("--mixing dense and --model are measured on config B only", file=sys.stderr)
             return 2
         if a.mixing != "path" and a.model != "fm256":
-            print("dense mixing is built for channels <= 64 (not the FM512 shape)", file=sys.stderr)
+            print("dense mixing is measured on the FM256 shape only", file=sys.stderr)
             return 2
         global MIXING, MODEL
         MIXING, MODEL = a.mixing, a.model
@@ -631,7 +634,7 @@ def main(argv=None):
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="bf16",
                data="synthetic (seeded jittered lattice, N(0,1/fan_in) weights)",
                config=dict(workload=f"{s.n_atoms}-atom periodic jittered SC lattice (24^3, a=2.2 A), 4 species, "
-                                    f"r_c 5.5 A, l_max 2, 2 layers, latent {hp['latent']}, 3-layer MLPs, energy+forces+virial "
+                                    f"r_c 5.5 A, l_max {hp['l_max']}, 2 layers, latent {hp['latent']}, 3-layer MLPs, energy+forces+virial "
                                     f"incl. edge-list build"
                                     + (", dense post-product channel mixing" if MIXING == "dense" else "")
                                     + ("; FM512 shape: 128 channels, two-body [128, 256, 512]"
