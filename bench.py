@@ -503,33 +503,34 @@ def bench_batch(a):
                            edge_tile="%dx%d" % tune["tile"], parallelism="single GPU"),
                edge_tile_tuner_ms=tune["ms"],
                roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
-                             frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"]),
+                             frac=r["frac"], traffic=load_traffic(dom, "configD"), kernel=dom, avg_ms=r["avg_ms"]),
                eager_ms_per_step=dt_eager / a.steps * 1e3,
                stage_ms={k: round(v["total_ms"] / v["launches"], 4) for k, v in stats.items()})
     del g
     # one call per structure: a calculator per structure, 512 evaluations per step
-    calcs = []
-    for k in range(s.n_struct):
-        lo, hi = int(s.seg[k]), int(s.seg[k + 1])
-        sk = afm.DeviceSystem.from_arrays(s.pos[lo:hi], s.species[lo:hi], s.cell[k:k + 1], s.pbc[k:k + 1],
-                                          np.array([0, hi - lo]))
-        ck = afm.Calculator(model, sk, r_list=hp.get("r_list", hp["r_cut"]))
-        calcs.append(ck)
-    n_ps = max(2, a.steps // 4)
-    for ck in calcs:
-        ck.build_neighbors()
-        ck.energy_forces()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_ps):
+    n_ps = 0 if a.no_per_structure else max(2, a.steps // 4)
+    if n_ps:
+        calcs = []
+        for k in range(s.n_struct):
+            lo, hi = int(s.seg[k]), int(s.seg[k + 1])
+            sk = afm.DeviceSystem.from_arrays(s.pos[lo:hi], s.species[lo:hi], s.cell[k:k + 1], s.pbc[k:k + 1],
+                                              np.array([0, hi - lo]))
+            ck = afm.Calculator(model, sk, r_list=hp.get("r_list", hp["r_cut"]))
+            calcs.append(ck)
         for ck in calcs:
             ck.build_neighbors()
             ck.energy_forces()
-    torch.cuda.synchronize()
-    dt_ps = time.perf_counter() - t0
-    out["per_structure_calls"] = dict(value=s.n_atoms * n_ps / dt_ps, ms_per_step=dt_ps / n_ps * 1e3, steps=n_ps,
-                                      what="one edge-list build + energy_forces call per structure")
-    del calcs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_ps):
+            for ck in calcs:
+                ck.build_neighbors()
+                ck.energy_forces()
+        torch.cuda.synchronize()
+        dt_ps = time.perf_counter() - t0
+        out["per_structure_calls"] = dict(value=s.n_atoms * n_ps / dt_ps, ms_per_step=dt_ps / n_ps * 1e3,
+                                          steps=n_ps, what="one edge-list build + energy_forces call per structure")
+        del calcs
     if not a.no_fp32:
         print("[bench] D: timing fp32 plain", file=sys.stderr, flush=True)
         _, _, _, c32 = setup("D", "fp32")
@@ -567,6 +568,8 @@ def main(argv=None):
                     help="config B: the FM256 shape (default), Table 1's 512-wide FM512 shape "
                          "(latent 512, 128 channels, two-body [128, 256, 512]) or the FM256 shape "
                          "with l_max = 3")
+    ap.add_argument("--no-per-structure", action="store_true",
+                    help="config D: skip timing one call per structure (profiler runs of the batch alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (HBM counter calibration)")
     a = ap.parse_args(argv)
