@@ -429,6 +429,11 @@ def bench_train(a):
     stats = afm.trace_read()
     afm.trace_enable(False)
     value = s.n_atoms * a.steps / dt
+    n_edges = int(calc.nl.n_edges.item())
+    costs = afm.stage_costs(hp)
+    roofs = stage_roofline(costs, stats, n_edges, s.n_atoms, a.steps)
+    dom = max(roofs, key=lambda k: roofs[k]["avg_ms"] * stats[k]["launches"])
+    r = roofs[dom]
     # the optimiser update on top (Adam kernel + repack of the model's weights)
     opt = afm.Adam(model, w, lr=1e-4)
     opt.step(theta.grad)
@@ -443,15 +448,48 @@ def bench_train(a):
                ms_per_step=dt / a.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="bf16+fp32", data="synthetic (seeded clusters, N(0,1) targets, N(0,1/fan_in) weights)",
                config=dict(workload=f"force-matching training step, {s.n_struct} clusters / {s.n_atoms} atoms, "
-                                    f"l_max 2, 2 layers, latent 128: BF16 energies+forces, FP32 double backward "
-                                    f"for the weight gradient of the E+F loss",
+                                    f"l_max 2, 2 layers, latent 128: BF16 energies+forces, double backward on BF16 "
+                                    f"MFMA (FP32 accumulation) for the weight gradient of the E+F loss",
                            n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=int(calc.nl.n_edges.item()),
                            n_params=calc.model_n_params(), parallelism="single GPU"),
                steps_per_s=a.steps / dt, loss=float(loss.item()),
                adam_update_ms=adam_ms,
+               roofline=dict(bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
+                             frac=r["frac"], traffic=None, kernel=dom, avg_ms=r["avg_ms"],
+                             per_launch=(r["flops_per_launch"] if r["unit"] == "TFLOP/s" else r["bytes_per_launch"])),
+               stage_roofline={k: dict(bound=v["bound"], frac=round(v["frac"], 4),
+                                       achieved=round(v["achieved"], 2), unit=v["unit"]) for k, v in roofs.items()},
                stage_ms={k: round(v["total_ms"] / a.steps, 4) for k, v in stats.items()})
+    if not a.no_cpu_baseline:
+        print("[bench] C: oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_train(hp, s, w, e_hat, f_hat)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def cpu_baseline_train(hp, s, w, e_hat, f_hat, budget_s=25.0):
+    """The FP64 oracle's training step (loss and weight gradient through its
+    autograd double backward), as it stands, on the first k clusters of the
+    batch, k grown until a run takes about half the budget."""
+    import torch
+    import synth
+    from oracle import model as M
+
+    def run(k):
+        hi = int(s.seg[k])
+        sub = synth.System(s.pos[:hi], s.species[:hi], s.cell[:k], s.pbc[:k], s.seg[:k + 1].copy(), s.n_species)
+        t0 = time.perf_counter()
+        M.loss_and_grad(hp, w, sub, e_hat[:k], f_hat[:hi], r_list=hp.get("r_list", hp["r_cut"]))
+        return time.perf_counter() - t0, hi
+    k = 1
+    while True:
+        t, n = run(k)
+        if t >= 0.4 * budget_s or k == s.n_struct:
+            break
+        k = int(min(s.n_struct, max(k + 1, k * min(4.0, 0.6 * budget_s / max(t, 1e-3)))))
+    return dict(value=n / t, unit="atom-steps/s", cores=int(torch.get_num_threads()), kind="oracle",
+                sample=f"the first {k} of {s.n_struct} clusters ({n} atoms): loss and weight gradient, FP64, "
+                       f"{t:.1f} s; os.cpu_count()={os.cpu_count()}")
 
 
 def bench_batch(a):

@@ -545,6 +545,24 @@ int afm_stage_costs(const afm_hparams* hp, afm_stage_cost* out, int32_t max, int
   }
   // rho and u adjoints in, dE/d delta out
   add("geometry_bwd", 0, 1, 40.0 + 4.0 * d.nb, 4.0 * (GEO_Y + 9) + 4 * (16 + 16) + 12, 0);
+  // the double backward (afm_backward_forces_backward): its GEMMs over the
+  // stacked primal and tangent rows (2 per edge) -- the forward chains, then
+  // per weight matrix the input-gradient and the weight-gradient products;
+  // its vector-ALU tensor-product passes are not counted
+  {
+    double mac = 0, io = 0;   // per stacked row
+    auto gemm = [&](double k, double n, int times) { mac += times * k * n; io += times * 4.0 * (k + n); };
+    gemm(2.0 * d.S + d.nb, d.tb[0], 2);                       // first two-body layer, its weight gradient
+    for (int k = 1; k < d.ntb; ++k) gemm(d.tb[k - 1], d.tb[k], 3);
+    gemm(W, ENV, 3);                                          // env^1
+    for (int L = 1; L <= d.NL; ++L) {
+      const double lin = W + P.layer[L - 1].n0e * C;
+      gemm(lin, W, 3);
+      for (int k = 1; k < d.depth; ++k) gemm(W, W, 3);
+      if (L < d.NL) gemm(W, ENV, 3);
+    }
+    add("second_order", 0, 0, 2.0 * 2.0 * mac, 2.0 * io, 0);
+  }
   add("energy", 0, 1, 1.0, 4, 8 + 4 + 8);
   // dE/d delta of the edge and of its reverse, col, rev, shift in; forces + virial per atom out
   add("force_scatter", 0, 1, 12.0 + 18.0, 12 + 12 + 4 + 4 + 3, 24 + 72);

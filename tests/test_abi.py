@@ -141,6 +141,7 @@ def test_stage_costs_cover_traced_stages():
     for L in (1, 2):
         names |= {f"tp_fwd{L}", f"tp_bwd{L}", f"latent_fwd{L}", f"latent_bwd{L}"}
     names.add("latent_fb2")                  # the fused last layer: forward + adjoint
+    names.add("second_order")                # the double backward's GEMMs
     assert set(c) == names
     assert c["latent_fb2"]["flops_per_edge"] == c["latent_fwd2"]["flops_per_edge"] + c["latent_bwd2"]["flops_per_edge"]
     W, C, D = hp["latent"], hp["channels"], hp["latent_depth"]
@@ -151,7 +152,12 @@ def test_stage_costs_cover_traced_stages():
     assert c["latent_bwd2"]["flops_per_edge"] == 2 * lat1
     tb = hp["twobody"]
     assert c["twobody_fwd"]["flops_per_edge"] == 2 * (hp["n_bessel"] * tb[0] + tb[0] * tb[1] + tb[1] * tb[2] + W * env)
-    assert all(v["kind"] == ("mfma" if k.startswith(("latent", "twobody")) else "vector") for k, v in c.items())
+    assert all(v["kind"] == ("mfma" if k.startswith(("latent", "twobody", "second")) else "vector") for k, v in c.items())
+    # the double backward: three products (forward, input and weight gradient) per weight matrix over
+    # two stacked rows per edge, two for the first two-body layer
+    lat = sum(3 * (((W + 3 * C) if k == 0 else W) * W) for k in range(D)) * 2 + 3 * W * env
+    two = 2 * (2 * hp["n_species"] + hp["n_bessel"]) * tb[0] + 3 * (tb[0] * tb[1] + tb[1] * tb[2]) + 3 * W * env
+    assert c["second_order"]["flops_per_edge"] == 4 * (lat + two)
     assert all(v["bytes_per_edge"] > 0 for v in c.values())
 
 
