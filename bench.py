@@ -577,6 +577,10 @@ def bench_batch(a):
                                  steps=a.fp32_steps, what="eager batched steps")
         out["speedup_bf16_vs_fp32"] = value / out["fp32_plain"]["value"]
         del c32
+    if not a.no_cpu_baseline:
+        print("[bench] D: oracle CPU baseline and FP64 errors", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(hp, s, w)
+        out["error_vs_fp64"] = force_errors(hp, s, w, {"bf16": out_})
     print(json.dumps(out), flush=True)
     return 0
 
