@@ -504,6 +504,7 @@ struct TP2Args {
   float* gomega;         // stacked dJ/domega^L
   float* galpha;         // [N][n_paths][C] per-atom alpha-gradient shares
   float* badj;           // position gradient: stacked per-edge basis adjoints (+= dJ/dY), or null
+  int c0;                // first channel of this launch (the arrays hold CS channels)
 };
 
 // sum over the C channel lanes of one edge slot (lanes of a slot are
@@ -549,16 +550,16 @@ __device__ __forceinline__ void path2(const float* V, const float* Vd, const flo
   });
 }
 
-template <int LMAX, int NL, int L, int C>
-__device__ __forceinline__ void load_V2(const TP2Args& a, int64_t t, int n, const float* Y, const float* Yd, float* V,
+template <int LMAX, int NL, int L, int CS>
+__device__ __forceinline__ void load_V2(const TP2Args& a, int64_t t, int nc, const float* Y, const float* Yd, float* V,
                                         float* Vd) {
   constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
   const int64_t ts = a.stack + t;
   if constexpr (L == 1) {
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
-      const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
-      const float wd = a.omega1[(ts * (LMAX + 1) + l) * C + n];
+      const float w = a.omega1[(t * (LMAX + 1) + l) * CS + nc];
+      const float wd = a.omega1[(ts * (LMAX + 1) + l) * CS + nc];
 #pragma unroll
       for (int m = 0; m < 2 * l + 1; ++m) {
         V[l * l + m] = w * Y[l * l + m];
@@ -568,13 +569,15 @@ __device__ __forceinline__ void load_V2(const TP2Args& a, int64_t t, int n, cons
   } else {
 #pragma unroll
     for (int q = 0; q < LP.n_in_comps; ++q) {
-      V[q] = a.vin[(t * LP.n_in_comps + q) * C + n];
-      Vd[q] = a.vin[(ts * LP.n_in_comps + q) * C + n];
+      V[q] = a.vin[(t * LP.n_in_comps + q) * CS + nc];
+      Vd[q] = a.vin[(ts * LP.n_in_comps + q) * CS + nc];
     }
   }
 }
 
-template <int LMAX, int NL, int L, int C>
+// C: channels per launch (the lanes of an edge slot); CS: channels in the
+// arrays (128 channels run as two launches of 64)
+template <int LMAX, int NL, int L, int C, int CS>
 __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
   constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
@@ -584,6 +587,7 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
   __shared__ float gam[NLM * C];
   __shared__ float gamd[NLM * C];
   const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int nc = a.c0 + n;   // channel in the arrays
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
   for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
@@ -597,8 +601,8 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
-        const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
-        const float wd = a.omega[(ts * (LMAX + 1) + l) * C + n];
+        const float w = a.omega[(t * (LMAX + 1) + l) * CS + nc];
+        const float wd = a.omega[(ts * (LMAX + 1) + l) * CS + nc];
 #pragma unroll
         for (int m = 0; m < 2 * l + 1; ++m) {
           acc[l * l + m] += w * Y[l * l + m];
@@ -623,8 +627,8 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       gd *= a.inv_sqrt_nbar;
       gam[q * C + n] = g;
       gamd[q * C + n] = gd;
-      a.gamma[(i * NLM + q) * C + n] = g;
-      a.gammad[(i * NLM + q) * C + n] = gd;
+      a.gamma[(i * NLM + q) * CS + nc] = g;
+      a.gammad[(i * NLM + q) * CS + nc] = gd;
     }
     __syncthreads();
     float G[NLM], Gd[NLM];
@@ -635,7 +639,7 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
       float V[NCI], Vd[NCI];
-      load_V2<LMAX, NL, L, C>(a, t, n, Y, Yd, V, Vd);
+      load_V2<LMAX, NL, L, CS>(a, t, nc, Y, Yd, V, Vd);
       float out[NCO], outd[NCO];
 #pragma unroll
       for (int q = 0; q < NCO; ++q) { out[q] = 0.0f; outd[q] = 0.0f; }
@@ -646,11 +650,11 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
         float T[d3], Td[d3];
         path2<LMAX, NL, L, k>(V, Vd, G, Gd, T, Td);
         if constexpr (pt.s_idx >= 0) {
-          a.s[(t * LP.n0e + pt.s_idx) * C + n] = T[0];
-          a.s[(ts * LP.n0e + pt.s_idx) * C + n] = Td[0];
+          a.s[(t * LP.n0e + pt.s_idx) * CS + nc] = T[0];
+          a.s[(ts * LP.n0e + pt.s_idx) * CS + nc] = Td[0];
         }
         if constexpr (pt.out_off >= 0) {
-          const float al = a.alpha[k * C + n];
+          const float al = a.alpha[k * CS + nc];
 #pragma unroll
           for (int m3 = 0; m3 < d3; ++m3) {
             out[pt.out_off + m3] += al * T[m3];
@@ -661,8 +665,8 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
       if constexpr (LP.n_out_comps > 0) {
 #pragma unroll
         for (int q = 0; q < LP.n_out_comps; ++q) {
-          a.vout[(t * LP.n_out_comps + q) * C + n] = out[q];
-          a.vout[(ts * LP.n_out_comps + q) * C + n] = outd[q];
+          a.vout[(t * LP.n_out_comps + q) * CS + nc] = out[q];
+          a.vout[(ts * LP.n_out_comps + q) * CS + nc] = outd[q];
         }
       }
     }
@@ -670,7 +674,7 @@ __global__ void __launch_bounds__(256) k_tp2_fwd(TP2Args a) {
   }
 }
 
-template <int LMAX, int NL, int L, int C>
+template <int LMAX, int NL, int L, int C, int CS>
 __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
   constexpr LayerPlan LP = LayerCT2<LMAX, NL, L>::lp;
   constexpr int NLM = (LMAX + 1) * (LMAX + 1);
@@ -680,6 +684,7 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
   __shared__ float red[NS * 2 * NLM * C];
   __shared__ float gg[2 * NLM * C];   // dJ/dGamma and dJ/dGamma_dot
   const int n = threadIdx.x % C, slot = threadIdx.x / C;
+  const int nc = a.c0 + n;   // channel in the arrays
   const int64_t a0 = a.rr.chunk_rows[a.rr.chunk], a1 = a.rr.chunk_rows[a.rr.chunk + 1];
   const int64_t e0 = a.rr.row_ptr[a0];
   for (int64_t i = a0 + blockIdx.x; i < a1; i += gridDim.x) {
@@ -687,8 +692,8 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
     float G[NLM], Gd[NLM], GG[NLM], GGd[NLM], ga[NP];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) {
-      G[q] = a.gamma[(i * NLM + q) * C + n];
-      Gd[q] = a.gammad[(i * NLM + q) * C + n];
+      G[q] = a.gamma[(i * NLM + q) * CS + nc];
+      Gd[q] = a.gammad[(i * NLM + q) * CS + nc];
       GG[q] = 0.0f;
       GGd[q] = 0.0f;
     }
@@ -699,7 +704,7 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
       const float* Y = a.geo + t * GEO_STRIDE + GEO_Y;
       const float* Yd = a.geo2 + t * GEO_STRIDE + GEO_Y;
       float V[NCI], Vd[NCI], GV[NCI], GVd[NCI];
-      load_V2<LMAX, NL, L, C>(a, t, n, Y, Yd, V, Vd);
+      load_V2<LMAX, NL, L, CS>(a, t, nc, Y, Yd, V, Vd);
 #pragma unroll
       for (int q = 0; q < NCI; ++q) { GV[q] = 0.0f; GVd[q] = 0.0f; }
       static_for<0, NP>([&](auto K) {
@@ -711,18 +716,18 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
 #pragma unroll
         for (int m3 = 0; m3 < d3; ++m3) { GT[m3] = 0.0f; GTd[m3] = 0.0f; }
         if constexpr (pt.s_idx >= 0) {
-          GT[0] = a.gs[(t * LP.n0e + pt.s_idx) * C + n];
-          GTd[0] = a.gs[(ts * LP.n0e + pt.s_idx) * C + n];
+          GT[0] = a.gs[(t * LP.n0e + pt.s_idx) * CS + nc];
+          GTd[0] = a.gs[(ts * LP.n0e + pt.s_idx) * CS + nc];
         }
         if constexpr (pt.out_off >= 0) {
-          const float al = a.alpha[k * C + n];
+          const float al = a.alpha[k * CS + nc];
           float T[d3], Td[d3];
           path2<LMAX, NL, L, k>(V, Vd, G, Gd, T, Td);
           float gal = 0.0f;
 #pragma unroll
           for (int m3 = 0; m3 < d3; ++m3) {
-            const float gvo = a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * C + n];
-            const float gvod = a.gvout[(ts * LP.n_out_comps + pt.out_off + m3) * C + n];
+            const float gvo = a.gvout[(t * LP.n_out_comps + pt.out_off + m3) * CS + nc];
+            const float gvod = a.gvout[(ts * LP.n_out_comps + pt.out_off + m3) * CS + nc];
             gal += gvo * T[m3] + gvod * Td[m3];
             GT[m3] += al * gvo;
             GTd[m3] += al * gvod;
@@ -743,8 +748,8 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
       if constexpr (L > 1) {
 #pragma unroll
         for (int q = 0; q < NCI; ++q) {
-          a.gvin[(t * NCI + q) * C + n] = GV[q];
-          a.gvin[(ts * NCI + q) * C + n] = GVd[q];
+          a.gvin[(t * NCI + q) * CS + nc] = GV[q];
+          a.gvin[(ts * NCI + q) * CS + nc] = GVd[q];
         }
       } else {
         // V^0 = omega (x) Y, V^0_dot = omega_dot (x) Y + omega (x) Y_dot
@@ -756,16 +761,16 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
             go += GV[l * l + m] * Y[l * l + m] + GVd[l * l + m] * Yd[l * l + m];
             god += GVd[l * l + m] * Y[l * l + m];
           }
-          a.gomega[(t * (LMAX + 1) + l) * C + n] = go;
-          a.gomega[(ts * (LMAX + 1) + l) * C + n] = god;
+          a.gomega[(t * (LMAX + 1) + l) * CS + nc] = go;
+          a.gomega[(ts * (LMAX + 1) + l) * CS + nc] = god;
         }
         if (a.badj) {
           // dJ/dY += GV omega + GVd omega_dot;  dJ/dY_dot += GVd omega
           float yb[9] = {}, ydb[9] = {};
 #pragma unroll
           for (int l = 0; l <= LMAX; ++l) {
-            const float w = a.omega1[(t * (LMAX + 1) + l) * C + n];
-            const float wd = a.omega1[(ts * (LMAX + 1) + l) * C + n];
+            const float w = a.omega1[(t * (LMAX + 1) + l) * CS + nc];
+            const float wd = a.omega1[(ts * (LMAX + 1) + l) * CS + nc];
 #pragma unroll
             for (int m = 0; m < 2 * l + 1; ++m) {
               yb[l * l + m] = GV[l * l + m] * w + GVd[l * l + m] * wd;
@@ -800,7 +805,7 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
           float v = 0.0f;
 #pragma unroll
           for (int s = 0; s < NS; ++s) v += red[s * C + n];
-          a.galpha[(i * NP + k) * C + n] = v;
+          a.galpha[(i * NP + k) * CS + nc] = v;
         }
         __syncthreads();
       });
@@ -819,8 +824,8 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
           go += G * Y[l * l + m] + Gd * Yd[l * l + m];
           god += Gd * Y[l * l + m];
         }
-        float* p0 = a.gomega + (t * (LMAX + 1) + l) * C + n;
-        float* p1 = a.gomega + (ts * (LMAX + 1) + l) * C + n;
+        float* p0 = a.gomega + (t * (LMAX + 1) + l) * CS + nc;
+        float* p1 = a.gomega + (ts * (LMAX + 1) + l) * CS + nc;
         if constexpr (L == 1) { *p0 += go; *p1 += god; } else { *p0 = go; *p1 = god; }
       }
       if (a.badj) {
@@ -829,8 +834,8 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
         float yb[9] = {}, ydb[9] = {};
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
-          const float w = a.omega[(t * (LMAX + 1) + l) * C + n];
-          const float wd = a.omega[(ts * (LMAX + 1) + l) * C + n];
+          const float w = a.omega[(t * (LMAX + 1) + l) * CS + nc];
+          const float wd = a.omega[(ts * (LMAX + 1) + l) * CS + nc];
 #pragma unroll
           for (int m = 0; m < 2 * l + 1; ++m) {
             const float G = gg[(l * l + m) * C + n], Gd = gg[(NLM + l * l + m) * C + n];
@@ -847,17 +852,17 @@ __global__ void __launch_bounds__(256) k_tp2_bwd(TP2Args a) {
 
 typedef void (*tp2_kernel_t)(TP2Args);
 
-template <int LMAX, int NL, int C>
+template <int LMAX, int NL, int C, int CS>
 static tp2_kernel_t pick2(int L, bool bwd) {
-  if (L == 1) return bwd ? k_tp2_bwd<LMAX, NL, 1, C> : k_tp2_fwd<LMAX, NL, 1, C>;
-  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp2_bwd<LMAX, NL, 2, C> : k_tp2_fwd<LMAX, NL, 2, C>;
-  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp2_bwd<LMAX, NL, 3, C> : k_tp2_fwd<LMAX, NL, 3, C>;
+  if (L == 1) return bwd ? k_tp2_bwd<LMAX, NL, 1, C, CS> : k_tp2_fwd<LMAX, NL, 1, C, CS>;
+  if constexpr (NL >= 2) if (L == 2) return bwd ? k_tp2_bwd<LMAX, NL, 2, C, CS> : k_tp2_fwd<LMAX, NL, 2, C, CS>;
+  if constexpr (NL >= 3) if (L == 3) return bwd ? k_tp2_bwd<LMAX, NL, 3, C, CS> : k_tp2_fwd<LMAX, NL, 3, C, CS>;
   return nullptr;
 }
 
 static tp2_kernel_t pick_tp2(int lmax, int NL, int L, int C, bool bwd) {
 #define AFM_TP2(LM, NLV, CV) \
-  if (lmax == LM && NL == NLV && C == CV) return pick2<LM, NLV, CV>(L, bwd);
+  if (lmax == LM && NL == NLV && C == CV) return pick2<LM, NLV, (CV > 64 ? 64 : CV), CV>(L, bwd);
   AFM_TP2(1, 1, 8)
   AFM_TP2(2, 1, 8)
   AFM_TP2(2, 2, 8)
@@ -865,8 +870,22 @@ static tp2_kernel_t pick_tp2(int lmax, int NL, int L, int C, bool bwd) {
   AFM_TP2(2, 2, 32)
   AFM_TP2(2, 2, 64)
   AFM_TP2(2, 3, 64)
+  AFM_TP2(2, 2, 128)
 #undef AFM_TP2
   return nullptr;
+}
+
+// one workgroup per atom; 128 channels run as two consecutive launches over
+// the channel groups (the products are channelwise; the per-edge basis
+// adjoints add group after group in a fixed order)
+static int launch_tp2(tp2_kernel_t k, int C, TP2Args a, int64_t n_atoms, hipStream_t st) {
+  const int CK = C > 64 ? 64 : C;
+  for (int c0 = 0; c0 < C; c0 += CK) {
+    a.c0 = c0;
+    hipLaunchKernelGGL(k, dim3(grid_for(n_atoms, 1, 65536)), dim3(256), 0, st, a);
+  }
+  AFM_LAUNCH_CHECK();
+  return AFM_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -1129,8 +1148,8 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       ta.inv_sqrt_nbar = inb;
       tp2_kernel_t kf = pick_tp2(d.lmax, d.NL, layer, d.c, false);
       if (!kf) { set_error("second-order tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
-      hipLaunchKernelGGL(kf, dim3(grid_for(s.N, 1, 65536)), dim3(256), 0, st, ta);
-      AFM_LAUNCH_CHECK();
+      rc = launch_tp2(kf, d.c, ta, s.N, st);
+      if (rc) return rc;
       const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
       for (int k = 0; k < d.depth; ++k) {
         float* pre = ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k]);
@@ -1222,8 +1241,8 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       ta.badj = badj;
       tp2_kernel_t kb = pick_tp2(d.lmax, d.NL, layer, d.c, true);
       if (!kb) { set_error("second-order tensor-product kernel not built for this shape"); return AFM_E_UNSUPPORTED; }
-      hipLaunchKernelGGL(kb, dim3(grid_for(s.N, 1, 65536)), dim3(256), 0, st, ta);
-      AFM_LAUNCH_CHECK();
+      rc = launch_tp2(kb, d.c, ta, s.N, st);
+      if (rc) return rc;
       // alpha shares are per atom (chunks do not overlap): reduced after the last chunk
     }
     // two-body reverse

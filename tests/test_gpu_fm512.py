@@ -2,7 +2,8 @@
 two-body MLP [128, 256, 512], l_max 2, 2 layers) through the C ABI: FP32
 and BF16 energies, forces and virials against the FP64 oracle on a periodic
 lattice spanning several edge tiles with a ragged tail, non-unit path
-mixing and species scales.  (Tensor products run as two 64-channel groups;
+mixing and species scales, and the double backward (weight gradient and
+dJ/dr).  (Tensor products run as two 64-channel groups;
 the MLP chains give each wavefront two output-row pairs.)"""
 
 import sys
@@ -73,16 +74,49 @@ def test_fm512_tiles_and_tuner():
     assert r["tile"] == (64, 8) and r["ms"]["128x16"] == -1.0 and r["ms"]["128x8"] == -1.0
 
 
-def test_fm512_second_order_is_refused():
-    """The double backward has no 128-channel tensor-product kernels: the
-    call fails with an error instead of running anything else."""
+D2_TOL = {"fp32": 1e-5, "bf16": 1.5e-2}   # relative norm of the weight gradient
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fm512_second_order_matches_oracle(prec):
+    """The double backward of the 512-wide model (its 128-channel tensor
+    products as two 64-channel launches): the weight gradient of
+    J = sum gE E + sum gF . F + sum gW : W against the FP64 oracle's double
+    backward, and for the FP32 model also dJ/dr."""
     import torch
     import paper_2502_06073_amd as afm
+    from oracle import model as M
     hp, s, w, _ = _case()
-    model = afm.Model(hp, w, precision="fp32")
+    rng = np.random.default_rng(9)
+    gE = rng.standard_normal(s.n_struct)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    gW = rng.standard_normal((s.n_struct, 3, 3))
+    model = afm.Model(hp, w, precision=prec)
     calc = afm.Calculator(model, afm.DeviceSystem.from_synth(s), second_order=True)
     calc.build_neighbors()
-    calc.energy_forces()
-    gE = torch.ones(s.n_struct, dtype=torch.float64, device="cuda")
-    with pytest.raises(afm.AfmError, match="second-order tensor-product kernel not built"):
-        calc.forces_backward(gE, None)
+    dev = "cuda"
+    g, gp = calc.forces_backward(torch.tensor(gE, device=dev), torch.tensor(gF, device=dev),
+                                 torch.tensor(gW, device=dev), want_pos=True)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    gp = gp.cpu().numpy()
+    ref = M.vjp_weights(M.HParams.from_dict(hp), w, s, gE, gF, grad_virial=gW, want_pos=True)
+    gr = ref["grad_weights"]
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+    errp = np.linalg.norm(gp - ref["grad_pos"]) / np.linalg.norm(ref["grad_pos"])
+    lay = M.param_layout(M.HParams.from_dict(hp))
+    worst, off = [], 0
+    for b in lay:
+        seg = slice(off, off + b["size"])
+        den = max(np.linalg.norm(gr[seg]), 1e-30)
+        worst.append((round(float(np.linalg.norm(g[seg] - gr[seg]) / den), 7), b["name"]))
+        off += b["size"]
+    worst.sort(reverse=True)
+    _say(f"[fm512 d2 {prec}] weights rel {err:.2e}, cosine {cos:.7f}, grad_pos rel {errp:.2e}; "
+         f"worst blocks {worst[:3]}")
+    assert err < D2_TOL[prec] and cos > 0.999
+    if prec == "fp32":
+        assert worst[0][0] < 10 * D2_TOL[prec]
+        assert errp < D2_TOL[prec]
+    assert calc.status() == 0
