@@ -396,6 +396,8 @@ def bench_train(a):
     import synth
     import paper_2502_06073_amd as afm
     hp = synth.load_hparams("C")
+    if MODEL == "fm512":
+        hp.update(latent=512, channels=128, twobody=[128, 256, 512])
     s = synth.SYSTEMS["C"]()
     w = synth.draw_weights(afm.param_layout(hp), synth.WEIGHT_SEEDS["C"])
     e_hat, f_hat = synth.training_targets(s, 4003)
@@ -448,8 +450,10 @@ def bench_train(a):
                ms_per_step=dt / a.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="bf16+fp32", data="synthetic (seeded clusters, N(0,1) targets, N(0,1/fan_in) weights)",
                config=dict(workload=f"force-matching training step, {s.n_struct} clusters / {s.n_atoms} atoms, "
-                                    f"l_max 2, 2 layers, latent 128: BF16 energies+forces, double backward on BF16 "
-                                    f"MFMA (FP32 accumulation) for the weight gradient of the E+F loss",
+                                    f"l_max 2, 2 layers, latent {hp['latent']}, {hp['channels']} channels, "
+                                    f"two-body {hp['twobody']}: BF16 energies+forces, double backward on BF16 "
+                                    f"MFMA (FP32 accumulation) for the weight gradient of the E+F loss"
+                                    + ("; FM512 shape" if MODEL == "fm512" else ""),
                            n_atoms=s.n_atoms, n_struct=s.n_struct, n_edges=int(calc.nl.n_edges.item()),
                            n_params=calc.model_n_params(), parallelism="single GPU"),
                steps_per_s=a.steps / dt, loss=float(loss.item()),
@@ -609,7 +613,7 @@ def main(argv=None):
     ap.add_argument("--model", default="fm256", choices=["fm256", "fm512", "lmax3"],
                     help="config B: the FM256 shape (default), Table 1's 512-wide FM512 shape "
                          "(latent 512, 128 channels, two-body [128, 256, 512]) or the FM256 shape "
-                         "with l_max = 3")
+                         "with l_max = 3; config C: fm512 runs the training step at the FM512 widths")
     ap.add_argument("--no-per-structure", action="store_true",
                     help="config D: skip timing one call per structure (profiler runs of the batch alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -632,8 +636,9 @@ def main(argv=None):
         global FORCED_TILE
         FORCED_TILE = tuple(int(v) for v in a.edge_tile.lower().split("x"))
     if a.mixing != "path" or a.model != "fm256":
-        if a.config != "B":
-            print("--mixing dense and --model are measured on config B only", file=sys.stderr)
+        if a.config != "B" and not (a.config == "C" and a.model == "fm512" and a.mixing == "path"):
+            print("--mixing dense and --model are measured on config B only (and --model fm512 on "
+                  "config C's training step)", file=sys.stderr)
             return 2
         if a.mixing != "path" and a.model != "fm256":
             print("dense mixing is measured on the FM256 shape only", file=sys.stderr)

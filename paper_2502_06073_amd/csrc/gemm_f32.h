@@ -368,41 +368,60 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-  // next stage fetched into registers while the current one is multiplied;
-  // A: element (r, kk) = (idx / 32, idx % 32), consecutive lanes along k
-  constexpr int QB = BN / 8;   // W elements per thread per stage
-  float ra[8], rb[QB];
+  // next stage fetched into registers while the current one is multiplied.
+  // Every thread stages groups of 8 consecutive reduction values and writes
+  // each group to LDS as one 16-byte store.  A: row tid / 4, values
+  // 8 (tid % 4) ..; W (NT, [n][k]): rows tid / 4 + 64 h, likewise; W
+  // ([k][n]): column tid % BN, values 8 (tid / BN + (256 / BN) h) ..
+  constexpr int HB = BN / 64;   // W groups per thread per stage
+  float ra[8], rb[HB][8];
+  const int ar = tid >> 2, akq = (tid & 3) * 8;
   auto fetch = [&](int k0) {
+    {
+      const int m = m0 + ar, kb = k0 + akq;
+      const bool live = m < rows && row_live(m, M, stack);
+      if (live && kb + 8 <= K) {   // whole group in range: unguarded, mergeable loads
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx >> 5, kk = idx & 31;
-      const int m = m0 + r, k = k0 + kk;
-      ra[q] = (m < rows && row_live(m, M, stack) && k < K) ? al(m, k) : 0.0f;
+        for (int q = 0; q < 8; ++q) ra[q] = al(m, kb + q);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ra[q] = (live && kb + q < K) ? al(m, kb + q) : 0.0f;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int idx = tid + 256 * q;
-      int c, kb;
-      if (NT) { c = idx >> 5; kb = idx & 31; } else { kb = idx / BN; c = idx % BN; }
-      const int k2 = k0 + kb, n = n0 + c;
-      float v = 0.0f;
-      if (k2 < K && n < N) v = NT ? W[(int64_t)n * ldw + k2] : W[(int64_t)k2 * ldw + n];
-      rb[q] = v;
+    for (int h = 0; h < HB; ++h) {
+      int c, kq;
+      if (NT) { c = ar + 64 * h; kq = akq; } else { c = tid % BN; kq = 8 * (tid / BN + (256 / BN) * h); }
+      const int n = n0 + c, kb = k0 + kq;
+      if (NT && n < N && kb + 8 <= K) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rb[h][q] = W[(int64_t)n * ldw + kb + q];
+        continue;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float v = 0.0f;
+        if (kb + q < K && n < N) v = NT ? W[(int64_t)n * ldw + kb + q] : W[(int64_t)(kb + q) * ldw + n];
+        rb[h][q] = v;
+      }
     }
   };
   fetch(0);
   for (int k0 = 0; k0 < K; k0 += KS) {
+    {
+      bf16x8_t v;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q;
-      As[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)ra[q];
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)ra[q];
+      *reinterpret_cast<bf16x8_t*>(As + ar * kBfRow + akq) = v;
     }
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int idx = tid + 256 * q;
-      if (NT) Bs[(idx >> 5) * kBfRow + (idx & 31)] = (__bf16)rb[q];
-      else Bs[(idx % BN) * kBfRow + idx / BN] = (__bf16)rb[q];
+    for (int h = 0; h < HB; ++h) {
+      int c, kq;
+      if (NT) { c = ar + 64 * h; kq = akq; } else { c = tid % BN; kq = 8 * (tid / BN + (256 / BN) * h); }
+      bf16x8_t v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)rb[h][q];
+      *reinterpret_cast<bf16x8_t*>(Bs + c * kBfRow + kq) = v;
     }
     __syncthreads();
     if (k0 + KS < K) fetch(k0 + KS);
@@ -453,25 +472,28 @@ __global__ void __launch_bounds__(256) k_wgrad_bf16(RowRange rr, int stack, int 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  // every thread stages rows 8 (tid / 64) .. + 7 of column tid % 64 (lanes
+  // along the columns: coalesced loads) and writes each group of 8 to LDS
+  // as one 16-byte store
   float ra[8], rb[8];
+  const int sc = tid & 63, smq = 8 * (tid >> 6);
   auto fetch = [&](int m0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q;
-      const int mm = idx >> 6, c = idx & 63;
-      const int m = m0 + mm;
+      const int m = m0 + smq + q;
       const bool live = m < r1 && row_live(m, M, stack);
-      ra[q] = (live && n0 + c < N) ? A(m, n0 + c) : 0.0f;
-      rb[q] = (live && k0 + c < K) ? Bl(m, k0 + c) : 0.0f;
+      ra[q] = (live && n0 + sc < N) ? A(m, n0 + sc) : 0.0f;
+      rb[q] = (live && k0 + sc < K) ? Bl(m, k0 + sc) : 0.0f;
     }
   };
   if (r0 < r1) fetch(r0);
   for (int m0 = r0; m0 < r1; m0 += MS) {
+    {
+      bf16x8_t va, vb;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q;
-      As[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)ra[q];
-      Bs[(idx & 63) * kBfRow + (idx >> 6)] = (__bf16)rb[q];
+      for (int q = 0; q < 8; ++q) { va[q] = (__bf16)ra[q]; vb[q] = (__bf16)rb[q]; }
+      *reinterpret_cast<bf16x8_t*>(As + sc * kBfRow + smq) = va;
+      *reinterpret_cast<bf16x8_t*>(Bs + sc * kBfRow + smq) = vb;
     }
     __syncthreads();
     if (m0 + MS < r1) fetch(m0 + MS);
