@@ -292,8 +292,13 @@ int afm_energy_forces_noalloc(const afm_model* model, const afm_system* sys, con
  * weight layout, overwritten).  A NULL grad_e_struct, grad_forces or
  * grad_virial stands for zeros.  (A stress sigma_s = W_s / V_s enters as
  * gW_s = g_sigma_s / V_s.)  Needs a workspace planned
- * with with_second_order = 1; runs in FP32 (GEMMs on FP32 MFMA) with FP64
- * accumulation of the weight gradients (deterministic).  If grad_pos
+ * with with_second_order = 1.  FP32 models run its GEMMs on FP32 MFMA,
+ * BF16 models on BF16 MFMA (operands rounded to bf16, FP32 accumulation);
+ * the weight gradients accumulate in FP64 in a fixed order
+ * (deterministic).  Built for per-path mixing at (l_max, layers, channels)
+ * = (1, 1, 8), (2, 1, 8), (2, 2, 8 | 16 | 32 | 64 | 128) and (2, 3, 64);
+ * other models (l_max = 3, dense mixing over two or more layers) get
+ * AFM_E_UNSUPPORTED before anything is launched.  If grad_pos
  * (device, float64 [n_atoms, 3]) is not NULL it receives the position
  * gradient of the same objective, dJ/dr_i (overwritten; the cells are held
  * fixed): the reverse pass then also carries the adjoints of each edge's
