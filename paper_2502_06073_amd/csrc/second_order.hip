@@ -352,6 +352,22 @@ __global__ void k_atom2(RowRange rr, int stack, const float* __restrict__ eps2, 
   }
 }
 
+// h = silu(a) (rows t) and h_dot = silu'(a) a_dot (rows stack + t) of the
+// stacked pre-activations, written once for the GEMMs that read them (a
+// loader that applied them would do so once per output-column tile)
+__global__ void k_act2_fwd(RowRange rr, int stack, int F, const float* __restrict__ pre, float* __restrict__ out) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+    const float a = pre[t * F + f];
+    out[t * F + f] = silu_f(a);
+    out[(stack + t) * F + f] = d1silu(a) * pre[(stack + t) * F + f];
+  }
+}
+
 // adjoint through an activation: given dJ/dh (rows t) and dJ/dh_dot
 // (rows stack + t) with h = silu(a), h_dot = silu'(a) a_dot:
 //   a_bar = h_bar silu'(a) + hd_bar silu''(a) a_dot;  ad_bar = hd_bar silu'(a)
@@ -1104,6 +1120,15 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
   if (rc) return rc;
   RowRange rr{ws_ptr<int64_t>(ws, L.chunk_rows), nl.row_ptr, 0};
   const float inb = (float)(1.0 / sqrt(d.nbar));
+  // activated stacked rows of a pre-activation buffer into gh (free wherever
+  // a GEMM reads them; it holds at least w columns); false if F > w, where
+  // the GEMM applies the activation in its loader instead
+  auto act_into_gh = [&](const float* pre, int F) {
+    if (F > d.w) return false;
+    hipLaunchKernelGGL(k_act2_fwd, dim3(grid_for((int64_t)stack * F, 256, 65536)), dim3(256), 0, st, rr, stack, F,
+                       pre, gh);
+    return true;
+  };
   for (int chunk = 0; chunk < ws->n_chunks; ++chunk) {
     rr.chunk = chunk;
     if (badj) {
@@ -1121,10 +1146,16 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
                        (const float*)geo, (const float*)geo2, (const int32_t*)eidx, (const int32_t*)nl.col, s.species,
                        m->W.tb[0], d.S, d.nb, d.tb[0], (float)d.r_cut, d.p, tbp0);
     AFM_LAUNCH_CHECK();
-    for (int k = 1; k < d.ntb; ++k)
-      sgemm_so<true>(so_bf16, st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
-                  LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack},
-                  EpSt{ws_ptr<float>(ws, L.so_tb_pre[k]), d.tb[k]}, stack);
+    for (int k = 1; k < d.ntb; ++k) {
+      const float* pa = ws_ptr<float>(ws, L.so_tb_pre[k - 1]);
+      const EpSt ep{ws_ptr<float>(ws, L.so_tb_pre[k]), d.tb[k]};
+      if (act_into_gh(pa, d.tb[k - 1]))
+        sgemm_so<true>(so_bf16, st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1], LdPlain{gh, d.tb[k - 1]},
+                       ep, stack);
+      else
+        sgemm_so<true>(so_bf16, st, rr, E2, d.tb[k - 1], d.tb[k], m->W.tb[k], d.tb[k - 1],
+                       LdAct{pa, d.tb[k - 1], stack}, ep, stack);
+    }
     float* x0 = ws_ptr<float>(ws, L.so_x[0]);
     hipLaunchKernelGGL(k_tb2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack, d.w,
                        (const float*)ws_ptr<float>(ws, L.so_tb_pre[d.ntb - 1]), (const float*)geo,
@@ -1156,9 +1187,11 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         if (k == 0)
           sgemm_so<true>(so_bf16, st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
                       EpSt{pre, d.w}, stack);
-        else
-          sgemm_so<true>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w,
-                      LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, EpSt{pre, d.w}, stack);
+        else {
+          act_into_gh(ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w);
+          sgemm_so<true>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{gh, d.w}, EpSt{pre, d.w},
+                         stack);
+        }
       }
       float* xn = ws_ptr<float>(ws, L.so_x[layer]);
       hipLaunchKernelGGL(k_lat2_out, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr, stack,
@@ -1205,8 +1238,8 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         snprintf(nm, sizeof nm, "layer%d.latent.%d", layer, k);
         const int64_t off = block_offset(m, nm);
         if (k > 0) {
-          rc = wgrad(so_bf16, st, rr, stack, d.w, d.w, LdPlain{ga, d.w},
-                     LdAct{ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w, stack}, partial, gacc, off);
+          act_into_gh(ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w);
+          rc = wgrad(so_bf16, st, rr, stack, d.w, d.w, LdPlain{ga, d.w}, LdPlain{gh, d.w}, partial, gacc, off);
           if (rc) return rc;
           sgemm_so<false>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{ga, d.w}, EpSt{gh, d.w}, stack);
           hipLaunchKernelGGL(k_act2_bwd, dim3(grid_for((int64_t)stack * d.w, 256, 65536)), dim3(256), 0, st, rr,
@@ -1263,8 +1296,13 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
         snprintf(nm, sizeof nm, "twobody.%d", k);
         const int64_t off = block_offset(m, nm);
         if (k > 0) {
-          rc = wgrad(so_bf16, st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
-                     LdAct{ws_ptr<float>(ws, L.so_tb_pre[k - 1]), d.tb[k - 1], stack}, partial, gacc, off);
+          const float* pa = ws_ptr<float>(ws, L.so_tb_pre[k - 1]);
+          if (act_into_gh(pa, d.tb[k - 1]))
+            rc = wgrad(so_bf16, st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]}, LdPlain{gh, d.tb[k - 1]},
+                       partial, gacc, off);
+          else
+            rc = wgrad(so_bf16, st, rr, stack, d.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
+                       LdAct{pa, d.tb[k - 1], stack}, partial, gacc, off);
           if (rc) return rc;
           sgemm_so<false>(so_bf16, st, rr, E2, d.tb[k], d.tb[k - 1], m->W.tb[k], d.tb[k - 1], LdPlain{ga, d.tb[k]},
                        EpSt{gh, d.tb[k - 1]}, stack);
