@@ -382,9 +382,8 @@ __global__ void __launch_bounds__(256) k_sgemm_bf16(RowRange rr, int K, int N, c
     {
       const int m = m0 + ar, kb = k0 + akq;
       const bool live = m < rows && row_live(m, M, stack);
-      if (live && kb + 8 <= K) {   // whole group in range: unguarded, mergeable loads
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ra[q] = al(m, kb + q);
+      if (live && kb + 8 <= K) {   // whole group in range: the loader's unguarded 8-value load
+        al.load8(m, kb, ra);
       } else {
 #pragma unroll
         for (int q = 0; q < 8; ++q) ra[q] = (live && kb + q < K) ? al(m, kb + q) : 0.0f;

@@ -914,15 +914,40 @@ struct LdAct {   // primal rows: silu(a); tangent rows: silu'(a) a_dot
     const float a = pre[(int64_t)(m - stack) * ld + k];
     return d1silu(a) * pre[(int64_t)m * ld + k];
   }
+  __device__ void load8(int m, int k, float* v) const {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (*this)(m, k + q);
+  }
 };
 struct LdPlain {
   const float* x; int ld;
   __device__ float operator()(int m, int k) const { return x[(int64_t)m * ld + k]; }
+  __device__ void load8(int m, int k, float* v) const {
+    const float* p = x + (int64_t)m * ld + k;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = p[q];
+  }
 };
 struct LdCat {
   const float* x; int w; const float* s; int ls;
   __device__ float operator()(int m, int k) const {
     return k < w ? x[(int64_t)m * w + k] : s[(int64_t)m * ls + (k - w)];
+  }
+  // values k .. k + 7 (all in range): one branch per group when the group
+  // lies in one part
+  __device__ void load8(int m, int k, float* v) const {
+    if (k + 8 <= w) {
+      const float* p = x + (int64_t)m * w + k;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[q];
+    } else if (k >= w) {
+      const float* p = s + (int64_t)m * ls + (k - w);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (*this)(m, k + q);
+    }
   }
 };
 struct LdCoef {
