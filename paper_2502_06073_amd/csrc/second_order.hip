@@ -368,6 +368,25 @@ __global__ void k_act2_fwd(RowRange rr, int stack, int F, const float* __restric
   }
 }
 
+// the concatenated first-GEMM input [x | s] of the stacked rows, written
+// once for the GEMM that reads it
+__global__ void k_cat2(RowRange rr, int stack, const float* __restrict__ x, int w, const float* __restrict__ sv, int ls,
+                       float* __restrict__ out) {
+  int64_t e0, e1;
+  rr.get(e0, e1);
+  const int64_t M = e1 - e0;
+  const int F = w + ls;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < M * F; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / F;
+    const int f = (int)(q % F);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r = t + h * (int64_t)stack;
+      out[r * F + f] = f < w ? x[r * w + f] : sv[r * ls + (f - w)];
+    }
+  }
+}
+
 // adjoint through an activation: given dJ/dh (rows t) and dJ/dh_dot
 // (rows stack + t) with h = silu(a), h_dot = silu'(a) a_dot:
 //   a_bar = h_bar silu'(a) + hd_bar silu''(a) a_dot;  ad_bar = hd_bar silu'(a)
@@ -1209,9 +1228,13 @@ int run_second_order(const afm_model* m, const SysDev& s, const NlDev& nl, const
       const float* xp = ws_ptr<float>(ws, L.so_x[layer - 1]);
       for (int k = 0; k < d.depth; ++k) {
         float* pre = ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k]);
-        if (k == 0)
-          sgemm_so<true>(so_bf16, st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdCat{xp, d.w, ta.s, ls},
-                      EpSt{pre, d.w}, stack);
+        if (k == 0) {
+          // [x | s] into gh (it holds w + max n0e c columns), then a plain GEMM
+          hipLaunchKernelGGL(k_cat2, dim3(grid_for((int64_t)stack * (d.w + ls), 256, 65536)), dim3(256), 0, st, rr,
+                             stack, xp, d.w, (const float*)ta.s, ls, gh);
+          sgemm_so<true>(so_bf16, st, rr, E2, d.w + ls, d.w, m->W.lat[layer - 1][0], d.w + ls, LdPlain{gh, d.w + ls},
+                         EpSt{pre, d.w}, stack);
+        }
         else {
           act_into_gh(ws_ptr<float>(ws, L.so_lat_pre[layer - 1][k - 1]), d.w);
           sgemm_so<true>(so_bf16, st, rr, E2, d.w, d.w, m->W.lat[layer - 1][k], d.w, LdPlain{gh, d.w}, EpSt{pre, d.w},
