@@ -343,7 +343,8 @@ __device__ __forceinline__ bf16x8_t lds_row8(const __bf16* T, int r, int g) {
 // output is the same for both widths.  (The weight-gradient kernel below
 // keeps 64 x 64 tiles and 32-row stages: 128-wide tiles, which halve its
 // workgroups, and 64-row stages, which double its registers, both measured
-// 7-11 % slower on the training step.  64-value stages here, which halve
+// 7-11 % slower on the training step; with 16-byte LDS staging, 64-row
+// stages (78 registers, 5 waves per SIMD instead of 8) measured the same.  64-value stages here, which halve
 // the barriers per product, need 140 registers instead of 74 and measured
 // 8 % slower.)
 template <bool NT, int BN, class AL, class EP>
